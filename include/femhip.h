@@ -1,0 +1,192 @@
+/*
+ * femhip.h -- C interface of the MI355X (gfx950) library for linear (P1) finite
+ * element assembly of the Poisson problem, its solve and its adjoint gradient.
+ *
+ * The method is the one of L. Chen, "Programming of Finite Element Methods in
+ * MATLAB": mesh arrays node/elem/bdFlag (Section 1), a sparse matrix built from
+ * element contributions whose duplicate (i, j) entries are added (Sections 2.2 and
+ * 3.1), a load vector by quadrature (Section 3.2), Dirichlet and Neumann boundary
+ * conditions (Section 3.3) and a solve on the free nodes (equation (directsolve)).
+ * The problem solved is -div(kappa grad u) = f with kappa constant on each element;
+ * kappa = 1 gives the paper's problem (PoissonEq).
+ *
+ * Conventions shared by every entry point
+ *  - Arrays marked "device" live in GPU memory and are owned by the caller; the
+ *    library never allocates or frees device memory.  Host pointers are marked.
+ *  - Indices are 0-based int32.  Sizes are int64 but must fit the int32 index
+ *    space: n_node, n_elem*(dim+1), and nnz below 2^31 (else FE_EOVERFLOW).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Work
+ *    is enqueued on it and returns before it finishes, except where a call is
+ *    documented as synchronizing.
+ *  - Every function returns an fe_status; outputs are unspecified on error.  A
+ *    problem found by a kernel (bad element, bad kappa) is recorded in the plan and
+ *    reported by fe_plan_status(), which synchronizes.
+ *  - A plan must not be used by two streams at the same time.
+ */
+#ifndef FEMHIP_H
+#define FEMHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fe_status {
+    FE_OK = 0,
+    FE_EINVAL = -1,        /* bad argument: NULL pointer, bad size, index out of range, kappa <= 0 */
+    FE_EMESH = -2,         /* element with non-positive or non-finite measure, repeated vertex */
+    FE_EUNSUPPORTED = -3,  /* dim not 2 or 3, boundary type 3 (Robin) */
+    FE_EOVERFLOW = -4,     /* a count exceeds the int32 index space */
+    FE_ESIZE = -5,         /* workspace smaller than the size query returned */
+    FE_EHIP = -6,          /* a HIP runtime call failed */
+    FE_ENOCONV = -7,       /* the iteration limit was reached before the tolerance */
+    FE_ELIMIT = -8         /* a vertex has more than 64 neighbours or 1024 incident elements */
+} fe_status;
+
+/* Boundary side types (Section 1.2).  Side a of an element is opposite local vertex a. */
+enum { FE_BD_INTERIOR = 0, FE_BD_DIRICHLET = 1, FE_BD_NEUMANN = 2, FE_BD_ROBIN = 3 };
+
+/* A simplicial mesh (Section 1.1), structure-of-arrays (MATLAB's column-major
+ * node(N,d) and elem(NT,d+1)).  Every element must be positively oriented:
+ * det[x_2 - x_1, ..., x_{d+1} - x_1] > 0 (counter-clockwise triangles, right-hand
+ * rule for tetrahedra). */
+typedef struct fe_mesh {
+    int32_t dim;            /* 2 (triangles) or 3 (tetrahedra) */
+    int64_t n_node;         /* N */
+    int64_t n_elem;         /* NT */
+    const double *node;     /* device, dim*N:      node[c*N + k] = coordinate c of vertex k */
+    const int32_t *elem;    /* device, (dim+1)*NT: elem[a*NT + t] = vertex a of element t */
+    const int8_t *bdflag;   /* device, (dim+1)*NT: type of side a of t (0, 1, 2); NULL = all 0 */
+} fe_mesh;
+
+/* Data functions: source f, Dirichlet value g_D, Neumann flux g_N = kappa du/dn. */
+enum {
+    FE_FN_ZERO = 0,          /* 0 */
+    FE_FN_CONST = 1,         /* c0 */
+    FE_FN_LINEAR = 2,        /* c0 + c1 x + c2 y (+ c3 z) */
+    FE_FN_SINPROD = 3,       /* c0 * prod_c sin(pi x_c) */
+    FE_FN_DUDN_SINPROD = 4,  /* c0 * grad(prod_c sin(pi x_c)) . n, n the outward unit normal (g_N only) */
+    FE_FN_NODAL = 5          /* piecewise-linear interpolant of nodal[0..N-1] (device array) */
+};
+typedef struct fe_fn {
+    int32_t kind;
+    double c[4];
+    const double *nodal;    /* device, N values; used by FE_FN_NODAL only */
+} fe_fn;
+
+typedef struct fe_plan fe_plan;   /* opaque, host-side; refers to the caller's workspace */
+
+typedef struct fe_plan_info {
+    int32_t dim;
+    int64_t n_node, n_elem;
+    int64_t nnz;            /* stored entries of A (all pairs of vertices sharing an element) */
+    int64_t n_inc;          /* (dim+1)*n_elem vertex-element incidences */
+    int32_t max_row;        /* longest row of A */
+    int32_t max_deg;        /* most elements around one vertex */
+    int64_t n_dirichlet;    /* Dirichlet nodes */
+} fe_plan_info;
+
+/* Library version string (host, static). */
+const char *fe_version(void);
+/* Human-readable name of a status code (host, static). */
+const char *fe_status_string(int status);
+
+/* ---------------------------------------------------------------------------
+ * Symbolic phase: everything that depends only on elem and bdflag.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace a plan for `mesh` needs (host arithmetic only; the
+ * node pointer is not read).  The workspace must stay allocated and untouched by
+ * the caller until fe_plan_destroy(). */
+int fe_plan_workspace_bytes(const fe_mesh *mesh, size_t *bytes);
+
+/* Build the plan for the topology of `mesh` (elem, bdflag; node is not read):
+ * vertex-to-element incidence lists in a fixed order, the row pattern of A and
+ * the Dirichlet node set (vertices of sides of type 1, Section 3.3).  The stored
+ * pattern of A is every pair of vertices that share an element (Section 3.1.2),
+ * including pairs whose sum of contributions is zero.  Synchronizes `stream` once
+ * and returns nnz in *nnz (host).  The plan keeps pointers to mesh->elem and
+ * mesh->bdflag, which must stay valid and unchanged while the plan lives.
+ * Errors: FE_EINVAL (NULL, sizes, vertex index out of range, bdflag code not in
+ * 0..3), FE_EUNSUPPORTED (dim, bdflag 3), FE_EMESH (repeated vertex in an
+ * element), FE_EOVERFLOW, FE_ESIZE, FE_ELIMIT, FE_EHIP. */
+int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe_plan **plan, int64_t *nnz,
+                   void *stream);
+
+/* Write the compressed-row pattern of A: rowptr (device, N+1, rowptr[0] = 0) and
+ * colind (device, nnz; columns strictly ascending within each row).  A is
+ * structurally symmetric, so these arrays are also its compressed-column pattern. */
+int fe_plan_pattern(fe_plan *plan, int32_t *rowptr, int32_t *colind, void *stream);
+
+/* Fill *info (host). */
+int fe_plan_get_info(const fe_plan *plan, fe_plan_info *info);
+
+/* Synchronize `stream` and return the first problem recorded by a kernel of this
+ * plan since the last call (FE_EMESH for an element of non-positive or non-finite
+ * measure, FE_EINVAL for kappa <= 0 or non-finite), then clear it. */
+int fe_plan_status(fe_plan *plan, void *stream);
+
+/* Release the host-side plan object (the workspace is the caller's). */
+int fe_plan_destroy(fe_plan *plan);
+
+/* ---------------------------------------------------------------------------
+ * Numeric phase (Sections 3.1.3, 3.2, 3.3).
+ * ------------------------------------------------------------------------- */
+
+/* Assemble, in the plan's pattern:
+ *   val[nnz]     A, a_ij = sum over elements t of kappa_t |t| grad(lambda_i).grad(lambda_j)
+ *                with grad(lambda_i) = n_i / (d! |t|) (equation (dlambda)),
+ *   b_load[N]    load plus Neumann terms: 2-D three edge-midpoint rule, 3-D symmetric
+ *                four-point rule of degree 2 (exact closed form for FE_FN_NODAL);
+ *                Neumann sides by the midpoint (2-D) / centroid (3-D) rule,
+ *   b[N]         lifted right-hand side: b_load - A u_D on free rows, g_D at Dirichlet rows,
+ *   val_bc[nnz]  A with Dirichlet rows and columns replaced by the identity, so that
+ *                val_bc u = b is the full-size form of A(free,free) u = b(free),
+ *   is_dirichlet[N]  1 at Dirichlet nodes, else 0.
+ * node: device coordinates (same layout as fe_mesh.node).  kappa: device, NT values
+ * > 0, or NULL for kappa = 1.  f, g_d, g_n: host structs, NULL = zero.  val and b are
+ * required; val_bc, b_load and is_dirichlet may be NULL.  Duplicates are added in
+ * ascending element order, so results are bitwise reproducible. */
+int fe_assemble(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                const fe_fn *g_d, const fe_fn *g_n, double *val, double *val_bc, double *b,
+                double *b_load, uint8_t *is_dirichlet, void *stream);
+
+/* y = A x for a CSR matrix (device arrays; n rows). */
+int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+            const double *x, double *y, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Solve (replaces the direct solve of equation (directsolve)).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace fe_solve needs for n unknowns. */
+int fe_solve_workspace_bytes(int64_t n, size_t *bytes);
+
+/* Jacobi-preconditioned conjugate gradients for the symmetric positive definite
+ * CSR matrix (rowptr, colind, val), typically val_bc from fe_assemble.  u (device,
+ * n) holds x0 on entry (with the Dirichlet values at Dirichlet rows) and the
+ * solution on return.  Stops when ||b - A u||_2 <= rtol ||b||_2 (recurrence
+ * residual) or after maxit iterations (FE_ENOCONV).  Synchronizes; *iters and
+ * *relres (host) receive the iteration count and the final recurrence ratio.
+ * Dot products use a fixed reduction order, so results are bitwise reproducible. */
+int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+             const double *b, double *u, double rtol, int32_t maxit, void *ws, size_t ws_bytes,
+             int32_t *iters, double *relres, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Adjoint gradient.
+ * ------------------------------------------------------------------------- */
+
+/* g[t] = -|t| grad(lam_h) . grad(u_h) on every element t (device arrays: u, lam of
+ * length N, g of length NT).  With A(free,free) lam(free) = dJ/du(free) and lam = 0
+ * at Dirichlet nodes this is dJ/dkappa_t, since dA/dkappa_t is the unit-coefficient
+ * local stiffness of t (Section 3.1). */
+int fe_grad(fe_plan *plan, const double *node, const double *u, const double *lam, double *g,
+            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEMHIP_H */

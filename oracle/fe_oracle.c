@@ -275,7 +275,8 @@ static void gather_coords(int dim, int64_t N, int64_t NT, const double *node, co
  *   b[N]        lifted right-hand side: free rows f + g_N terms - (A u_D), Dirichlet rows g_D
  *   b_load[N]   load plus Neumann terms before lifting
  *   is_d[N]     1 for Dirichlet nodes
- *   b_scale[N]  sum of |terms| entering b[i] (a size for rounding tolerances)
+ *   b_scale[N]  sum of |load and Neumann terms| entering b_load[i] (a size for
+ *               rounding tolerances)
  *   *nnz        number of stored entries
  */
 int oracle_assemble(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
@@ -429,18 +430,10 @@ int oracle_assemble(int dim, int64_t N, int64_t NT, const double *node, const in
                 uD[i] = fn_eval(gD, dim, x, 1, &one, &self, NULL);
             }
         for (int64_t i = 0; i < N; ++i) {
-            double s = 0.0, sa = 0.0;
-            for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-                s += val[q] * uD[colind[q]];
-                sa += fabs(val[q] * uD[colind[q]]);
-            }
-            if (is_d[i]) {
-                b[i] = uD[i];
-                b_scale[i] = fabs(uD[i]);
-            } else {
-                b[i] -= s;
-                b_scale[i] += sa;
-            }
+            double s = 0.0;
+            for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) s += val[q] * uD[colind[q]];
+            if (is_d[i]) b[i] = uD[i];
+            else b[i] -= s;
         }
         for (int64_t i = 0; i < N; ++i)
             for (int64_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {

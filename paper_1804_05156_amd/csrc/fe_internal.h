@@ -1,0 +1,204 @@
+// fe_internal.h -- internal declarations of the HIP library (gfx950 only).
+//
+// Device helpers, the plan object and its workspace layout, shared by the
+// library's .hip translation units.  Nothing here is part of the C interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "femhip.h"
+
+// ---------------------------------------------------------------------------
+// Error bits recorded by kernels in plan->status[ST_ERR].
+// ---------------------------------------------------------------------------
+enum : int32_t {
+    ERR_INDEX = 1,      // vertex index outside [0, N)
+    ERR_BDCODE = 2,     // bdflag not in 0..3
+    ERR_ROBIN = 4,      // bdflag 3
+    ERR_REPEAT = 8,     // an element lists a vertex twice
+    ERR_MEASURE = 16,   // element measure not positive / not finite
+    ERR_KAPPA = 32,     // kappa not positive / not finite
+    ERR_LIMIT = 64,     // a row exceeds the fixed per-row capacity
+    ERR_OVERFLOW = 128  // a prefix sum exceeds the int32 range
+};
+
+// Slots of the device status array.
+enum { ST_ERR = 0, ST_UNUSED = 1, ST_MAXROW = 2, ST_MAXDEG = 3, ST_NDIR = 4, ST_COUNT = 16 };
+
+// Fixed per-row capacities of the symbolic kernels.
+template <int NV> struct RowCaps;
+template <> struct RowCaps<3> { static constexpr int DEG = 32, COL = 32, BLOCK = 128; };
+template <> struct RowCaps<4> { static constexpr int DEG = 96, COL = 64, BLOCK = 64; };
+
+// Incidence metadata word (one per vertex-element incidence, in row order):
+//   bits 0-1                 local index a of the row's vertex in the element
+//   bits 2+8j .. 9+8j        offset within the row of the column of local vertex
+//                            fe_other<NV>(a, j), j = 0..NV-2
+//   bit  2+8(NV-1)+j         that vertex is a Dirichlet node
+//   bit  2+9(NV-1)+j         the side opposite that vertex is a Neumann side
+//                            (the sides opposite the other vertices are the sides
+//                            that contain vertex a)
+template <int NV> struct Meta {
+    static constexpr int OFF = 2;
+    static constexpr int DBIT = 2 + 8 * (NV - 1);
+    static constexpr int NBIT = 2 + 9 * (NV - 1);
+};
+
+// Local order used for the row of local vertex a: the element's vertices are
+// taken as (a, other(a,0), ..., other(a,NV-2)), an even permutation of the stored
+// order, so the element keeps its positive orientation.  2-D: cyclic rotation.
+// 3-D: (0,1,2,3), (1,2,0,3), (2,0,1,3), (3,0,2,1).
+template <int NV> __host__ __device__ __forceinline__ int fe_other(int a, int jj)
+{
+    if (NV == 3) return (a + 1 + jj) % 3;
+    // 2 bits per entry, entry (a, jj) at bit 2*(3a + jj)
+    constexpr uint32_t T = (1u << 0) | (2u << 2) | (3u << 4) |    // a = 0: 1 2 3
+                           (2u << 6) | (0u << 8) | (3u << 10) |   // a = 1: 2 0 3
+                           (0u << 12) | (1u << 14) | (3u << 16) | // a = 2: 0 1 3
+                           (0u << 18) | (2u << 20) | (1u << 22);  // a = 3: 0 2 1
+    return (int)((T >> (2 * (3 * a + jj))) & 3u);
+}
+
+// Row info word (one per row, in processing order): bits 0-7 row length,
+// bits 8-15 offset of the diagonal, bit 16 the row's vertex is a Dirichlet node.
+
+struct fe_plan {
+    int32_t dim, nv;
+    int64_t N, NT, ninc;
+    const int32_t *elem;
+    const int8_t *bdflag;
+    // device arrays inside the caller's workspace
+    int32_t *status;      // ST_COUNT ints
+    int64_t *totals;      // scan totals (4 slots)
+    int64_t *part;        // scan partials
+    int32_t *deg;         // N     incident elements per vertex (label order)
+    int32_t *owner;       // N     smallest incidence key t*nv+a of the vertex
+    uint8_t *isd;         // N     Dirichlet flag (label order)
+    int32_t *rank;        // ninc  arrival rank of each incidence in its vertex list
+    int32_t *owncnt;      // NT+1  vertices whose first incidence is in element t -> offsets
+    int32_t *pi;          // N     processing order -> vertex label
+    int32_t *piinv;       // N     vertex label -> processing position
+    int32_t *pincptr;     // N+1   incidence ranges in processing order
+    int32_t *pinc;        // ninc  incidence keys t*nv+a, ascending within a row
+    uint32_t *pmeta;      // ninc  incidence metadata (Meta<NV>)
+    int32_t *rowlen;      // N+1   row lengths (label order) -> row pointer
+    int32_t *prow_start;  // N     first entry of the row (processing order)
+    uint32_t *prow_info;  // N     row info word (processing order)
+    // host copies
+    int64_t nnz, nused, ndir;
+    int32_t max_row, max_deg;
+    int pattern_done;
+};
+
+// ---------------------------------------------------------------------------
+// Small device helpers.
+// ---------------------------------------------------------------------------
+#define FE_DEV __device__ __forceinline__
+
+struct DevFn {
+    int32_t kind;
+    double c0, c1, c2, c3;
+    const double *nodal;
+};
+
+static inline DevFn make_devfn(const fe_fn *f)
+{
+    DevFn d{};
+    if (!f) { d.kind = FE_FN_ZERO; return d; }
+    d.kind = f->kind;
+    d.c0 = f->c[0]; d.c1 = f->c[1]; d.c2 = f->c[2]; d.c3 = f->c[3];
+    d.nodal = f->nodal;
+    return d;
+}
+
+static inline bool devfn_valid(const fe_fn *f, bool allow_dudn)
+{
+    if (!f) return true;
+    if (f->kind < FE_FN_ZERO || f->kind > FE_FN_NODAL) return false;
+    if (f->kind == FE_FN_DUDN_SINPROD && !allow_dudn) return false;
+    if (f->kind == FE_FN_NODAL && !f->nodal) return false;
+    return true;
+}
+
+// Value of a point-evaluable data function (not NODAL, not DUDN) at x.
+template <int DIM> FE_DEV double fn_point(const DevFn &f, const double *x)
+{
+    switch (f.kind) {
+    case FE_FN_CONST: return f.c0;
+    case FE_FN_LINEAR: {
+        double v = f.c0 + f.c1 * x[0] + f.c2 * x[1];
+        if (DIM == 3) v += f.c3 * x[2];
+        return v;
+    }
+    case FE_FN_SINPROD: {
+        double v = f.c0 * sinpi(x[0]) * sinpi(x[1]);
+        if (DIM == 3) v *= sinpi(x[2]);
+        return v;
+    }
+    default: return 0.0;
+    }
+}
+
+// c0 * grad(prod sin(pi x_c)) . nrm
+template <int DIM> FE_DEV double fn_dudn(const DevFn &f, const double *x, const double *nrm)
+{
+    double s[DIM], c[DIM];
+    for (int k = 0; k < DIM; ++k) { s[k] = sinpi(x[k]); c[k] = cospi(x[k]); }
+    const double pi = 3.14159265358979323846;
+    double acc = 0.0;
+    for (int k = 0; k < DIM; ++k) {
+        double g = pi * c[k];
+        for (int e = 0; e < DIM; ++e)
+            if (e != k) g *= s[e];
+        acc += g * nrm[k];
+    }
+    return f.c0 * acc;
+}
+
+// Deterministic block-wide sum (fixed combination order) of one double per thread.
+// `lds` needs BLOCK/64 doubles.  Every thread of the block must call it.
+template <int BLOCK> FE_DEV double block_sum(double v, double *lds)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < BLOCK / 64; ++w) s += lds[w];
+    __syncthreads();
+    return s;   // valid in thread 0
+}
+
+// ---------------------------------------------------------------------------
+// Host helpers.
+// ---------------------------------------------------------------------------
+#define FE_HIP_CHECK(expr)                                  \
+    do {                                                    \
+        hipError_t e_ = (expr);                             \
+        if (e_ != hipSuccess) return FE_EHIP;               \
+    } while (0)
+
+static inline int fe_launch_check()
+{
+    return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
+}
+
+static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Exclusive prefix sum of in[0..n) into out[0..n] (out[n] = total, in may equal out).
+// The 64-bit total is also stored at *total_dev; ERR_OVERFLOW is set in *status if
+// it does not fit int32.  `part` needs fe_scan_part_elems(n) int64 entries.
+int64_t fe_scan_part_elems(int64_t n);
+int fe_scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int64_t *total_dev, int64_t *part,
+                      int32_t *status, hipStream_t s);
+
+// Fill helpers (kernels, so they are safe to record in a graph).
+int fe_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+int fe_fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
+int fe_fill_f64(double *p, int64_t n, double v, hipStream_t s);
+
+int fe_status_from_bits(int32_t bits);

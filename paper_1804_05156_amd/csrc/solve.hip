@@ -1,0 +1,284 @@
+// solve.hip -- CSR SpMV and Jacobi-preconditioned conjugate gradients (FP64).
+//
+// Stands in for the direct solve A(free,free) \ b(free) of equation (directsolve):
+// with the Dirichlet rows and columns of A replaced by the identity and b = g_D
+// there, A_bc u = b is the same system at full size and is symmetric positive
+// definite, so CG applies.
+//
+// One CG iteration is two kernels:
+//   K_A: p = z + beta p_old (row i), q = A p computed as A (z + beta p_old) on the
+//        fly (so no grid-wide barrier is needed between the two), partial p.q
+//   K_B: x += alpha p, r -= alpha q, z = r / diag(A), partials r.z and r.r
+// Each block writes its partial sums; the last block to finish (integer ticket)
+// adds all partials in index order and derives alpha, or beta and the stopping
+// test, so every reduction has a fixed order and results are bitwise repeatable.
+// Scalars live in device memory; the host launches iterations in chunks and reads
+// the "done" flag once per chunk, kernels after convergence return at once.
+#include "fe_internal.h"
+
+namespace {
+
+constexpr int SB = 256;   // threads per block, one row per thread
+
+enum { S_RZ = 0, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_PQ, S_NSCAL = 8 };
+enum { F_DONE = 0, F_ITER, F_TICKET, F_BAD, F_NFLAG = 8 };
+
+struct SolveWs {
+    double *r, *z, *p0, *p1, *q, *dinv;
+    double *part;      // 3 * nblocks
+    double *scal;      // S_NSCAL
+    int32_t *flag;     // F_NFLAG
+};
+
+size_t ws_layout(int64_t n, SolveWs *w, char *base)
+{
+    const int64_t nb = cdiv(n > 0 ? n : 1, SB);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += align256(bytes);
+        return base ? base + at : nullptr;
+    };
+    char *r = take(sizeof(double) * n), *z = take(sizeof(double) * n), *p0 = take(sizeof(double) * n),
+         *p1 = take(sizeof(double) * n), *q = take(sizeof(double) * n), *d = take(sizeof(double) * n),
+         *part = take(sizeof(double) * 3 * nb), *scal = take(sizeof(double) * S_NSCAL),
+         *flag = take(sizeof(int32_t) * F_NFLAG);
+    if (w) {
+        w->r = (double *)r; w->z = (double *)z; w->p0 = (double *)p0; w->p1 = (double *)p1;
+        w->q = (double *)q; w->dinv = (double *)d; w->part = (double *)part; w->scal = (double *)scal;
+        w->flag = (int32_t *)flag;
+    }
+    return o;
+}
+
+__global__ __launch_bounds__(SB) void k_spmv(int32_t n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ colind, const double *__restrict__ val,
+                                             const double *__restrict__ x, double *__restrict__ y)
+{
+    const int32_t i = blockIdx.x * SB + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) s += val[q] * x[colind[q]];
+    y[i] = s;
+}
+
+// Last-block reduction: returns true in every thread of the block that arrived
+// last; that block then sees all partials written before the ticket.
+FE_DEV bool last_block(int32_t *ticket)
+{
+    __shared__ int is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t prev = atomicAdd(ticket, 1);
+        is_last = (prev == (int32_t)gridDim.x - 1);
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last != 0;
+}
+
+// Sum part[k*stride] for k in [0, nb) in a fixed order (block-strided then tree).
+FE_DEV double sum_partials(const double *part, int32_t nb, double *lds)
+{
+    double v = 0.0;
+    for (int32_t k = threadIdx.x; k < nb; k += SB) v += part[k];
+    return block_sum<SB>(v, lds);
+}
+
+// diag(A)^-1, r = b - A x, z = r * dinv, p_old = 0; partials r.z, r.r, b.b.
+__global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ colind, const double *__restrict__ val,
+                                                const double *__restrict__ b, const double *__restrict__ x,
+                                                double *r, double *z, double *p0, double *dinv, double *part,
+                                                double *scal, int32_t *flag, double rtol)
+{
+    __shared__ double lds[SB / 64];
+    const int32_t i = blockIdx.x * SB + threadIdx.x;
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    if (i < n) {
+        double s = 0.0, d = 0.0;
+        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+            const int32_t c = colind[q];
+            s += val[q] * x[c];
+            if (c == i) d = val[q];
+        }
+        if (!(d > 0.0)) atomicOr(flag + F_BAD, 1);
+        const double di = 1.0 / d;
+        const double ri = b[i] - s;
+        dinv[i] = di;
+        r[i] = ri;
+        z[i] = ri * di;
+        p0[i] = 0.0;
+        rz = ri * ri * di;
+        rr = ri * ri;
+        bb = b[i] * b[i];
+    }
+    const int32_t nb = gridDim.x;
+    double s0 = block_sum<SB>(rz, lds);
+    double s1 = block_sum<SB>(rr, lds);
+    double s2 = block_sum<SB>(bb, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0;
+        part[nb + blockIdx.x] = s1;
+        part[2 * nb + blockIdx.x] = s2;
+    }
+    if (!last_block(flag + F_TICKET)) return;
+    const double RZ = sum_partials(part, nb, lds);
+    const double RR = sum_partials(part + nb, nb, lds);
+    const double BB = sum_partials(part + 2 * nb, nb, lds);
+    if (threadIdx.x == 0) {
+        const double bn2 = BB > 0.0 ? BB : 1.0;
+        scal[S_RZ] = RZ;
+        scal[S_RR] = RR;
+        scal[S_BB] = bn2;
+        scal[S_TOL2] = rtol * rtol * bn2;
+        scal[S_BETA] = 0.0;
+        scal[S_ALPHA] = 0.0;
+        flag[F_ITER] = 0;
+        flag[F_DONE] = (RR <= rtol * rtol * bn2) ? 1 : 0;
+        flag[F_TICKET] = 0;
+    }
+}
+
+// p = z + beta p_old; q = A p (as A z + beta A p_old); partial p.q -> alpha.
+__global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ colind, const double *__restrict__ val,
+                                             const double *__restrict__ z, const double *__restrict__ pold,
+                                             double *__restrict__ pnew, double *__restrict__ qv, double *part,
+                                             double *scal, int32_t *flag)
+{
+    __shared__ double lds[SB / 64];
+    if (*(volatile int32_t *)(flag + F_DONE)) return;
+    const double beta = scal[S_BETA];
+    const int32_t i = blockIdx.x * SB + threadIdx.x;
+    double pq = 0.0;
+    if (i < n) {
+        double s = 0.0;
+        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
+            const int32_t c = colind[q];
+            s += val[q] * (z[c] + beta * pold[c]);
+        }
+        const double pi = z[i] + beta * pold[i];
+        pnew[i] = pi;
+        qv[i] = s;
+        pq = pi * s;
+    }
+    const double bs = block_sum<SB>(pq, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+    if (!last_block(flag + F_TICKET)) return;
+    const double PQ = sum_partials(part, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        scal[S_PQ] = PQ;
+        scal[S_ALPHA] = scal[S_RZ] / PQ;
+        flag[F_TICKET] = 0;
+    }
+}
+
+// x += alpha p; r -= alpha q; z = r dinv; partials r.z, r.r -> beta, stopping test.
+__global__ __launch_bounds__(SB) void k_cg_b(int32_t n, double *__restrict__ x, const double *__restrict__ p,
+                                             const double *__restrict__ qv, double *__restrict__ r,
+                                             double *__restrict__ z, const double *__restrict__ dinv, double *part,
+                                             double *scal, int32_t *flag)
+{
+    __shared__ double lds[SB / 64];
+    if (*(volatile int32_t *)(flag + F_DONE)) return;
+    const double alpha = scal[S_ALPHA];
+    const int32_t i = blockIdx.x * SB + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < n) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * qv[i];
+        const double zi = ri * dinv[i];
+        r[i] = ri;
+        z[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    const int32_t nb = gridDim.x;
+    const double s0 = block_sum<SB>(rz, lds);
+    const double s1 = block_sum<SB>(rr, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s0;
+        part[nb + blockIdx.x] = s1;
+    }
+    if (!last_block(flag + F_TICKET)) return;
+    const double RZ = sum_partials(part, nb, lds);
+    const double RR = sum_partials(part + nb, nb, lds);
+    if (threadIdx.x == 0) {
+        scal[S_BETA] = RZ / scal[S_RZ];
+        scal[S_RZ] = RZ;
+        scal[S_RR] = RR;
+        flag[F_ITER] += 1;
+        if (RR <= scal[S_TOL2]) flag[F_DONE] = 1;
+        flag[F_TICKET] = 0;
+    }
+}
+
+}  // namespace
+
+extern "C" int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, const double *x,
+                       double *y, void *stream)
+{
+    if (n < 0 || n >= INT32_MAX) return FE_EINVAL;
+    if (n == 0) return FE_OK;
+    if (!rowptr || !colind || !val || !x || !y) return FE_EINVAL;
+    hipLaunchKernelGGL(k_spmv, dim3((unsigned)cdiv(n, SB)), dim3(SB), 0, static_cast<hipStream_t>(stream),
+                       (int32_t)n, rowptr, colind, val, x, y);
+    return fe_launch_check();
+}
+
+extern "C" int fe_solve_workspace_bytes(int64_t n, size_t *bytes)
+{
+    if (n < 0 || n >= INT32_MAX || !bytes) return FE_EINVAL;
+    *bytes = ws_layout(n, nullptr, nullptr);
+    return FE_OK;
+}
+
+extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, const double *b,
+                        double *u, double rtol, int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters,
+                        double *relres, void *stream)
+{
+    if (n <= 0 || n >= INT32_MAX || maxit < 0 || !(rtol >= 0.0)) return FE_EINVAL;
+    if (!rowptr || !colind || !val || !b || !u || !ws || !iters || !relres) return FE_EINVAL;
+    if ((uintptr_t)ws & 255) return FE_EINVAL;
+    SolveWs W;
+    const size_t need = ws_layout(n, &W, static_cast<char *>(ws));
+    if (ws_bytes < need) return FE_ESIZE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t nn = (int32_t)n;
+    const unsigned nb = (unsigned)cdiv(n, SB);
+    int rc;
+    if ((rc = fe_fill_i32(W.flag, F_NFLAG, 0, s))) return rc;
+    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, b, (const double *)u, W.r, W.z,
+                       W.p0, W.dinv, W.part, W.scal, W.flag, rtol);
+    if ((rc = fe_launch_check())) return rc;
+    int32_t fl[F_NFLAG];
+    double sc[S_NSCAL];
+    int32_t launched = 0;
+    int parity = 0;
+    const int CHUNK = 32;
+    for (;;) {
+        FE_HIP_CHECK(hipMemcpyAsync(fl, W.flag, sizeof(fl), hipMemcpyDeviceToHost, s));
+        FE_HIP_CHECK(hipStreamSynchronize(s));
+        if (fl[F_BAD]) return FE_EINVAL;          // non-positive diagonal: not SPD
+        if (fl[F_DONE] || launched >= maxit) break;
+        const int32_t chunk = (maxit - launched < CHUNK) ? (maxit - launched) : CHUNK;
+        for (int32_t c = 0; c < chunk; ++c) {
+            double *pold = parity ? W.p1 : W.p0;
+            double *pnew = parity ? W.p0 : W.p1;
+            hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, (const double *)W.z,
+                               (const double *)pold, pnew, W.q, W.part, W.scal, W.flag);
+            hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(SB), 0, s, nn, u, (const double *)pnew, (const double *)W.q,
+                               W.r, W.z, (const double *)W.dinv, W.part, W.scal, W.flag);
+            parity ^= 1;
+        }
+        if ((rc = fe_launch_check())) return rc;
+        launched += chunk;
+    }
+    FE_HIP_CHECK(hipMemcpyAsync(sc, W.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
+    FE_HIP_CHECK(hipStreamSynchronize(s));
+    *iters = fl[F_ITER];
+    *relres = sqrt(sc[S_RR] / sc[S_BB]);
+    return fl[F_DONE] ? FE_OK : FE_ENOCONV;
+}

@@ -1,0 +1,260 @@
+"""GPU parity of assembly (A, A_bc, b, Dirichlet set) against the CPU oracle.
+
+Every test runs the HIP library through its C interface (ctypes binding) on the
+same seeded inputs as the oracle and compares element by element: pattern bit
+for bit, values within the scaled tolerance of gpu_helpers.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_05156_amd import meshgen
+from gpu_helpers import TOL, compare, data_scale, fns, host, log, run_gpu, to_dev, two_ring_submesh
+
+pytestmark = pytest.mark.gpu
+
+FE_FN_CONST, FE_FN_LINEAR, FE_FN_SINPROD, FE_FN_DUDN_SINPROD, FE_FN_NODAL = 1, 2, 3, 4, 5
+TWO_PI2 = 2 * math.pi ** 2
+
+
+def test_uniform_square_bitwise():
+    """33x33 uniform grid, kappa = 1, f = 2 pi^2 sin sin, g_D = 0 (dyadic geometry:
+    every stiffness value is exact, so A matches the oracle bit for bit)."""
+    log("case: uniform 33x33")
+    m = meshgen.workload("square33")
+    spec = [(FE_FN_SINPROD, (TWO_PI2,))]
+    (f, fo), _, _ = fns(*spec)
+    plan, asm = run_gpu(m, None, f)
+    g = host(plan, asm)
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, None, f=fo)
+    compare(g, ora, data=data_scale(m, spec))
+    assert np.array_equal(g["val"], ora.val)
+    assert np.array_equal(g["val_bc"], ora.val_bc)
+    n = 33
+    for j in (1, 16, 31):
+        for i in (1, 7, 31):
+            r = j * n + i
+            c = g["colind"][g["rowptr"][r]:g["rowptr"][r + 1]]
+            v = g["val"][g["rowptr"][r]:g["rowptr"][r + 1]]
+            want = {r - n - 1: 0.0, r - n: -1.0, r - 1: -1.0, r: 4.0, r + 1: -1.0, r + n: -1.0, r + n + 1: 0.0}
+            assert c.tolist() == sorted(want) and v.tolist() == [want[k] for k in c]
+
+
+def _random_sides(rng, count):
+    return tuple(int(x) for x in rng.choice([1, 2], size=count))
+
+
+@pytest.mark.parametrize("seed,n", [(1, 5), (2, 9), (3, 17), (4, 33), (5, 40)])
+def test_parity_2d_jittered_permuted(seed, n):
+    log(f"case: 2d jitter permute seed={seed} n={n}")
+    rng = np.random.default_rng(100 + seed)
+    sides = _random_sides(rng, 4)
+    if 1 not in sides:
+        sides = (1,) + sides[1:]
+    m = meshgen.square_mesh(n, jitter=0.2, permute=True, seed=seed, kappa="lognormal", sides=sides)
+    specs = [(FE_FN_SINPROD, (TWO_PI2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7)),
+             (FE_FN_DUDN_SINPROD, (1.3,)) if seed % 2 else (FE_FN_CONST, (0.9,))]
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    plan, asm = run_gpu(m, None, f, gd, gn)
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno)
+    worst = compare(host(plan, asm), ora, data=data_scale(m, specs))
+    log(f"  worst scaled value error {worst:.2e}")
+
+
+@pytest.mark.parametrize("seed,n", [(1, 3), (2, 4), (3, 6), (4, 9)])
+def test_parity_3d_jittered_permuted(seed, n):
+    log(f"case: 3d kuhn jitter permute seed={seed} n={n}")
+    rng = np.random.default_rng(200 + seed)
+    faces = tuple(int(x) for x in rng.choice([0, 1, 2], size=6))
+    if 1 not in faces:
+        faces = (1,) + faces[1:]
+    m = meshgen.kuhn_cube(n, jitter=0.15, permute=True, seed=seed, kappa="lognormal", faces=faces)
+    specs = [(FE_FN_SINPROD, (3 * math.pi ** 2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7, 0.4)),
+             (FE_FN_DUDN_SINPROD, (1.0,)) if seed % 2 else (FE_FN_LINEAR, (0.5, 0.2, 0.1, -0.3))]
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    plan, asm = run_gpu(m, None, f, gd, gn)
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno)
+    worst = compare(host(plan, asm), ora, data=data_scale(m, specs))
+    log(f"  worst scaled value error {worst:.2e}")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_parity_nodal_data(dim):
+    log(f"case: nodal data dim={dim}")
+    if dim == 2:
+        m = meshgen.square_mesh(12, jitter=0.2, permute=True, seed=9, kappa="lognormal", sides=(1, 2, 2, 1))
+    else:
+        m = meshgen.kuhn_cube(5, jitter=0.2, permute=True, seed=9, kappa="lognormal")
+    rng = np.random.default_rng(5)
+    fv, gv, nv = (rng.standard_normal(m.n_node) for _ in range(3))
+    specs = [(FE_FN_NODAL, (0,), fv), (FE_FN_NODAL, (0,), gv), (FE_FN_NODAL, (0,), nv)]
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    plan, asm = run_gpu(m, None, f, gd, gn)
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno)
+    compare(host(plan, asm), ora, data=data_scale(m, specs))
+
+
+def test_unused_vertex_single_elements():
+    log("case: unused vertex / single elements")
+    # one triangle plus an unused vertex: its row is empty, as sparse() gives
+    node = np.array([[0.0, 1.0, 0.0, 5.0], [0.0, 0.0, 1.0, 5.0]])
+    elem = np.array([[0], [1], [2]], np.int32)
+    bd = np.array([[1], [2], [0]], np.int8)
+    m = meshgen.Mesh(node, elem, bd, np.array([2.0]))
+    specs = [(FE_FN_CONST, (1.0,)), (FE_FN_LINEAR, (1.0, 2.0, 3.0)), (FE_FN_CONST, (0.5,))]
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    plan, asm = run_gpu(m, None, f, gd, gn)
+    ora = oracle.assemble(node, elem, bd, m.kappa, f=fo, gD=gdo, gN=gno)
+    g = host(plan, asm)
+    assert g["rowptr"].tolist() == [0, 3, 6, 9, 9]
+    compare(g, ora, data=data_scale(m, specs))
+    # one tetrahedron
+    node = np.array([[0.0, 1.0, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0], [0.0, 0.0, 0.0, 1.0]])
+    elem = np.array([[0], [1], [2], [3]], np.int32)
+    bd = np.array([[2], [0], [1], [2]], np.int8)
+    m = meshgen.Mesh(node, elem, bd, np.array([0.7]))
+    plan, asm = run_gpu(m, None, f, gd, gn)
+    compare(host(plan, asm), oracle.assemble(node, elem, bd, m.kappa, f=fo, gD=gdo, gN=gno),
+            data=data_scale(m, specs))
+
+
+def _fan(k):
+    """k triangles around the origin (a vertex with k neighbours), outer ring Dirichlet."""
+    ang = 2 * math.pi * np.arange(k) / k
+    node = np.vstack([np.r_[0.0, np.cos(ang)], np.r_[0.0, np.sin(ang)]])
+    elem = np.array([[0] * k, list(range(1, k + 1)), [1 + (j + 1) % k for j in range(k)]], np.int32)
+    bd = np.zeros((3, k), np.int8)
+    bd[0] = 1
+    return meshgen.Mesh(node, elem, bd, np.exp(np.sin(np.arange(k))))
+
+
+@pytest.mark.parametrize("k", [3, 15, 20, 31])
+def test_high_degree_vertex(k):
+    """Rows longer than 16 entries take the wider accumulator kernels."""
+    log(f"case: fan k={k}")
+    m = _fan(k)
+    specs = [(FE_FN_SINPROD, (1.0,)), (FE_FN_LINEAR, (1.0, 0.5, 0.25))]
+    (f, fo), (gd, gdo), _ = fns(*specs)
+    plan, asm = run_gpu(m, None, f, gd)
+    assert plan.info["max_row"] == k + 1
+    compare(host(plan, asm), oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo),
+            data=data_scale(m, specs))
+
+
+def test_row_capacity_limit_is_reported():
+    from paper_1804_05156_amd import femhip
+    log("case: fan beyond row capacity")
+    m = _fan(40)
+    node, elem, bd, _ = to_dev(m)
+    with pytest.raises(femhip.FemhipError) as e:
+        femhip.Plan(node, elem, bd)
+    assert e.value.code == femhip.FE_ELIMIT
+
+
+def test_error_paths():
+    from paper_1804_05156_amd import femhip
+    log("case: error paths")
+    m = meshgen.square_mesh(6, jitter=0.1, seed=3)
+    node, elem, bd, kap = to_dev(m)
+    bad = elem.clone()
+    bad[1, 3] = m.n_node                      # index out of range
+    with pytest.raises(femhip.FemhipError) as e:
+        femhip.Plan(node, bad, bd)
+    assert e.value.code == femhip.FE_EINVAL
+    bad = elem.clone()
+    bad[2, 5] = bad[0, 5]                     # repeated vertex
+    with pytest.raises(femhip.FemhipError) as e:
+        femhip.Plan(node, bad, bd)
+    assert e.value.code == femhip.FE_EMESH
+    b3 = bd.clone()
+    b3[1, 0] = 3                              # Robin side
+    with pytest.raises(femhip.FemhipError) as e:
+        femhip.Plan(node, elem, b3)
+    assert e.value.code == femhip.FE_EUNSUPPORTED
+    cw = elem.clone()
+    cw[[0, 1], 4] = cw[[1, 0], 4]             # clockwise element: found by the numeric kernel
+    plan = femhip.Plan(node, cw, bd)
+    plan.assemble(kap)
+    with pytest.raises(femhip.FemhipError) as e:
+        plan.check()
+    assert e.value.code == femhip.FE_EMESH
+    plan = femhip.Plan(node, elem, bd)
+    k2 = kap.clone()
+    k2[7] = -1.0
+    plan.assemble(k2)
+    with pytest.raises(femhip.FemhipError) as e:
+        plan.check()
+    assert e.value.code == femhip.FE_EINVAL
+    plan.assemble(kap)
+    plan.check()                              # status was cleared by the previous check
+
+
+def test_bitwise_repeatable():
+    log("case: determinism")
+    m = meshgen.square_mesh(65, jitter=0.2, permute=True, seed=21, kappa="lognormal")
+    (f, _), (gd, _), _ = fns((FE_FN_SINPROD, (TWO_PI2,)), (FE_FN_LINEAR, (1.0, 1.0, 1.0)))
+    dev = to_dev(m)
+    p1, a1 = run_gpu(m, None, f, gd, dev_arrays=dev)
+    p2, a2 = run_gpu(m, None, f, gd, dev_arrays=dev)
+    a3 = p1.assemble(dev[3], f, gd)
+    torch.cuda.synchronize()
+    for x, y in ((a1.val, a2.val), (a1.val, a3.val), (a1.b, a2.b), (a1.b, a3.b), (a1.val_bc, a2.val_bc)):
+        assert torch.equal(x, y)
+    assert torch.equal(p1.colind, p2.colind) and torch.equal(p1.rowptr, p2.rowptr)
+
+
+def _sampled_full_size(m, specs, nsample=64, seed=0):
+    (f, fo), (gd, gdo), (gn, gno) = fns(*(list(specs) + [None] * 3)[:3])
+    plan, asm = run_gpu(m, None, f, gd, gn)
+    log(f"  nnz={plan.nnz} max_row={plan.info['max_row']} max_deg={plan.info['max_deg']}")
+    g = host(plan, asm)
+    rng = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([rng.integers(0, m.n_node, nsample), [0, m.n_node - 1]]))
+    # boundary rows too: vertices of Dirichlet and Neumann sides
+    bdv = np.unique(m.elem[:, np.nonzero((m.bdflag > 0).any(axis=0))[0][:8]])
+    rows = np.unique(np.concatenate([rows, bdv]))
+    sub = two_ring_submesh(m, rows)
+    sm = meshgen.Mesh(m.node, m.elem[:, sub], m.bdflag[:, sub], m.kappa[sub])
+    ora = oracle.assemble(sm.node, sm.elem, sm.bdflag, sm.kappa, f=fo, gD=gdo, gN=gno)
+    worst = compare(g, ora, rows_subset=rows, data=data_scale(sm, specs))
+    log(f"  sampled {rows.size} rows, worst scaled error {worst:.2e}")
+    return plan, asm, g
+
+
+def test_full_size_jittered_2049_sampled():
+    """The 2049^2 permuted jittered mesh at full size: sampled rows against the
+    oracle on their two-ring submesh, plus properties that hold at any size."""
+    log("case: 2049^2 jittered permuted, full size")
+    m = meshgen.workload("jitter2049")
+    plan, asm, g = _sampled_full_size(m, [(FE_FN_SINPROD, (TWO_PI2,))])
+    N, NT = m.n_node, m.n_elem
+    assert plan.nnz == 3 * N + 2 * NT - 2
+    # zero row sums of A (gradients sum to zero) and symmetry of the pattern/values
+    rows = torch.repeat_interleave(torch.arange(N, device="cuda"), (plan.rowptr[1:] - plan.rowptr[:-1]).long())
+    val = asm.val[:plan.nnz]
+    col = plan.colind[:plan.nnz].long()
+    diag = torch.zeros(N, dtype=torch.float64, device="cuda")
+    on = col == rows
+    diag[rows[on]] = val[on]
+    rs = torch.zeros(N, dtype=torch.float64, device="cuda").index_add_(0, rows, val)
+    assert torch.all(rs.abs() <= 1e-13 * diag)
+    key = rows * N + col
+    tkey = col * N + rows
+    order = torch.argsort(tkey)
+    assert torch.equal(tkey[order], key)
+    scale = torch.sqrt(diag[rows] * diag[col])
+    assert torch.all((val[order] - val).abs() <= 1e-13 * scale)
+
+
+def test_full_size_kuhn129_sampled():
+    log("case: 129^3 Kuhn, full size")
+    m = meshgen.workload("kuhn129")
+    u = np.prod(np.sin(math.pi * m.node), axis=0)
+    specs = [(FE_FN_NODAL, (0,), 3 * math.pi ** 2 * u), None, (FE_FN_DUDN_SINPROD, (1.0,))]
+    plan, asm, g = _sampled_full_size(m, specs)
+    n = 129
+    E = 3 * n * n * (n - 1) + 3 * n * (n - 1) ** 2 + (n - 1) ** 3
+    assert plan.nnz == n ** 3 + 2 * E
