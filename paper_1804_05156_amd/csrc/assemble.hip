@@ -12,33 +12,131 @@
 // Section 2.2 done per row, in a fixed order, with no atomics and no triplet array.
 // The same walk adds the load term of Section 3.2, the Neumann side terms and the
 // Dirichlet lifting of Section 3.3, so A, A_bc and b come out of one kernel.
+//
+// Memory layout.  Rows run in the plan's processing order (an order that follows
+// the element order), so neighbouring threads touch neighbouring elements.  A
+// prepass copies the coordinates into that order (xyp) once per call; the plan
+// stores every element's vertices as processing positions (elemp).  All gathers of
+// the main kernel (elemp[t], kappa[t], xyp[p]) are then spatially coherent even
+// when the vertex labels are a random permutation; the only label-ordered
+// accesses left are the row's own outputs.
 #include "fe_internal.h"
 
 namespace {
 
 struct AsmArgs {
     int32_t N, NT;
-    const int32_t *elem;
-    const double *node;
     const double *kappa;
-    const int32_t *pi, *pincptr, *pinc, *prow_start;
-    const uint32_t *pmeta, *prow_info;
+    const int32_t *pi, *pincptr, *prowptr, *elemp;
+    const int2 *pincm;
+    const uint32_t *prow_info;
+    const double *xyp, *fp;
     DevFn f, gd, gn;
-    double *val, *val_bc, *b, *b_load;
-    uint8_t *isd_out;
+    double *valp;          // rows in processing order: row k at prowptr[k] + 2k, its values
+                           // followed by (b, b_load)
     int32_t *status;
 };
 
-template <int DIM> FE_DEV void load_xy(const double *node, int32_t N, int32_t v, double *x)
+// Coordinates (and nodal source values) in processing order: read in label order
+// (coalesced) and write each vertex's record to its processing position (one 16-
+// or 32-byte store per vertex, cheaper than gathering two 8-byte values).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_scatter_coords(int32_t N, const int32_t *__restrict__ piinv,
+                                                        const double *__restrict__ node, double *__restrict__ xyp,
+                                                        const double *__restrict__ fnodal, double *__restrict__ fp)
+{
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const int32_t k = piinv[i];
+    if (DIM == 2) {
+        reinterpret_cast<double2 *>(xyp)[k] = make_double2(node[i], node[(int64_t)N + i]);
+    } else {
+        double2 *o = reinterpret_cast<double2 *>(xyp) + 2 * (int64_t)k;
+        o[0] = make_double2(node[i], node[(int64_t)N + i]);
+        o[1] = make_double2(node[2 * (int64_t)N + i], 0.0);
+    }
+    if (fnodal) fp[k] = fnodal[i];
+}
+
+template <int DIM> FE_DEV void load_label_xy(const double *node, int32_t N, int32_t v, double *x)
 {
     for (int c = 0; c < DIM; ++c) x[c] = node[(int64_t)c * N + v];
 }
 
-// Value of g_D at vertex v with coordinates x.
+// Value of g_D at the vertex with label v and coordinates x.
 template <int DIM> FE_DEV double dirichlet_value(const DevFn &g, int32_t v, const double *x)
 {
     if (g.kind == FE_FN_NODAL) return g.nodal[v];
     return fn_point<DIM>(g, x);
+}
+
+FE_DEV int sel3(int4 q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : q.z); }
+FE_DEV int sel4(int4 q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
+
+// Write the accumulated row and its right-hand side entries, in processing order
+// (consecutive threads write consecutive rows, so the stores are contiguous).
+template <int BLOCK>
+FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, int len, bool rowd, double bsum,
+                      double lift, double gdi)
+{
+    double *row = A.valp + A.prowptr[k] + 2 * (int64_t)k;
+    for (int c = 0; c < len; ++c) row[c] = acc[c * BLOCK + tid];
+    row[len] = rowd ? gdi : bsum - lift;
+    row[len + 1] = bsum;
+}
+
+// Label-order outputs from the processing-order rows: one wavefront per 64
+// consecutive label rows, lanes writing consecutive entries of the rows' joint
+// output range (fully coalesced stores); each source row is read once, whole.
+// A_bc replaces Dirichlet rows by the identity row and zeroes Dirichlet columns
+// (the row record holds the row's info word and its Dirichlet-column mask).
+__global__ __launch_bounds__(256) void k_values_to_label(int32_t N, const int32_t *__restrict__ rowptr,
+                                                         const int4 *__restrict__ rowrec,
+                                                         const int32_t *__restrict__ piinv,
+                                                         const double *__restrict__ valp, double *val, double *val_bc,
+                                                         double *b, double *b_load, uint8_t *isd)
+{
+    __shared__ int32_t sdst[4][65];
+    __shared__ int4 srec[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t i0 = (blockIdx.x * 4 + w) * 64;
+    const int32_t i = i0 + lane;
+    sdst[w][lane] = rowptr[min(i, N)];
+    if (lane == 0) sdst[w][64] = rowptr[min(i0 + 64, N)];
+    int4 rec = make_int4(0, 0, 0, 0);
+    if (i < N) {
+        rec = rowrec[i];
+        rec.x += 2 * piinv[i];                         // start of the row in valp
+        const int len = rec.y & 0xff;
+        b[i] = valp[rec.x + len];
+        if (b_load) b_load[i] = valp[rec.x + len + 1];
+        if (isd) isd[i] = (uint8_t)((rec.y >> 16) & 1);
+    }
+    srec[w][lane] = rec;
+    __syncthreads();
+    const int32_t base = sdst[w][0];
+    const int32_t total = sdst[w][64] - base;
+    for (int32_t e = lane; e < total; e += 64) {
+        const int32_t pos = base + e;
+        int lo = 0, hi = 63;   // last row r with sdst[r] <= pos
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sdst[w][mid] <= pos) lo = mid;
+            else hi = mid - 1;
+        }
+        const int4 r = srec[w][lo];
+        const int c = pos - sdst[w][lo];
+        const double v = valp[r.x + c];
+        val[pos] = v;
+        if (val_bc) {
+            const uint32_t info = (uint32_t)r.y;
+            const uint64_t dm = (uint64_t)(uint32_t)r.z | ((uint64_t)(uint32_t)r.w << 32);
+            double vb = v;
+            if ((info >> 16) & 1u) vb = (c == (int)((info >> 8) & 0xffu)) ? 1.0 : 0.0;
+            else if ((dm >> c) & 1ull) vb = 0.0;
+            val_bc[pos] = vb;
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------- 2-D
@@ -47,118 +145,131 @@ template <int DIM> FE_DEV double dirichlet_value(const DevFn &g, int32_t v, cons
 // orientation, so with E0 = X2 - X1, E1 = X0 - X2, E2 = X1 - X0 (the edge vectors
 // opposite X0, X1, X2) the doubled area is E1 x E2 > 0 and K[0][c] =
 // kappa E0 . Ec / (2 * doubled area).
-template <int ROWCAP, int BLOCK>
+// Incidences are handled in batches of UNR whose loads are all issued before any
+// arithmetic, to overlap the three dependent gathers (incidence -> element ->
+// coordinates) across the batch.
+template <int ROWCAP, int BLOCK, int UNR>
 __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
 {
     __shared__ double acc[ROWCAP * BLOCK];
     const int tid = threadIdx.x;
     const int32_t k = blockIdx.x * BLOCK + tid;
     if (k >= A.N) return;
-    const int32_t i = A.pi[k];
     const int32_t s = A.pincptr[k], e = A.pincptr[k + 1];
-    const int32_t rs = A.prow_start[k];
     const uint32_t info = A.prow_info[k];
     const int len = info & 0xff, diag = (info >> 8) & 0xff;
     const bool rowd = (info >> 16) & 1;
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
-    double X0[2];
-    load_xy<2>(A.node, A.N, i, X0);
+    const double2 X0 = reinterpret_cast<const double2 *>(A.xyp)[k];
+    const double2 *xy = reinterpret_cast<const double2 *>(A.xyp);
+    const int4 *ep4 = reinterpret_cast<const int4 *>(A.elemp);
     double bsum = 0.0, lift = 0.0;
-    uint64_t dmask = 0;
     int32_t err = 0;
     const bool nodal_f = A.f.kind == FE_FN_NODAL;
-    for (int32_t p = s; p < e; ++p) {
-        const int32_t key = A.pinc[p];
-        const uint32_t meta = A.pmeta[p];
-        const int32_t t = key / 3;
-        const int a = key - 3 * t;
-        const int b1 = (a == 2) ? 0 : a + 1;
-        const int b2 = (a == 0) ? 2 : a - 1;
-        const int32_t v1 = A.elem[(int64_t)b1 * A.NT + t];
-        const int32_t v2 = A.elem[(int64_t)b2 * A.NT + t];
-        double X1[2], X2[2];
-        load_xy<2>(A.node, A.N, v1, X1);
-        load_xy<2>(A.node, A.N, v2, X2);
-        const double E0x = X2[0] - X1[0], E0y = X2[1] - X1[1];
-        const double E1x = X0[0] - X2[0], E1y = X0[1] - X2[1];
-        const double E2x = X1[0] - X0[0], E2y = X1[1] - X0[1];
-        const double area2 = E1x * E2y - E1y * E2x;        // 2|t|
-        const double kt = A.kappa ? A.kappa[t] : 1.0;
-        if (!(area2 > 0.0) || !isfinite(area2)) err |= ERR_MEASURE;
-        if (!(kt > 0.0) || !isfinite(kt)) err |= ERR_KAPPA;
-        const double sc = kt / (2.0 * area2);
-        const double k00 = sc * (E0x * E0x + E0y * E0y);
-        const double k01 = sc * (E0x * E1x + E0y * E1y);
-        const double k02 = sc * (E0x * E2x + E0y * E2y);
-        const int o1 = (meta >> Meta<3>::OFF) & 0xff;
-        const int o2 = (meta >> (Meta<3>::OFF + 8)) & 0xff;
-        acc[diag * BLOCK + tid] += k00;
-        acc[o1 * BLOCK + tid] += k01;
-        acc[o2 * BLOCK + tid] += k02;
-        // load: |t| (f(m1) + f(m2)) / 6, m1 = (X2+X0)/2, m2 = (X0+X1)/2 (Section 3.2)
-        if (A.f.kind != FE_FN_ZERO) {
-            double f1, f2;
-            if (nodal_f) {
-                const double fa = A.f.nodal[i], g1 = A.f.nodal[v1], g2 = A.f.nodal[v2];
-                f1 = 0.5 * (g2 + fa);
-                f2 = 0.5 * (fa + g1);
-            } else {
-                const double m1[2] = {0.5 * (X2[0] + X0[0]), 0.5 * (X2[1] + X0[1])};
-                const double m2[2] = {0.5 * (X0[0] + X1[0]), 0.5 * (X0[1] + X1[1])};
-                f1 = fn_point<2>(A.f, m1);
-                f2 = fn_point<2>(A.f, m2);
+    const double fi = nodal_f ? A.fp[k] : 0.0;
+    for (int32_t p0 = s; p0 < e; p0 += UNR) {
+        int2 km[UNR];
+        int4 ep[UNR];
+        double kt[UNR];
+        double2 X1[UNR], X2[UNR];
+        int p1[UNR], p2[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (p0 + u < e) km[u] = A.pincm[p0 + u];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (p0 + u < e) {
+                const int32_t t = km[u].x / 3;
+                ep[u] = ep4[t];
+                kt[u] = A.kappa ? A.kappa[t] : 1.0;
             }
-            bsum += area2 * (f1 + f2) / 12.0;
-        }
-        // Neumann sides through vertex a: the side opposite X1 (X2-X0) and opposite X2 (X0-X1)
-        const uint32_t nb = (meta >> Meta<3>::NBIT) & 3u;
-        if (nb) {
-            for (int jj = 0; jj < 2; ++jj) {
-                if (!((nb >> jj) & 1u)) continue;
-                const double *Xo = jj == 0 ? X2 : X1;              // other end of the side
-                const double ex = jj == 0 ? E1x : E2x, ey = jj == 0 ? E1y : E2y;
-                const double L = sqrt(ex * ex + ey * ey);
-                const double mid[2] = {0.5 * (X0[0] + Xo[0]), 0.5 * (X0[1] + Xo[1])};
-                double g;
-                if (A.gn.kind == FE_FN_DUDN_SINPROD) {
-                    // inward normal of the side = its edge vector rotated counter-clockwise
-                    const double nrm[2] = {ey / L, -ex / L};           // outward unit normal
-                    g = fn_dudn<2>(A.gn, mid, nrm);
-                } else if (A.gn.kind == FE_FN_NODAL) {
-                    const int32_t vo = jj == 0 ? v2 : v1;
-                    g = 0.5 * (A.gn.nodal[i] + A.gn.nodal[vo]);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+            if (p0 + u < e) {
+                const int32_t t = km[u].x / 3;
+                const int a = km[u].x - 3 * t;
+                p1[u] = sel3(ep[u], a == 2 ? 0 : a + 1);
+                p2[u] = sel3(ep[u], a == 0 ? 2 : a - 1);
+                X1[u] = xy[p1[u]];
+                X2[u] = xy[p2[u]];
+            }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (p0 + u >= e) break;
+            const uint32_t meta = (uint32_t)km[u].y;
+            const double E0x = X2[u].x - X1[u].x, E0y = X2[u].y - X1[u].y;
+            const double E1x = X0.x - X2[u].x, E1y = X0.y - X2[u].y;
+            const double E2x = X1[u].x - X0.x, E2y = X1[u].y - X0.y;
+            const double area2 = E1x * E2y - E1y * E2x;        // 2|t|
+            if (!(area2 > 0.0) || !isfinite(area2)) err |= ERR_MEASURE;
+            if (!(kt[u] > 0.0) || !isfinite(kt[u])) err |= ERR_KAPPA;
+            const double sc = kt[u] / (2.0 * area2);
+            const double k00 = sc * (E0x * E0x + E0y * E0y);
+            const double k01 = sc * (E0x * E1x + E0y * E1y);
+            const double k02 = sc * (E0x * E2x + E0y * E2y);
+            const int o1 = (meta >> Meta<3>::OFF) & 0xff;
+            const int o2 = (meta >> (Meta<3>::OFF + 8)) & 0xff;
+            acc[diag * BLOCK + tid] += k00;
+            acc[o1 * BLOCK + tid] += k01;
+            acc[o2 * BLOCK + tid] += k02;
+            // load: |t| (f(m1) + f(m2)) / 6, m1 = (X2+X0)/2, m2 = (X0+X1)/2 (Section 3.2)
+            if (A.f.kind != FE_FN_ZERO) {
+                double f1, f2;
+                if (nodal_f) {
+                    f1 = 0.5 * (A.fp[p2[u]] + fi);
+                    f2 = 0.5 * (fi + A.fp[p1[u]]);
                 } else {
-                    g = fn_point<2>(A.gn, mid);
+                    const double m1[2] = {0.5 * (X2[u].x + X0.x), 0.5 * (X2[u].y + X0.y)};
+                    const double m2[2] = {0.5 * (X0.x + X1[u].x), 0.5 * (X0.y + X1[u].y)};
+                    f1 = fn_point<2>(A.f, m1);
+                    f2 = fn_point<2>(A.f, m2);
                 }
-                bsum += L * g / 2.0;
+                bsum += area2 * (f1 + f2) / 12.0;
             }
-        }
-        // Dirichlet columns: record them and lift b by K[a][c] u_D(c)
-        const uint32_t db = (meta >> Meta<3>::DBIT) & 3u;
-        if (db) {
-            if (db & 1u) {
-                dmask |= 1ull << o1;
-                if (A.gd.kind != FE_FN_ZERO) lift += k01 * dirichlet_value<2>(A.gd, v1, X1);
+            // Neumann sides through the row's vertex: opposite X1 (X2-X0) and opposite X2 (X0-X1)
+            const uint32_t nb = (meta >> Meta<3>::NBIT) & 3u;
+            if (nb) {
+                for (int jj = 0; jj < 2; ++jj) {
+                    if (!((nb >> jj) & 1u)) continue;
+                    const double2 Xo = jj == 0 ? X2[u] : X1[u];         // other end of the side
+                    const double ex = jj == 0 ? E1x : E2x, ey = jj == 0 ? E1y : E2y;
+                    const double L = sqrt(ex * ex + ey * ey);
+                    const double mid[2] = {0.5 * (X0.x + Xo.x), 0.5 * (X0.y + Xo.y)};
+                    double g;
+                    if (A.gn.kind == FE_FN_DUDN_SINPROD) {
+                        // inward normal of the side = its edge vector rotated counter-clockwise
+                        const double nrm[2] = {ey / L, -ex / L};        // outward unit normal
+                        g = fn_dudn<2>(A.gn, mid, nrm);
+                    } else if (A.gn.kind == FE_FN_NODAL) {
+                        const int32_t vo = A.pi[jj == 0 ? p2[u] : p1[u]];
+                        g = 0.5 * (A.gn.nodal[A.pi[k]] + A.gn.nodal[vo]);
+                    } else {
+                        g = fn_point<2>(A.gn, mid);
+                    }
+                    bsum += L * g / 2.0;
+                }
             }
-            if (db & 2u) {
-                dmask |= 1ull << o2;
-                if (A.gd.kind != FE_FN_ZERO) lift += k02 * dirichlet_value<2>(A.gd, v2, X2);
+            // Dirichlet columns: lift b by K[0][c] u_D(c)
+            const uint32_t db = (meta >> Meta<3>::DBIT) & 3u;
+            if (db && A.gd.kind != FE_FN_ZERO) {
+                if (db & 1u) {
+                    const double x1[2] = {X1[u].x, X1[u].y};
+                    lift += k01 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[p1[u]] : 0, x1);
+                }
+                if (db & 2u) {
+                    const double x2[2] = {X2[u].x, X2[u].y};
+                    lift += k02 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[p2[u]] : 0, x2);
+                }
             }
         }
     }
     if (err) atomicOr(A.status + ST_ERR, err);
-    for (int c = 0; c < len; ++c) A.val[rs + c] = acc[c * BLOCK + tid];
-    if (A.val_bc) {
-        for (int c = 0; c < len; ++c) {
-            double v = acc[c * BLOCK + tid];
-            if (rowd) v = (c == diag) ? 1.0 : 0.0;
-            else if ((dmask >> c) & 1ull) v = 0.0;
-            A.val_bc[rs + c] = v;
-        }
+    double gdi = 0.0;
+    if (rowd) {
+        const double x0[2] = {X0.x, X0.y};
+        gdi = dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[k] : 0, x0);
     }
-    if (A.b_load) A.b_load[i] = bsum;
-    A.b[i] = rowd ? dirichlet_value<2>(A.gd, i, X0) : bsum - lift;
-    if (A.isd_out) A.isd_out[i] = rowd ? 1 : 0;
+    write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
 }
 
 // ----------------------------------------------------------------------------- 3-D
@@ -166,7 +277,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
 // which keeps the orientation.  Sides opposite Y0..Y3 follow the paper's face list
 // [1 3 2], [0 2 3], [0 3 1], [0 1 2]; n_f = (Y_F1 - Y_F0) x (Y_F2 - Y_F0) is the
 // inward normal of a positively oriented tetrahedron, 6|t| = n_3 . (Y3 - Y0) and
-// K[0][q] = kappa n_0 . n_q / (6 * 6|t|).
+// K[0][q] = kappa n_0 . n_q / (6 * 6|t|).  The four side vectors sum to zero, so
+// n_0 = -(n_1 + n_2 + n_3).
 FE_DEV void cross3(const double *u, const double *v, double *w)
 {
     w[0] = u[1] * v[2] - u[2] * v[1];
@@ -176,143 +288,158 @@ FE_DEV void cross3(const double *u, const double *v, double *w)
 
 FE_DEV double dot3(const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
 
-template <int ROWCAP, int BLOCK>
+template <int ROWCAP, int BLOCK, int UNR>
 __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
 {
     __shared__ double acc[ROWCAP * BLOCK];
     const int tid = threadIdx.x;
     const int32_t k = blockIdx.x * BLOCK + tid;
     if (k >= A.N) return;
-    const int32_t i = A.pi[k];
     const int32_t s = A.pincptr[k], e = A.pincptr[k + 1];
-    const int32_t rs = A.prow_start[k];
     const uint32_t info = A.prow_info[k];
     const int len = info & 0xff, diag = (info >> 8) & 0xff;
     const bool rowd = (info >> 16) & 1;
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
-    double Y[4][3];
-    load_xy<3>(A.node, A.N, i, Y[0]);
+    const double2 *xy = reinterpret_cast<const double2 *>(A.xyp);
+    const int4 *ep4 = reinterpret_cast<const int4 *>(A.elemp);
+    double Y0[3];
+    {
+        const double2 q0 = xy[2 * (int64_t)k], q1 = xy[2 * (int64_t)k + 1];
+        Y0[0] = q0.x; Y0[1] = q0.y; Y0[2] = q1.x;
+    }
     double bsum = 0.0, lift = 0.0;
-    uint64_t dmask = 0;
     int32_t err = 0;
     const double alpha = 0.58541019662496845446;   // (5 + 3 sqrt 5) / 20
     const double beta = 0.13819660112501051518;    // (5 - sqrt 5) / 20
-    const double fi = (A.f.kind == FE_FN_NODAL) ? A.f.nodal[i] : 0.0;
-    for (int32_t p = s; p < e; ++p) {
-        const int32_t key = A.pinc[p];
-        const uint32_t meta = A.pmeta[p];
-        const int32_t t = key >> 2;
-        const int a = key & 3;
-        int32_t v[4];
-        v[0] = i;
+    const bool nodal_f = A.f.kind == FE_FN_NODAL;
+    const double fi = nodal_f ? A.fp[k] : 0.0;
+    for (int32_t p0 = s; p0 < e; p0 += UNR) {
+        int2 km[UNR];
+        int4 ep[UNR];
+        double kt[UNR];
+        int pq[UNR][3];
+        double Y[UNR][3][3];
 #pragma unroll
-        for (int q = 1; q < 4; ++q) {
-            v[q] = A.elem[(int64_t)fe_other<4>(a, q - 1) * A.NT + t];
-            load_xy<3>(A.node, A.N, v[q], Y[q]);
-        }
-        double d10[3], d20[3], d30[3], d31[3], d21[3];
+        for (int u = 0; u < UNR; ++u)
+            if (p0 + u < e) km[u] = A.pincm[p0 + u];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            d10[c] = Y[1][c] - Y[0][c];
-            d20[c] = Y[2][c] - Y[0][c];
-            d30[c] = Y[3][c] - Y[0][c];
-            d31[c] = Y[3][c] - Y[1][c];
-            d21[c] = Y[2][c] - Y[1][c];
-        }
-        double n[4][3];
-        cross3(d31, d21, n[0]);   // side [1 3 2]
-        cross3(d20, d30, n[1]);   // side [0 2 3]
-        cross3(d30, d10, n[2]);   // side [0 3 1]
-        cross3(d10, d20, n[3]);   // side [0 1 2]
-        const double vol6 = dot3(n[3], d30);
-        const double kt = A.kappa ? A.kappa[t] : 1.0;
-        if (!(vol6 > 0.0) || !isfinite(vol6)) err |= ERR_MEASURE;
-        if (!(kt > 0.0) || !isfinite(kt)) err |= ERR_KAPPA;
-        const double sc = kt / (6.0 * vol6);
-        double kr[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) kr[q] = sc * dot3(n[0], n[q]);
-        acc[diag * BLOCK + tid] += kr[0];
-        int off[3];
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-            off[jj] = (meta >> (Meta<4>::OFF + 8 * jj)) & 0xff;
-            acc[off[jj] * BLOCK + tid] += kr[jj + 1];
-        }
-        const double vol = vol6 / 6.0;
-        // load (Section 3.2): symmetric 4-point rule; exact closed form for nodal f
-        if (A.f.kind == FE_FN_NODAL) {
-            const double sf = fi + A.f.nodal[v[1]] + A.f.nodal[v[2]] + A.f.nodal[v[3]];
-            bsum += vol * (fi + sf) / 20.0;
-        } else if (A.f.kind != FE_FN_ZERO) {
-            double S[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) S[c] = Y[0][c] + Y[1][c] + Y[2][c] + Y[3][c];
-            double q = 0.0;
-#pragma unroll
-            for (int kq = 0; kq < 4; ++kq) {
-                double pt[3];
-                for (int c = 0; c < 3; ++c) pt[c] = beta * S[c] + (alpha - beta) * Y[kq][c];
-                q += fn_point<3>(A.f, pt) * (kq == 0 ? alpha : beta);
+        for (int u = 0; u < UNR; ++u)
+            if (p0 + u < e) {
+                const int32_t t = km[u].x >> 2;
+                ep[u] = ep4[t];
+                kt[u] = A.kappa ? A.kappa[t] : 1.0;
             }
-            bsum += vol * q / 4.0;
-        }
-        // Neumann sides containing Y0: the sides opposite Y1, Y2, Y3
-        const uint32_t nb = (meta >> Meta<4>::NBIT) & 7u;
-        if (nb) {
 #pragma unroll
-            for (int jj = 0; jj < 3; ++jj) {
-                if (!((nb >> jj) & 1u)) continue;
-                const int fq = jj + 1;
-                const double nn = sqrt(dot3(n[fq], n[fq]));
-                const double area = 0.5 * nn;
-                double cen[3];
-                for (int c = 0; c < 3; ++c) cen[c] = (Y[0][c] + Y[1][c] + Y[2][c] + Y[3][c] - Y[fq][c]) / 3.0;
-                double g;
-                if (A.gn.kind == FE_FN_DUDN_SINPROD) {
-                    const double nrm[3] = {-n[fq][0] / nn, -n[fq][1] / nn, -n[fq][2] / nn};
-                    g = fn_dudn<3>(A.gn, cen, nrm);
-                } else if (A.gn.kind == FE_FN_NODAL) {
-                    double sg = 0.0;
-                    for (int c = 0; c < 4; ++c)
-                        if (c != fq) sg += A.gn.nodal[v[c]];
-                    g = sg / 3.0;
-                } else {
-                    g = fn_point<3>(A.gn, cen);
+        for (int u = 0; u < UNR; ++u)
+            if (p0 + u < e) {
+                const int a = km[u].x & 3;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    pq[u][q] = sel4(ep[u], fe_other<4>(a, q));
+                    const double2 c0 = xy[2 * (int64_t)pq[u][q]], c1 = xy[2 * (int64_t)pq[u][q] + 1];
+                    Y[u][q][0] = c0.x; Y[u][q][1] = c0.y; Y[u][q][2] = c1.x;
                 }
-                bsum += area * g / 3.0;
             }
-        }
-        const uint32_t db = (meta >> Meta<4>::DBIT) & 7u;
-        if (db) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (p0 + u >= e) break;
+            const uint32_t meta = (uint32_t)km[u].y;
+            const double *Y1 = Y[u][0], *Y2 = Y[u][1], *Y3 = Y[u][2];
+            double d10[3], d20[3], d30[3], d31[3], d21[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                d10[c] = Y1[c] - Y0[c];
+                d20[c] = Y2[c] - Y0[c];
+                d30[c] = Y3[c] - Y0[c];
+                d31[c] = Y3[c] - Y1[c];
+                d21[c] = Y2[c] - Y1[c];
+            }
+            double n1[3], n2[3], n3[3], n0[3];
+            cross3(d20, d30, n1);   // side [0 2 3]
+            cross3(d30, d10, n2);   // side [0 3 1]
+            cross3(d10, d20, n3);   // side [0 1 2]
+            for (int c = 0; c < 3; ++c) n0[c] = -(n1[c] + n2[c] + n3[c]);
+            const double vol6 = dot3(n3, d30);
+            if (!(vol6 > 0.0) || !isfinite(vol6)) err |= ERR_MEASURE;
+            if (!(kt[u] > 0.0) || !isfinite(kt[u])) err |= ERR_KAPPA;
+            const double sc = kt[u] / (6.0 * vol6);
+            const double kr0 = sc * dot3(n0, n0);
+            const double kr[3] = {sc * dot3(n0, n1), sc * dot3(n0, n2), sc * dot3(n0, n3)};
+            acc[diag * BLOCK + tid] += kr0;
+            int off[3];
 #pragma unroll
             for (int jj = 0; jj < 3; ++jj) {
-                if (!((db >> jj) & 1u)) continue;
-                dmask |= 1ull << off[jj];
-                if (A.gd.kind != FE_FN_ZERO) lift += kr[jj + 1] * dirichlet_value<3>(A.gd, v[jj + 1], Y[jj + 1]);
+                off[jj] = (meta >> (Meta<4>::OFF + 8 * jj)) & 0xff;
+                acc[off[jj] * BLOCK + tid] += kr[jj];
+            }
+            const double vol = vol6 / 6.0;
+            // load (Section 3.2): symmetric 4-point rule; exact closed form for nodal f
+            if (nodal_f) {
+                const double sf = fi + A.fp[pq[u][0]] + A.fp[pq[u][1]] + A.fp[pq[u][2]];
+                bsum += vol * (fi + sf) / 20.0;
+            } else if (A.f.kind != FE_FN_ZERO) {
+                double S[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) S[c] = Y0[c] + Y1[c] + Y2[c] + Y3[c];
+                double q = 0.0;
+#pragma unroll
+                for (int kq = 0; kq < 4; ++kq) {
+                    const double *Yk = kq == 0 ? Y0 : Y[u][kq - 1];
+                    double pt[3];
+                    for (int c = 0; c < 3; ++c) pt[c] = beta * S[c] + (alpha - beta) * Yk[c];
+                    q += fn_point<3>(A.f, pt) * (kq == 0 ? alpha : beta);
+                }
+                bsum += vol * q / 4.0;
+            }
+            // Neumann sides containing Y0: the sides opposite Y1, Y2, Y3
+            const uint32_t nb = (meta >> Meta<4>::NBIT) & 7u;
+            if (nb) {
+                const double *nq[3] = {n1, n2, n3};
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    if (!((nb >> jj) & 1u)) continue;
+                    const double *nf = nq[jj];
+                    const double nn = sqrt(dot3(nf, nf));
+                    const double area = 0.5 * nn;
+                    double cen[3];
+                    for (int c = 0; c < 3; ++c) cen[c] = (Y0[c] + Y1[c] + Y2[c] + Y3[c] - Y[u][jj][c]) / 3.0;
+                    double g;
+                    if (A.gn.kind == FE_FN_DUDN_SINPROD) {
+                        const double nrm[3] = {-nf[0] / nn, -nf[1] / nn, -nf[2] / nn};
+                        g = fn_dudn<3>(A.gn, cen, nrm);
+                    } else if (A.gn.kind == FE_FN_NODAL) {
+                        double sg = A.gn.nodal[A.pi[k]];
+                        for (int c = 0; c < 3; ++c)
+                            if (c != jj) sg += A.gn.nodal[A.pi[pq[u][c]]];
+                        g = sg / 3.0;
+                    } else {
+                        g = fn_point<3>(A.gn, cen);
+                    }
+                    bsum += area * g / 3.0;
+                }
+            }
+            const uint32_t db = (meta >> Meta<4>::DBIT) & 7u;
+            if (db && A.gd.kind != FE_FN_ZERO) {
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    if (!((db >> jj) & 1u)) continue;
+                    lift += kr[jj] * dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[pq[u][jj]] : 0,
+                                                        Y[u][jj]);
+                }
             }
         }
     }
     if (err) atomicOr(A.status + ST_ERR, err);
-    for (int c = 0; c < len; ++c) A.val[rs + c] = acc[c * BLOCK + tid];
-    if (A.val_bc) {
-        for (int c = 0; c < len; ++c) {
-            double v = acc[c * BLOCK + tid];
-            if (rowd) v = (c == diag) ? 1.0 : 0.0;
-            else if ((dmask >> c) & 1ull) v = 0.0;
-            A.val_bc[rs + c] = v;
-        }
-    }
-    if (A.b_load) A.b_load[i] = bsum;
-    A.b[i] = rowd ? dirichlet_value<3>(A.gd, i, Y[0]) : bsum - lift;
-    if (A.isd_out) A.isd_out[i] = rowd ? 1 : 0;
+    double gdi = 0.0;
+    if (rowd) gdi = dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[k] : 0, Y0);
+    write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
 }
 
 template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream_t s)
 {
     const unsigned g = (unsigned)cdiv(A.N, BLOCK);
-    if (dim == 2) hipLaunchKernelGGL((k_assemble_2d<ROWCAP, BLOCK>), dim3(g), dim3(BLOCK), 0, s, A);
-    else hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK>), dim3(g), dim3(BLOCK), 0, s, A);
+    if (dim == 2) hipLaunchKernelGGL((k_assemble_2d<ROWCAP, BLOCK, 4>), dim3(g), dim3(BLOCK), 0, s, A);
+    else hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2>), dim3(g), dim3(BLOCK), 0, s, A);
     return fe_launch_check();
 }
 
@@ -328,27 +455,38 @@ extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kapp
     AsmArgs A{};
     A.N = (int32_t)plan->N;
     A.NT = (int32_t)plan->NT;
-    A.elem = plan->elem;
-    A.node = node;
     A.kappa = kappa;
     A.pi = plan->pi;
     A.pincptr = plan->pincptr;
-    A.pinc = plan->pinc;
-    A.prow_start = plan->prow_start;
-    A.pmeta = plan->pmeta;
+    A.prowptr = plan->prowptr;
+    A.elemp = plan->elemp;
+    A.pincm = plan->pincm;
     A.prow_info = plan->prow_info;
+    A.xyp = plan->xyp;
+    A.fp = plan->fp;
     A.f = make_devfn(f);
     A.gd = make_devfn(g_d);
     A.gn = make_devfn(g_n);
-    A.val = val;
-    A.val_bc = val_bc;
-    A.b = b;
-    A.b_load = b_load;
-    A.isd_out = is_dirichlet;
+    A.valp = plan->valp;
     A.status = plan->status;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const unsigned gg = (unsigned)cdiv(A.N, 256);
+    const double *fnodal = (A.f.kind == FE_FN_NODAL) ? A.f.nodal : nullptr;
+    if (plan->dim == 2)
+        hipLaunchKernelGGL(k_scatter_coords<2>, dim3(gg), dim3(256), 0, s, A.N, plan->piinv, node, plan->xyp, fnodal,
+                           plan->fp);
+    else
+        hipLaunchKernelGGL(k_scatter_coords<3>, dim3(gg), dim3(256), 0, s, A.N, plan->piinv, node, plan->xyp, fnodal,
+                           plan->fp);
+    int rc = fe_launch_check();
+    if (rc) return rc;
     const int mr = plan->max_row;
-    if (mr <= 16) return launch<16, 256>(plan->dim, A, s);
-    if (mr <= 32) return launch<32, 128>(plan->dim, A, s);
-    return launch<64, 64>(plan->dim, A, s);
+    if (mr <= 16) rc = launch<16, 256>(plan->dim, A, s);
+    else if (mr <= 32) rc = launch<32, 128>(plan->dim, A, s);
+    else rc = launch<64, 64>(plan->dim, A, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_values_to_label, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,
+                       (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,
+                       (const double *)plan->valp, val, val_bc, b, b_load, is_dirichlet);
+    return fe_launch_check();
 }

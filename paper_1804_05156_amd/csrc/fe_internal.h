@@ -27,10 +27,11 @@ enum : int32_t {
 // Slots of the device status array.
 enum { ST_ERR = 0, ST_UNUSED = 1, ST_MAXROW = 2, ST_MAXDEG = 3, ST_NDIR = 4, ST_COUNT = 16 };
 
-// Fixed per-row capacities of the symbolic kernels.
+// Fixed per-row capacity (stored columns, the vertex itself included) of the row
+// kernels, and their block sizes.
 template <int NV> struct RowCaps;
-template <> struct RowCaps<3> { static constexpr int DEG = 32, COL = 32, BLOCK = 128; };
-template <> struct RowCaps<4> { static constexpr int DEG = 96, COL = 64, BLOCK = 64; };
+template <> struct RowCaps<3> { static constexpr int COL = 32, BLOCK = 128; };
+template <> struct RowCaps<4> { static constexpr int COL = 64, BLOCK = 64; };
 
 // Incidence metadata word (one per vertex-element incidence, in row order):
 //   bits 0-1                 local index a of the row's vertex in the element
@@ -69,23 +70,44 @@ struct fe_plan {
     int64_t N, NT, ninc;
     const int32_t *elem;
     const int8_t *bdflag;
+    int32_t bs, nb, nblk1;   // bucket shift (2^bs vertices per bucket), bucket count, level-1 chunks
     // device arrays inside the caller's workspace
     int32_t *status;      // ST_COUNT ints
     int64_t *totals;      // scan totals (4 slots)
     int64_t *part;        // scan partials
-    int32_t *deg;         // N     incident elements per vertex (label order)
-    int32_t *owner;       // N     smallest incidence key t*nv+a of the vertex
-    uint8_t *isd;         // N     Dirichlet flag (label order)
-    int32_t *rank;        // ninc  arrival rank of each incidence in its vertex list
-    int32_t *owncnt;      // NT+1  vertices whose first incidence is in element t -> offsets
-    int32_t *pi;          // N     processing order -> vertex label
-    int32_t *piinv;       // N     vertex label -> processing position
-    int32_t *pincptr;     // N+1   incidence ranges in processing order
-    int32_t *pinc;        // ninc  incidence keys t*nv+a, ascending within a row
-    uint32_t *pmeta;      // ninc  incidence metadata (Meta<NV>)
-    int32_t *rowlen;      // N+1   row lengths (label order) -> row pointer
-    int32_t *prow_start;  // N     first entry of the row (processing order)
-    uint32_t *prow_info;  // N     row info word (processing order)
+    int2 *vinfo;          // N      per vertex (label order): (start of its sorted list in
+                          //        sorted_l, incident elements | Dirichlet flag << 30)
+    int32_t *inclp;       // N      start of the sorted list (processing order)
+    uint8_t *isd;         // N      Dirichlet flag (label order)
+    uint8_t *isdp;        // N      Dirichlet flag (processing order)
+    int4 *precp;          // N      row record (processing order), see rowrec
+    uint8_t *ownf;        // ninc   1 if incidence t*nv+a is the first one of its vertex
+    int32_t *hist1;       // nb*nblk1+1  level-1 bucket histogram (bucket-major) -> offsets
+    int2 *pairs;          // ninc   (vertex, key) grouped by coarse bucket (shares memory with pincm)
+    int2 *pairs2;         // ninc   (vertex, key) grouped by bucket
+    int32_t *fstart;      // nb+1   first incidence of each bucket in pairs2
+    int32_t ncb;          // coarse buckets (FINE buckets each)
+    int32_t *sorted_l;    // ninc   keys grouped by vertex label, ascending
+    int32_t *owncnt;      // NT+1   vertices whose first incidence is in element t -> offsets
+    int32_t *pi;          // N      processing order -> vertex label
+    int32_t *piinv;       // N      vertex label -> processing position
+    int32_t *pincptr;     // N+1    incidence ranges in processing order
+    int32_t *pinc;        // ninc   incidence keys t*nv+a, ascending within a row
+    int2 *pincm;          // ninc   (key, metadata word) per incidence, processing order
+    int32_t *elemp;       // 4*NT   processing positions of each element's vertices (AoS)
+    int32_t *rowlen;      // N+1    row lengths (label order) -> row pointer (label order)
+    int32_t *prowptr;     // N+1    row lengths (processing order) -> row pointer of the
+                          //        processing-order copy of the matrix
+    uint32_t *prow_info;  // N      row info word (processing order)
+    int4 *rowrec;         // N      per label row: (processing-order start, info word, Dirichlet
+                          //        column mask low, high 32 bits)
+    double *xyp;          // 4*N    numeric scratch: coordinates in processing order
+    double *fp;           // N      numeric scratch: nodal source values in processing order
+    double *valp;         // nnz_max+2N numeric scratch: processing-order rows, row k at
+                          //        prowptr[k] + 2k holding its values then (b, b_load); the
+                          //        pattern pass keeps its column indices here as int32
+    int64_t nnz_max;      // capacity of valp
+    int64_t *stat_part;   // per-block partial statistics
     // host copies
     int64_t nnz, nused, ndir;
     int32_t max_row, max_deg;
@@ -170,6 +192,35 @@ template <int BLOCK> FE_DEV double block_sum(double v, double *lds)
         for (int w = 0; w < BLOCK / 64; ++w) s += lds[w];
     __syncthreads();
     return s;   // valid in thread 0
+}
+
+// Exclusive scan of one int per thread over a block of BLOCK threads (BLOCK a
+// multiple of 64); *total receives the block sum.  `lds` needs 2*BLOCK/64 ints.
+// Every thread of the block must call it.
+template <int BLOCK> FE_DEV int32_t block_exclusive_i32(int32_t v, int32_t *lds, int32_t *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int NW = BLOCK / 64;
+    int32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) lds[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int32_t w = (lane < NW) ? lds[lane] : 0;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(w, off, 64);
+            if (lane >= off) w += y;
+        }
+        if (lane < NW) lds[NW + lane] = w;
+    }
+    __syncthreads();
+    const int32_t pre = (wid > 0) ? lds[NW + wid - 1] : 0;
+    *total = lds[2 * NW - 1];
+    __syncthreads();
+    return pre + x - v;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,16 +1,24 @@
 // plan.hip -- symbolic phase: everything that depends on elem and bdflag only.
 //
 // The duplicate summation of `sparse` (Section 2.2) needs, for every vertex i, the
-// list of element contributions to row i.  It is built here as a counting sort of
-// the (dim+1)*NT vertex-element incidences by vertex, each list then sorted by
-// element so that every sum later runs in ascending element order (this fixes the
-// rounding, whatever the thread schedule).
+// list of element contributions to row i.  Here that list is the set of
+// vertex-element incidences (t, a) with elem[a][t] = i, sorted by element, built by
+// a two-level counting sort of the (dim+1)*NT incidences by vertex that uses only
+// LDS atomics:
+//   level 1: element chunks histogram the incidences by vertex bucket (2^bs
+//            vertices per bucket) and scatter (vertex, key) pairs into buckets;
+//   level 2: one block per bucket counts, places and sorts its incidences per
+//            vertex entirely in LDS.
+// Every per-vertex list is sorted by key t*(dim+1)+a, so sums later run in
+// ascending element order whatever the thread schedule.
 //
-// Rows are processed in an order chosen for memory locality, not in label order:
-// vertex v gets processing position = rank of its first incidence (smallest
-// t*nv + a).  For meshes stored element by element in a spatial order this walks
-// the mesh in that order even when the vertex labels are randomly permuted, so the
-// gathers of element data in the numeric kernel stay within a small window.
+// Rows are then processed in an order chosen for memory locality, not in label
+// order: vertex v gets processing position = rank of its first incidence.  For
+// meshes stored element by element in a spatial order this walks the mesh in that
+// order even when the vertex labels are randomly permuted, so the gathers of the
+// row kernels stay within a small window.  The matrix pattern is first built in
+// that order; a label-order pass then gathers whole rows into the output layout
+// with coalesced stores.
 #include <climits>
 #include <cstdlib>
 #include <cstring>
@@ -20,16 +28,31 @@
 
 namespace {
 
-constexpr int EBLOCK = 256;   // element-parallel kernels
+constexpr int EBLOCK = 256;     // element-parallel kernels
+constexpr int L1B = 1024;       // threads of the level-1 kernels
+constexpr int L1CH = 32768;     // elements per level-1 chunk
+constexpr int NBMAX = 16384;    // buckets held in LDS by the level-1 kernels
+constexpr int VBMAX = 4096;     // vertices per bucket (2^bs) at most
+constexpr int BKB = 256;        // threads of the bucket kernel
+constexpr int BCAPMAX = 24576;  // incidences per bucket sorted in LDS at most (larger: global path)
+constexpr int FINE = 32;        // buckets per coarse bucket
+constexpr int FB = 1024;        // threads of the coarse-to-fine kernel
+constexpr int RUNR = 4;         // incidences per batch in the row kernels
 
-template <int NV>
-__global__ __launch_bounds__(EBLOCK) void k_sym_count(const int32_t *__restrict__ elem, const int8_t *__restrict__ bd,
-                                                      int32_t NT, int32_t N, int32_t *deg, int32_t *owner,
-                                                      int32_t *rank, uint8_t *isd, int32_t *status)
+// Level-1 chunk of block b.  Blocks are dealt to the 8 XCDs round-robin; this gives
+// every XCD a contiguous range of chunks, so the runs that neighbouring chunks
+// write into one bucket are written through the same L2.
+FE_DEV int32_t l1_chunk(int32_t b, int32_t nblk)
 {
-    const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
-    if (t >= NT) return;
-    int32_t v[NV];
+    const int32_t q = nblk / 8, r = nblk % 8, x = b % 8;
+    return x * q + min(x, r) + b / 8;
+}
+
+// Validate one element: vertex range, repeated vertices, side codes.
+template <int NV>
+FE_DEV int32_t check_element(const int32_t *__restrict__ elem, const int8_t *__restrict__ bd, int32_t NT, int32_t N,
+                             int32_t t, int32_t *v, int8_t *code)
+{
     int32_t err = 0;
     for (int a = 0; a < NV; ++a) {
         v[a] = elem[(int64_t)a * NT + t];
@@ -39,224 +62,629 @@ __global__ __launch_bounds__(EBLOCK) void k_sym_count(const int32_t *__restrict_
         for (int a = 0; a < NV; ++a)
             for (int b = a + 1; b < NV; ++b)
                 if (v[a] == v[b]) err |= ERR_REPEAT;
-    int8_t code[NV];
     for (int f = 0; f < NV; ++f) {
         code[f] = bd ? bd[(int64_t)f * NT + t] : 0;
         if (code[f] < 0 || code[f] > 3) err |= ERR_BDCODE;
         else if (code[f] == 3) err |= ERR_ROBIN;
     }
-    if (err) {
-        atomicOr(status + ST_ERR, err);
-        return;
+    return err;
+}
+
+// Level 1a: validation, Dirichlet marks, histogram of incidences per coarse bucket
+// (FINE buckets, 2^(bs+5) vertices).  hist1 is coarse-bucket-major:
+// hist1[cb * nblk1 + chunk].  LDS: nb ints (dynamic), nb = number of coarse buckets.
+template <int NV>
+__global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ elem, const int8_t *__restrict__ bd,
+                                                 int32_t NT, int32_t N, int32_t bs, int32_t nb, int32_t nblk1,
+                                                 int32_t *hist1, uint8_t *isd, int32_t *status)
+{
+    extern __shared__ int32_t h[];
+    for (int b = threadIdx.x; b < nb; b += L1B) h[b] = 0;
+    __syncthreads();
+    const int32_t ch = l1_chunk(blockIdx.x, nblk1);
+    const int32_t t0 = ch * L1CH;
+    const int32_t t1 = min(NT, t0 + L1CH);
+    int32_t err = 0;
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += L1B) {
+        int32_t v[NV];
+        int8_t code[NV];
+        const int32_t e = check_element<NV>(elem, bd, NT, N, t, v, code);
+        if (e) {
+            err |= e;
+            continue;
+        }
+        for (int a = 0; a < NV; ++a) atomicAdd(h + (v[a] >> (bs + 5)), 1);
+        for (int f = 0; f < NV; ++f)
+            if (code[f] == FE_BD_DIRICHLET)
+                for (int q = 0; q < NV; ++q)
+                    if (q != f) isd[v[q]] = 1;
     }
-    for (int a = 0; a < NV; ++a) {
-        rank[(int64_t)a * NT + t] = atomicAdd(deg + v[a], 1);
-        atomicMin(owner + v[a], t * NV + a);
+    if (err) atomicOr(status + ST_ERR, err);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += L1B) hist1[(int64_t)b * nblk1 + ch] = h[b];
+}
+
+// Level 1b: scatter (vertex, key) pairs into their coarse bucket's range.  Every
+// chunk writes one run per coarse bucket (a few hundred pairs: long coalesced runs).
+// The order inside a bucket is arbitrary (LDS atomics); level 2 sorts it.
+template <int NV>
+__global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ elem, int32_t NT, int32_t bs,
+                                                    int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
+                                                    int2 *pairs)
+{
+    extern __shared__ int32_t cur[];
+    const int32_t ch = l1_chunk(blockIdx.x, nblk1);
+    for (int b = threadIdx.x; b < nb; b += L1B) cur[b] = offs[(int64_t)b * nblk1 + ch];
+    __syncthreads();
+    const int32_t t0 = ch * L1CH;
+    const int32_t t1 = min(NT, t0 + L1CH);
+    for (int32_t t = t0 + threadIdx.x; t < t1; t += L1B) {
+        for (int a = 0; a < NV; ++a) {
+            const int32_t v = elem[(int64_t)a * NT + t];
+            const int32_t pos = atomicAdd(cur + (v >> (bs + 5)), 1);
+            pairs[pos] = make_int2(v, t * NV + a);
+        }
     }
-    for (int f = 0; f < NV; ++f)
-        if (code[f] == FE_BD_DIRICHLET)
-            for (int e = 0; e < NV; ++e)
-                if (e != f) isd[v[e]] = 1;
+}
+
+// Level 1c: one block per coarse bucket splits it into its FINE buckets: counts
+// (LDS), bucket starts (fstart), then a scatter whose runs are long again.
+__global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t ncb, const int32_t *__restrict__ offs,
+                                                int32_t nblk1, int64_t ninc, const int2 *__restrict__ pairs,
+                                                int2 *pairs2, int32_t *fstart)
+{
+    __shared__ int32_t cnt[FINE];
+    __shared__ int32_t cur[FINE];
+    const int32_t cb = blockIdx.x;
+    const int32_t s = offs[(int64_t)cb * nblk1];
+    const int32_t e = (cb + 1 < ncb) ? offs[(int64_t)(cb + 1) * nblk1] : (int32_t)ninc;
+    if (threadIdx.x < FINE) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t fbase = cb * FINE;
+    for (int32_t j = s + threadIdx.x; j < e; j += FB) atomicAdd(cnt + ((pairs[j].x >> bs) - fbase), 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = s;
+        for (int f = 0; f < FINE; ++f) {
+            cur[f] = run;
+            if (fbase + f < nb) fstart[fbase + f] = run;
+            run += cnt[f];
+        }
+        if (cb == ncb - 1) fstart[nb] = (int32_t)ninc;
+    }
+    __syncthreads();
+    for (int32_t j = s + threadIdx.x; j < e; j += FB) {
+        const int2 pr = pairs[j];
+        pairs2[atomicAdd(cur + ((pr.x >> bs) - fbase), 1)] = pr;
+    }
+}
+
+// Sort keys[lo, lo+n) ascending (insertion sort: lists are short).
+FE_DEV void isort(int32_t *keys, int32_t lo, int32_t n)
+{
+    for (int32_t j = 1; j < n; ++j) {
+        const int32_t x = keys[lo + j];
+        int32_t m = j - 1;
+        while (m >= 0 && keys[lo + m] > x) {
+            keys[lo + m + 1] = keys[lo + m];
+            --m;
+        }
+        keys[lo + m + 1] = x;
+    }
+}
+
+
+
+// Level 2: one block per bucket.  Count incidences per vertex, place them, sort
+// each vertex's list, write the sorted lists, the per-vertex word (list start,
+// degree, Dirichlet flag) and the first-incidence flag.  LDS holds `cap` keys and
+// two counters per vertex; larger buckets are left to k_l2_bucket_global.
+__global__ __launch_bounds__(BKB) void k_l2_bucket(int32_t N, int32_t bs, int32_t cap,
+                                                   const int32_t *__restrict__ fstart, const int2 *__restrict__ pairs,
+                                                   const uint8_t *__restrict__ isd, int32_t *sorted_l, int2 *vinfo,
+                                                   uint8_t *ownf)
+{
+    extern __shared__ int32_t dyn[];
+    __shared__ int32_t sl[2 * (BKB / 64)];
+    const int32_t b = blockIdx.x;
+    const int32_t VB = 1 << bs;
+    int32_t *keys = dyn;            // cap
+    int32_t *cnt = dyn + cap;       // VB
+    int32_t *cur = cnt + VB;        // VB
+    const int32_t s = fstart[b], e = fstart[b + 1];
+    const int32_t n = e - s;
+    if (n > cap) return;
+    for (int q = threadIdx.x; q < VB; q += BKB) cnt[q] = 0;
+    __syncthreads();
+    const int32_t vbase = b << bs;
+    for (int32_t j = threadIdx.x; j < n; j += BKB) atomicAdd(cnt + (pairs[s + j].x - vbase), 1);
+    __syncthreads();
+    // exclusive scan of cnt[0..VB): each thread owns PER consecutive entries
+    const int PER = (VB + BKB - 1) / BKB;
+    const int q0 = threadIdx.x * PER;
+    int32_t tsum = 0;
+    for (int q = q0; q < q0 + PER && q < VB; ++q) tsum += cnt[q];
+    int32_t tot;
+    int32_t run = block_exclusive_i32<BKB>(tsum, sl, &tot);
+    for (int q = q0; q < q0 + PER && q < VB; ++q) {
+        const int32_t c = cnt[q];
+        cur[q] = run;
+        const int32_t v = vbase + q;
+        if (v < N) vinfo[v] = make_int2(s + run, c | ((int32_t)isd[v] << 30));
+        run += c;
+    }
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < n; j += BKB) {
+        const int2 pr = pairs[s + j];
+        const int32_t pos = atomicAdd(cur + (pr.x - vbase), 1);
+        keys[pos] = pr.y;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < VB; q += BKB) {
+        const int32_t c = cnt[q];
+        if (c == 0) continue;
+        const int32_t lo = cur[q] - c;   // the cursor ended at the list's end
+        isort(keys, lo, c);
+        ownf[keys[lo]] = 1;
+    }
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < n; j += BKB) sorted_l[s + j] = keys[j];
+}
+
+// Level 2 for buckets above `cap` (rare: very uneven degrees): the same steps with
+// the lists in global memory, one block per bucket.  `cnt` and `cursor` are
+// N-sized scratch arrays.
+__global__ __launch_bounds__(BKB) void k_l2_bucket_global(int32_t N, int32_t bs, int32_t cap,
+                                                          const int32_t *__restrict__ fstart,
+                                                          const int2 *__restrict__ pairs,
+                                                          const uint8_t *__restrict__ isd, int32_t *sorted_l,
+                                                          int2 *vinfo, int32_t *cnt, int32_t *cursor, uint8_t *ownf)
+{
+    const int32_t b = blockIdx.x;
+    const int32_t VB = 1 << bs;
+    const int32_t s = fstart[b], e = fstart[b + 1];
+    const int32_t n = e - s;
+    if (n <= cap) return;
+    const int32_t vbase = b << bs;
+    const int32_t vend = min(N, vbase + VB);
+    for (int32_t v = vbase + threadIdx.x; v < vend; v += BKB) cnt[v] = 0;
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < n; j += BKB) atomicAdd(cnt + pairs[s + j].x, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = s;
+        for (int32_t v = vbase; v < vend; ++v) {
+            cursor[v] = run;
+            run += cnt[v];
+        }
+    }
+    __syncthreads();
+    for (int32_t v = vbase + threadIdx.x; v < vend; v += BKB)
+        vinfo[v] = make_int2(cursor[v], cnt[v] | ((int32_t)isd[v] << 30));
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < n; j += BKB) {
+        const int2 pr = pairs[s + j];
+        sorted_l[atomicAdd(cursor + pr.x, 1)] = pr.y;
+    }
+    __syncthreads();
+    for (int32_t v = vbase + threadIdx.x; v < vend; v += BKB) {
+        const int32_t c = cnt[v];
+        if (c == 0) continue;
+        const int32_t lo = cursor[v] - c;
+        isort(sorted_l, lo, c);
+        ownf[sorted_l[lo]] = 1;
+    }
 }
 
 template <int NV>
-__global__ __launch_bounds__(EBLOCK) void k_sym_own_count(const int32_t *__restrict__ elem, int32_t NT,
-                                                          const int32_t *__restrict__ owner, int32_t *owncnt)
+__global__ __launch_bounds__(EBLOCK) void k_own_count(int32_t NT, const uint8_t *__restrict__ ownf, int32_t *owncnt)
 {
     const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
     if (t >= NT) return;
     int c = 0;
-    for (int a = 0; a < NV; ++a) c += (owner[elem[(int64_t)a * NT + t]] == t * NV + a);
+    for (int a = 0; a < NV; ++a) c += ownf[(int64_t)t * NV + a];
     owncnt[t] = c;
 }
 
+// Processing order: the vertex owned by incidence (t, a) goes to position
+// ownoff[t] + (rank of a among t's owned vertices).
 template <int NV>
-__global__ __launch_bounds__(EBLOCK) void k_sym_pi(const int32_t *__restrict__ elem, int32_t NT,
-                                                   const int32_t *__restrict__ owner, const int32_t *__restrict__ ownoff,
-                                                   const int32_t *__restrict__ deg, int32_t *pi, int32_t *piinv,
-                                                   int32_t *pdeg)
+__global__ __launch_bounds__(EBLOCK) void k_pi(const int32_t *__restrict__ elem, int32_t NT,
+                                               const uint8_t *__restrict__ ownf, const int32_t *__restrict__ ownoff,
+                                               const int2 *__restrict__ vinfo, int32_t *pi, int32_t *piinv,
+                                               int32_t *pdeg, int32_t *inclp, uint8_t *isdp)
 {
     const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
     if (t >= NT) return;
     int32_t j = ownoff[t];
     for (int a = 0; a < NV; ++a) {
+        if (!ownf[(int64_t)t * NV + a]) continue;
         const int32_t v = elem[(int64_t)a * NT + t];
-        if (owner[v] == t * NV + a) {
-            pi[j] = v;
-            piinv[v] = j;
-            pdeg[j] = deg[v];
-            ++j;
-        }
+        const int2 vi = vinfo[v];
+        pi[j] = v;
+        piinv[v] = j;
+        pdeg[j] = vi.y & ((1 << 30) - 1);
+        inclp[j] = vi.x;
+        isdp[j] = (uint8_t)((vi.y >> 30) & 1);
+        ++j;
     }
 }
 
 // Vertices used by no element go after the used ones (their rows are empty); their
 // relative order does not affect any value.
-__global__ __launch_bounds__(EBLOCK) void k_sym_unused(int32_t N, const int32_t *__restrict__ deg,
-                                                       const int64_t *__restrict__ nused, int32_t *pi,
-                                                       int32_t *piinv, int32_t *pdeg, int32_t *status)
+__global__ __launch_bounds__(EBLOCK) void k_unused(int32_t N, const int2 *__restrict__ vinfo,
+                                                   const int64_t *__restrict__ nused, int32_t *pi, int32_t *piinv,
+                                                   int32_t *pdeg, int32_t *inclp, uint8_t *isdp, int32_t *status)
 {
     const int32_t v = blockIdx.x * EBLOCK + threadIdx.x;
     if (v >= N) return;
-    if (deg[v] == 0) {
+    if ((vinfo[v].y & ((1 << 30) - 1)) == 0) {
         const int32_t k = (int32_t)(*nused) + atomicAdd(status + ST_UNUSED, 1);
         pi[k] = v;
         piinv[v] = k;
         pdeg[k] = 0;
+        inclp[k] = 0;
+        isdp[k] = 0;
     }
 }
 
-template <int NV>
-__global__ __launch_bounds__(EBLOCK) void k_sym_fill(const int32_t *__restrict__ elem, int32_t NT,
-                                                     const int32_t *__restrict__ piinv,
-                                                     const int32_t *__restrict__ pincptr,
-                                                     const int32_t *__restrict__ rank, int32_t *pinc)
+struct RowArgs {
+    int32_t NT, N;
+    const int32_t *elem;
+    const int8_t *bd;
+    const int32_t *pi, *pincptr, *inclp, *sorted_l;
+    const uint8_t *isdp;
+    int32_t *pinc;        // count: written; final: read
+    int32_t *prowptr;     // count: row lengths; final: row starts
+    int32_t *elemp;       // count: written; final: read
+    int32_t *colindp;     // final
+    int2 *pincm;          // final
+    uint32_t *prow_info;  // final
+    int4 *precp;          // final
+    int32_t *status;
+};
+
+// Insert c into the sorted set cols[0..*u) (stride B in LDS); false if full.
+template <int B, int COLCAP> FE_DEV bool set_insert(int32_t *cols, int tid, int *u, int32_t c)
 {
-    const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
-    if (t >= NT) return;
-    for (int a = 0; a < NV; ++a) {
-        const int32_t v = elem[(int64_t)a * NT + t];
-        pinc[pincptr[piinv[v]] + rank[(int64_t)a * NT + t]] = t * NV + a;
-    }
+    int m = 0;
+    while (m < *u && cols[m * B + tid] < c) ++m;
+    if (m < *u && cols[m * B + tid] == c) return true;
+    if (*u == COLCAP) return false;
+    for (int q = *u; q > m; --q) cols[q * B + tid] = cols[(q - 1) * B + tid];
+    cols[m * B + tid] = c;
+    ++*u;
+    return true;
 }
 
-// Per row (one thread, processing order): sort the incidence keys ascending, then
-// build the sorted set of columns {i} u {vertices of the incident elements}.
-//   FINAL = false: write the row length (label order); keep the sorted keys.
-//   FINAL = true:  write colind, the per-incidence metadata and the row info.
+// Per row (one thread, processing order): the sorted set of columns {i} u
+// {vertices of the incident elements}.  Incidences go in batches of RUNR whose
+// loads are issued together.
+//   FINAL = false: copy the row's sorted incidence keys into processing order,
+//                  record the row's position in each incident element (elemp) and
+//                  write the row length (processing order).
+//   FINAL = true:  write the row's columns and the per-incidence (key, metadata)
+//                  words in processing order and the row record; Dirichlet flags
+//                  of the columns are read in processing order through elemp, which
+//                  keeps those reads local.
 template <int NV, bool FINAL>
-__global__ __launch_bounds__(RowCaps<NV>::BLOCK) void k_sym_rows(
-    const int32_t *__restrict__ elem, const int8_t *__restrict__ bd, int32_t NT, int32_t N,
-    const int32_t *__restrict__ pi, const int32_t *__restrict__ pincptr, int32_t *pinc, int32_t *rowlen,
-    const int32_t *__restrict__ rowptr, const uint8_t *__restrict__ isd, int32_t *colind, uint32_t *pmeta,
-    int32_t *prow_start, uint32_t *prow_info, int32_t *status)
+__global__ __launch_bounds__(RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
 {
-    constexpr int B = RowCaps<NV>::BLOCK, DEGCAP = RowCaps<NV>::DEG, COLCAP = RowCaps<NV>::COL;
-    __shared__ int32_t keys[DEGCAP * B];
+    constexpr int B = RowCaps<NV>::BLOCK, COLCAP = RowCaps<NV>::COL;
     __shared__ int32_t cols[COLCAP * B];
     const int tid = threadIdx.x;
     const int32_t k = blockIdx.x * B + tid;
-    if (k >= N) return;
-    const int32_t i = pi[k];
-    const int32_t s = pincptr[k];
-    const int32_t d = pincptr[k + 1] - s;
+    if (k >= R.N) return;
+    const int32_t i = R.pi[k];
+    const int32_t s = R.pincptr[k];
+    const int32_t d = R.pincptr[k + 1] - s;
     if (d == 0) {   // vertex of no element: empty row, as sparse() would give
         if (!FINAL) {
-            rowlen[i] = 0;
+            R.prowptr[k] = 0;
         } else {
-            prow_start[k] = rowptr[i];
-            prow_info[k] = 0;
+            R.prow_info[k] = 0;
+            R.precp[k] = make_int4(R.prowptr[k], 0, 0, 0);
         }
         return;
     }
-    if (d > DEGCAP) {
-        atomicOr(status + ST_ERR, ERR_LIMIT);
-        if (!FINAL) rowlen[i] = 0;
-        return;
-    }
-    for (int j = 0; j < d; ++j) keys[j * B + tid] = pinc[s + j];
-    if (!FINAL) {
-        for (int j = 1; j < d; ++j) {   // insertion sort (lists are short)
-            int32_t x = keys[j * B + tid];
-            int m = j - 1;
-            while (m >= 0 && keys[m * B + tid] > x) {
-                keys[(m + 1) * B + tid] = keys[m * B + tid];
-                --m;
-            }
-            keys[(m + 1) * B + tid] = x;
-        }
-        for (int j = 0; j < d; ++j) pinc[s + j] = keys[j * B + tid];
-    }
-    // sorted unique column set
+    const int32_t src = FINAL ? s : R.inclp[k];
+    const int32_t *klist = FINAL ? R.pinc : R.sorted_l;
     int u = 1;
     cols[tid] = i;
-    bool over = false;
-    for (int j = 0; j < d && !over; ++j) {
-        const int32_t key = keys[j * B + tid];
-        const int32_t t = key / NV;
-        const int a = key - t * NV;
-        for (int jj = 0; jj < NV - 1; ++jj) {
-            const int b = fe_other<NV>(a, jj);
-            const int32_t c = elem[(int64_t)b * NT + t];
-            int m = 0;
-            while (m < u && cols[m * B + tid] < c) ++m;
-            if (m < u && cols[m * B + tid] == c) continue;
-            if (u == COLCAP) { over = true; break; }
-            for (int q = u; q > m; --q) cols[q * B + tid] = cols[(q - 1) * B + tid];
-            cols[m * B + tid] = c;
-            ++u;
-        }
+    bool ok = true;
+    for (int32_t j0 = 0; j0 < d && ok; j0 += RUNR) {
+        int32_t key[RUNR];
+        int32_t c[RUNR][NV - 1];
+#pragma unroll
+        for (int q = 0; q < RUNR; ++q)
+            if (j0 + q < d) key[q] = klist[src + j0 + q];
+#pragma unroll
+        for (int q = 0; q < RUNR; ++q)
+            if (j0 + q < d) {
+                const int32_t t = key[q] / NV;
+                const int a = key[q] - t * NV;
+                if (!FINAL) {
+                    R.pinc[s + j0 + q] = key[q];
+                    R.elemp[(int64_t)t * 4 + a] = k;
+                }
+#pragma unroll
+                for (int jj = 0; jj < NV - 1; ++jj) c[q][jj] = R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
+            }
+#pragma unroll
+        for (int q = 0; q < RUNR; ++q)
+            if (j0 + q < d)
+#pragma unroll
+                for (int jj = 0; jj < NV - 1; ++jj) ok = ok && set_insert<B, COLCAP>(cols, tid, &u, c[q][jj]);
     }
-    if (over) {
-        atomicOr(status + ST_ERR, ERR_LIMIT);
-        if (!FINAL) rowlen[i] = 0;
+    if (!ok) {
+        atomicOr(R.status + ST_ERR, ERR_LIMIT);
+        if (!FINAL) R.prowptr[k] = 0;
         return;
     }
     if (!FINAL) {
-        rowlen[i] = u;
-        atomicMax(status + ST_MAXROW, u);
-        atomicMax(status + ST_MAXDEG, d);
-        if (isd[i]) atomicAdd(status + ST_NDIR, 1);
+        R.prowptr[k] = u;
         return;
     }
-    const int32_t rs = rowptr[i];
+    const int32_t ps = R.prowptr[k];
     int diag = 0;
     for (int m = 0; m < u; ++m) {
         const int32_t c = cols[m * B + tid];
-        colind[rs + m] = c;
+        R.colindp[ps + m] = c;
         if (c == i) diag = m;
     }
-    for (int j = 0; j < d; ++j) {
-        const int32_t key = keys[j * B + tid];
-        const int32_t t = key / NV;
-        const int a = key - t * NV;
-        uint32_t meta = (uint32_t)a;
-        for (int jj = 0; jj < NV - 1; ++jj) {
-            const int b = fe_other<NV>(a, jj);
-            const int32_t c = elem[(int64_t)b * NT + t];
-            int m = 0;
-            while (cols[m * B + tid] != c) ++m;   // present by construction
-            meta |= (uint32_t)m << (Meta<NV>::OFF + 8 * jj);
-            if (isd[c]) meta |= 1u << (Meta<NV>::DBIT + jj);
-            if (bd && bd[(int64_t)b * NT + t] == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
-        }
-        pmeta[s + j] = meta;
+    uint64_t dmask = 0;
+    const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
+    for (int32_t j0 = 0; j0 < d; j0 += RUNR) {
+        int32_t key[RUNR];
+        int4 ep[RUNR];
+        int32_t c[RUNR][NV - 1];
+        uint8_t dz[RUNR][NV - 1];
+        int8_t code[RUNR][NV - 1];
+#pragma unroll
+        for (int q = 0; q < RUNR; ++q)
+            if (j0 + q < d) key[q] = R.pinc[s + j0 + q];
+#pragma unroll
+        for (int q = 0; q < RUNR; ++q)
+            if (j0 + q < d) {
+                const int32_t t = key[q] / NV;
+                const int a = key[q] - t * NV;
+                ep[q] = ep4[t];
+#pragma unroll
+                for (int jj = 0; jj < NV - 1; ++jj) {
+                    const int b = fe_other<NV>(a, jj);
+                    c[q][jj] = R.elem[(int64_t)b * R.NT + t];
+                    code[q][jj] = R.bd ? R.bd[(int64_t)b * R.NT + t] : 0;
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < RUNR; ++q)
+            if (j0 + q < d) {
+                const int a = key[q] % NV;
+#pragma unroll
+                for (int jj = 0; jj < NV - 1; ++jj) {
+                    const int b = fe_other<NV>(a, jj);
+                    const int32_t pb = b == 0 ? ep[q].x : (b == 1 ? ep[q].y : (b == 2 ? ep[q].z : ep[q].w));
+                    dz[q][jj] = R.isdp[pb];
+                }
+            }
+#pragma unroll
+        for (int q = 0; q < RUNR; ++q)
+            if (j0 + q < d) {
+                uint32_t meta = (uint32_t)(key[q] % NV);
+#pragma unroll
+                for (int jj = 0; jj < NV - 1; ++jj) {
+                    int m = 0;
+                    while (cols[m * B + tid] != c[q][jj]) ++m;   // present by construction
+                    meta |= (uint32_t)m << (Meta<NV>::OFF + 8 * jj);
+                    if (dz[q][jj]) {
+                        meta |= 1u << (Meta<NV>::DBIT + jj);
+                        dmask |= 1ull << m;
+                    }
+                    if (code[q][jj] == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
+                }
+                R.pincm[s + j0 + q] = make_int2(key[q], (int32_t)meta);
+            }
     }
-    prow_start[k] = rs;
-    prow_info[k] = (uint32_t)u | ((uint32_t)diag << 8) | ((uint32_t)(isd[i] ? 1 : 0) << 16);
+    const uint32_t info = (uint32_t)u | ((uint32_t)diag << 8) | ((uint32_t)(R.isdp[k] ? 1 : 0) << 16);
+    R.prow_info[k] = info;
+    R.precp[k] = make_int4(ps, (int32_t)info, (int32_t)(uint32_t)dmask, (int32_t)(uint32_t)(dmask >> 32));
 }
 
+// Label-order row records and lengths: rowrec[i] = precp[piinv[i]], rowlen[i] =
+// its length (one gather per row; the stores are coalesced).
+__global__ __launch_bounds__(256) void k_label_rows(int32_t N, const int32_t *__restrict__ piinv,
+                                                    const int4 *__restrict__ precp, int4 *rowrec, int32_t *rowlen)
+{
+    const int32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const int4 r = precp[piinv[i]];
+    rowrec[i] = r;
+    rowlen[i] = r.y & 0xff;
+}
+
+// Label-order copy of the column indices from the processing-order rows: one
+// wavefront per 64 consecutive label rows, each lane writing consecutive entries
+// of their (contiguous) output range, so the stores are fully coalesced; the reads
+// gather whole rows of the processing-order copy.
+__global__ __launch_bounds__(256) void k_pattern_to_label(int32_t N, const int32_t *__restrict__ rowptr,
+                                                          const int4 *__restrict__ rowrec,
+                                                          const int32_t *__restrict__ colindp, int32_t *colind)
+{
+    __shared__ int32_t sdst[4][65];
+    __shared__ int32_t ssrc[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t i0 = (blockIdx.x * 4 + w) * 64;
+    const int32_t i = i0 + lane;
+    sdst[w][lane] = rowptr[min(i, N)];
+    ssrc[w][lane] = (i < N) ? rowrec[i].x : 0;
+    if (lane == 0) sdst[w][64] = rowptr[min(i0 + 64, N)];
+    __syncthreads();
+    const int32_t base = sdst[w][0];
+    const int32_t total = sdst[w][64] - base;
+    for (int32_t e = lane; e < total; e += 64) {
+        const int32_t pos = base + e;
+        int lo = 0, hi = 63;   // last row r with sdst[r] <= pos
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (sdst[w][mid] <= pos) lo = mid;
+            else hi = mid - 1;
+        }
+        colind[pos] = colindp[ssrc[w][lo] + (pos - sdst[w][lo])];
+    }
+}
+
+// Row statistics without same-address atomics: per-block partials (max row length,
+// max incidences per vertex, Dirichlet count), then one block combines them.
+constexpr int STB = 256;
+
+FE_DEV void block_reduce3(int64_t &mr, int64_t &md, int64_t &nd, int64_t *lds)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        mr = max(mr, (int64_t)__shfl_xor(mr, off, 64));
+        md = max(md, (int64_t)__shfl_xor(md, off, 64));
+        nd += (int64_t)__shfl_xor(nd, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        lds[wid] = mr;
+        lds[STB / 64 + wid] = md;
+        lds[2 * (STB / 64) + wid] = nd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        mr = lds[0];
+        md = lds[STB / 64];
+        nd = lds[2 * (STB / 64)];
+        for (int w = 1; w < STB / 64; ++w) {
+            mr = max(mr, lds[w]);
+            md = max(md, lds[STB / 64 + w]);
+            nd += lds[2 * (STB / 64) + w];
+        }
+    }
+}
+
+// Statistics over processing-order arrays: row lengths (prowptr after its scan),
+// incidences per vertex (pincptr), Dirichlet flags.
+__global__ __launch_bounds__(STB) void k_stats_partial(int32_t N, const int32_t *__restrict__ prowptr,
+                                                       const int32_t *__restrict__ pincptr,
+                                                       const uint8_t *__restrict__ isdp, int64_t *part)
+{
+    __shared__ int64_t lds[3 * (STB / 64)];
+    const int32_t k = blockIdx.x * STB + threadIdx.x;
+    int64_t mr = 0, md = 0, nd = 0;
+    if (k < N) {
+        mr = prowptr[k + 1] - prowptr[k];
+        md = pincptr[k + 1] - pincptr[k];
+        nd = isdp[k];
+    }
+    block_reduce3(mr, md, nd, lds);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = mr;
+        part[3 * blockIdx.x + 1] = md;
+        part[3 * blockIdx.x + 2] = nd;
+    }
+}
+
+__global__ __launch_bounds__(STB) void k_stats_final(int32_t nb, const int64_t *__restrict__ part, int32_t *status)
+{
+    __shared__ int64_t lds[3 * (STB / 64)];
+    int64_t mr = 0, md = 0, nd = 0;
+    for (int32_t b = threadIdx.x; b < nb; b += STB) {
+        mr = max(mr, part[3 * b]);
+        md = max(md, part[3 * b + 1]);
+        nd += part[3 * b + 2];
+    }
+    block_reduce3(mr, md, nd, lds);
+    if (threadIdx.x == 0) {
+        status[ST_MAXROW] = (int32_t)mr;
+        status[ST_MAXDEG] = (int32_t)md;
+        status[ST_NDIR] = (int32_t)nd;
+    }
+}
+
+// Bucket size: about 4096 incidences per bucket on average, at most NBMAX buckets.
+struct Buckets {
+    int32_t bs, nb, ncb, nblk1;
+};
+
+Buckets choose_buckets(int64_t N, int64_t NT, int nv)
+{
+    Buckets B{};
+    const double avg = N > 0 ? (double)nv * (double)NT / (double)N : 1.0;
+    int bs = 0;
+    while (bs < 12 && (double)(1 << (bs + 1)) * avg <= 4096.0) ++bs;
+    if (bs < 4) bs = 4;
+    while (bs < 12 && cdiv(N, (int64_t)1 << bs) > NBMAX) ++bs;
+    B.bs = bs;
+    B.nb = (int32_t)cdiv(N, (int64_t)1 << bs);
+    B.ncb = (int32_t)cdiv(B.nb, FINE);
+    B.nblk1 = (int32_t)cdiv(NT > 0 ? NT : 1, L1CH);
+    return B;
+}
+
+// Upper bound of the number of stored entries: every row has at most the per-row
+// capacity, and every element adds at most nv*(nv-1) off-diagonal entries.
+int64_t nnz_bound(int64_t N, int64_t NT, int nv)
+{
+    const int64_t a = N * (nv == 3 ? RowCaps<3>::COL : RowCaps<4>::COL);
+    const int64_t b = N + NT * nv * (nv - 1);
+    return a < b ? a : b;
+}
+
+enum {
+    W_STATUS, W_TOTALS, W_PART, W_VINFO, W_INCLP, W_ISD, W_ISDP, W_OWNF, W_HIST1, W_OWNCNT, W_PI, W_PIINV,
+    W_PINCPTR, W_PINC, W_PINCM, W_ELEMP, W_ROWLEN, W_PROWPTR, W_PROWINFO, W_PRECP, W_ROWREC, W_XYP, W_FP,
+    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_COUNT
+};
+
 struct Layout {
-    size_t off[20];
+    size_t off[W_COUNT];
     size_t total;
 };
 
-// Workspace layout (every array 256-byte aligned).
+// Workspace layout (every array 256-byte aligned).  The level-1 pairs share memory
+// with pincm (dead before the final row pass writes pincm); the level-2 global
+// path borrows rowlen and prowptr as scratch.
 Layout plan_layout(int64_t N, int64_t NT, int nv)
 {
     const int64_t ninc = (int64_t)nv * NT;
-    const int64_t npart = fe_scan_part_elems(N > NT ? (N > ninc ? N : ninc) : (NT > ninc ? NT : ninc));
-    const size_t sz[] = {
-        sizeof(int32_t) * ST_COUNT,             // 0 status
-        sizeof(int64_t) * 4,                    // 1 totals
-        sizeof(int64_t) * (size_t)(npart + 1),  // 2 part
-        sizeof(int32_t) * (size_t)N,            // 3 deg
-        sizeof(int32_t) * (size_t)N,            // 4 owner
-        sizeof(uint8_t) * (size_t)N,            // 5 isd
-        sizeof(int32_t) * (size_t)ninc,         // 6 rank
-        sizeof(int32_t) * (size_t)(NT + 1),     // 7 owncnt
-        sizeof(int32_t) * (size_t)N,            // 8 pi
-        sizeof(int32_t) * (size_t)N,            // 9 piinv
-        sizeof(int32_t) * (size_t)(N + 1),      // 10 pincptr
-        sizeof(int32_t) * (size_t)ninc,         // 11 pinc
-        sizeof(uint32_t) * (size_t)ninc,        // 12 pmeta
-        sizeof(int32_t) * (size_t)(N + 1),      // 13 rowlen / rowptr
-        sizeof(int32_t) * (size_t)N,            // 14 prow_start
-        sizeof(uint32_t) * (size_t)N,           // 15 prow_info
-    };
+    const Buckets Bk = choose_buckets(N, NT, nv);
+    const int64_t nh = (int64_t)Bk.ncb * Bk.nblk1 + 1;
+    int64_t nscan = N;
+    if (NT > nscan) nscan = NT;
+    if (nh > nscan) nscan = nh;
+    size_t sz[W_COUNT];
+    sz[W_STATUS] = sizeof(int32_t) * ST_COUNT;
+    sz[W_TOTALS] = sizeof(int64_t) * 8;
+    sz[W_PART] = sizeof(int64_t) * (size_t)(fe_scan_part_elems(nscan) + 1);
+    sz[W_VINFO] = sizeof(int2) * (size_t)N;
+    sz[W_INCLP] = sizeof(int32_t) * (size_t)N;
+    sz[W_ISD] = sizeof(uint8_t) * (size_t)N;
+    sz[W_ISDP] = sizeof(uint8_t) * (size_t)N;
+    sz[W_OWNF] = sizeof(uint8_t) * (size_t)ninc;
+    sz[W_HIST1] = sizeof(int32_t) * (size_t)nh;
+    sz[W_OWNCNT] = sizeof(int32_t) * (size_t)(NT + 1);
+    sz[W_PI] = sizeof(int32_t) * (size_t)N;
+    sz[W_PIINV] = sizeof(int32_t) * (size_t)N;
+    sz[W_PINCPTR] = sizeof(int32_t) * (size_t)(N + 1);
+    sz[W_PINC] = sizeof(int32_t) * (size_t)ninc;
+    sz[W_PINCM] = sizeof(int2) * (size_t)ninc;
+    sz[W_ELEMP] = sizeof(int32_t) * 4 * (size_t)NT;
+    sz[W_ROWLEN] = sizeof(int32_t) * (size_t)(N + 1);
+    sz[W_PROWPTR] = sizeof(int32_t) * (size_t)(N + 1);
+    sz[W_PROWINFO] = sizeof(uint32_t) * (size_t)N;
+    sz[W_PRECP] = sizeof(int4) * (size_t)N;
+    sz[W_ROWREC] = sizeof(int4) * (size_t)N;
+    sz[W_XYP] = sizeof(double) * 4 * (size_t)N;
+    sz[W_FP] = sizeof(double) * (size_t)N;
+    sz[W_VALP] = sizeof(double) * (size_t)(nnz_bound(N, NT, nv) + 2 * N);
+    sz[W_STATPART] = sizeof(int64_t) * 3 * (size_t)(cdiv(N, STB) + 1);
+    sz[W_SORTED] = sizeof(int32_t) * (size_t)ninc;
+    sz[W_PAIRS2] = sizeof(int2) * (size_t)ninc;
+    sz[W_FSTART] = sizeof(int32_t) * (size_t)(Bk.nb + 1);
     Layout L{};
     size_t o = 0;
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < W_COUNT; ++k) {
         L.off[k] = o;
         o += align256(sz[k]);
     }
@@ -271,7 +699,31 @@ int check_mesh(const fe_mesh *m)
     if (m->n_node <= 0 || m->n_elem < 0) return FE_EINVAL;
     const int64_t nv = m->dim + 1;
     if (m->n_node >= INT32_MAX || m->n_elem >= INT32_MAX / nv) return FE_EOVERFLOW;
+    if (cdiv(m->n_node, (int64_t)VBMAX) > NBMAX) return FE_ELIMIT;   // more than 2^26 vertices
     return FE_OK;
+}
+
+RowArgs row_args(fe_plan *P)
+{
+    RowArgs R{};
+    R.NT = (int32_t)P->NT;
+    R.N = (int32_t)P->N;
+    R.elem = P->elem;
+    R.bd = P->bdflag;
+    R.pi = P->pi;
+    R.pincptr = P->pincptr;
+    R.inclp = P->inclp;
+    R.sorted_l = P->sorted_l;
+    R.isdp = P->isdp;
+    R.pinc = P->pinc;
+    R.prowptr = P->prowptr;
+    R.elemp = P->elemp;
+    R.colindp = reinterpret_cast<int32_t *>(P->valp);
+    R.pincm = P->pincm;
+    R.prow_info = P->prow_info;
+    R.precp = P->precp;
+    R.status = P->status;
+    return R;
 }
 
 template <int NV> int plan_build(fe_plan *P, hipStream_t s)
@@ -279,42 +731,67 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     const int32_t N = (int32_t)P->N, NT = (int32_t)P->NT;
     const unsigned eg = (unsigned)cdiv(NT > 0 ? NT : 1, EBLOCK);
     const unsigned ng = (unsigned)cdiv(N, EBLOCK);
+    const int64_t nh = (int64_t)P->ncb * P->nblk1;
+    const size_t l1lds = sizeof(int32_t) * (size_t)P->ncb;
     int rc;
     if ((rc = fe_fill_i32(P->status, ST_COUNT, 0, s))) return rc;
-    if ((rc = fe_fill_i32(P->deg, N, 0, s))) return rc;
-    if ((rc = fe_fill_i32(P->owner, N, INT32_MAX, s))) return rc;
     if ((rc = fe_fill_u8(P->isd, N, 0, s))) return rc;
+    if ((rc = fe_fill_u8(P->ownf, P->ninc, 0, s))) return rc;
+    if ((rc = fe_fill_i32(reinterpret_cast<int32_t *>(P->vinfo), 2 * (int64_t)N, 0, s))) return rc;
     if (NT > 0)
-        hipLaunchKernelGGL(k_sym_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, P->bdflag, NT, N, P->deg,
-                           P->owner, P->rank, P->isd, P->status);
+        hipLaunchKernelGGL(k_l1_hist<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, P->bdflag, NT, N,
+                           P->bs, P->ncb, P->nblk1, P->hist1, P->isd, P->status);
     if ((rc = fe_launch_check())) return rc;
-    // Vertex indices are validated by the count kernel only: stop here, before any
-    // kernel uses elem entries as addresses, if one was out of range.
+    // Vertex indices are validated by the histogram kernel only: stop here, before
+    // any kernel uses elem entries as addresses, if one was out of range.
     int32_t err = 0;
     FE_HIP_CHECK(hipMemcpyAsync(&err, P->status + ST_ERR, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     FE_HIP_CHECK(hipStreamSynchronize(s));
     if (err) return fe_status_from_bits(err);
-    if (NT > 0)
-        hipLaunchKernelGGL(k_sym_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, P->owner, P->owncnt);
+    if (NT > 0) {
+        if ((rc = fe_scan_exclusive(P->hist1, P->hist1, nh, P->totals + 4, P->part, P->status, s))) return rc;
+        hipLaunchKernelGGL(k_l1_scatter<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, NT, P->bs,
+                           P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs);
+        hipLaunchKernelGGL(k_l1_fine, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
+                           (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs, P->pairs2, P->fstart);
+        // LDS capacity per bucket: twice the average bucket, at least 2048 keys
+        int64_t cap = cdiv(2 * P->ninc, P->nb);
+        cap = cdiv(cap, 1024) * 1024;
+        if (cap < 2048) cap = 2048;
+        if (cap > BCAPMAX) cap = BCAPMAX;
+        const size_t lds = sizeof(int32_t) * ((size_t)cap + 2 * ((size_t)1 << P->bs));
+        FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_l2_bucket),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        hipLaunchKernelGGL(k_l2_bucket, dim3((unsigned)P->nb), dim3(BKB), lds, s, N, P->bs, (int32_t)cap,
+                           (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd, P->sorted_l,
+                           P->vinfo, P->ownf);
+        hipLaunchKernelGGL(k_l2_bucket_global, dim3((unsigned)P->nb), dim3(BKB), 0, s, N, P->bs, (int32_t)cap,
+                           (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd,
+                           P->sorted_l, P->vinfo, P->rowlen, P->prowptr, P->ownf);
+        hipLaunchKernelGGL(k_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, (const uint8_t *)P->ownf, P->owncnt);
+        if ((rc = fe_launch_check())) return rc;
+    }
     if ((rc = fe_scan_exclusive(P->owncnt, P->owncnt, NT, P->totals + 0, P->part, P->status, s))) return rc;
     if (NT > 0)
-        hipLaunchKernelGGL(k_sym_pi<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, P->owner, P->owncnt, P->deg,
-                           P->pi, P->piinv, P->pincptr);
-    hipLaunchKernelGGL(k_sym_unused, dim3(ng), dim3(EBLOCK), 0, s, N, P->deg, P->totals + 0, P->pi, P->piinv,
-                       P->pincptr, P->status);
+        hipLaunchKernelGGL(k_pi<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, (const uint8_t *)P->ownf,
+                           (const int32_t *)P->owncnt, (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp,
+                           P->isdp);
+    hipLaunchKernelGGL(k_unused, dim3(ng), dim3(EBLOCK), 0, s, N, (const int2 *)P->vinfo,
+                       (const int64_t *)(P->totals + 0), P->pi, P->piinv, P->pincptr, P->inclp, P->isdp, P->status);
     if ((rc = fe_launch_check())) return rc;
     if ((rc = fe_scan_exclusive(P->pincptr, P->pincptr, N, P->totals + 1, P->part, P->status, s))) return rc;
-    if (NT > 0)
-        hipLaunchKernelGGL(k_sym_fill<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, P->piinv, P->pincptr, P->rank,
-                           P->pinc);
     constexpr int RB = RowCaps<NV>::BLOCK;
-    hipLaunchKernelGGL((k_sym_rows<NV, false>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, P->elem, P->bdflag, NT,
-                       N, P->pi, P->pincptr, P->pinc, P->rowlen, (const int32_t *)nullptr, P->isd,
-                       (int32_t *)nullptr, (uint32_t *)nullptr, (int32_t *)nullptr, (uint32_t *)nullptr, P->status);
+    const RowArgs R = row_args(P);
+    hipLaunchKernelGGL((k_rows<NV, false>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R);
     if ((rc = fe_launch_check())) return rc;
-    if ((rc = fe_scan_exclusive(P->rowlen, P->rowlen, N, P->totals + 2, P->part, P->status, s))) return rc;
+    if ((rc = fe_scan_exclusive(P->prowptr, P->prowptr, N, P->totals + 2, P->part, P->status, s))) return rc;
+    const unsigned sb = (unsigned)cdiv(N, STB);
+    hipLaunchKernelGGL(k_stats_partial, dim3(sb), dim3(STB), 0, s, N, (const int32_t *)P->prowptr,
+                       (const int32_t *)P->pincptr, (const uint8_t *)P->isdp, P->stat_part);
+    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STB), 0, s, (int32_t)sb, (const int64_t *)P->stat_part, P->status);
+    if ((rc = fe_launch_check())) return rc;
     int32_t st[ST_COUNT];
-    int64_t tot[4];
+    int64_t tot[8];
     FE_HIP_CHECK(hipMemcpyAsync(st, P->status, sizeof(st), hipMemcpyDeviceToHost, s));
     FE_HIP_CHECK(hipMemcpyAsync(tot, P->totals, sizeof(tot), hipMemcpyDeviceToHost, s));
     FE_HIP_CHECK(hipStreamSynchronize(s));
@@ -325,17 +802,24 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     P->max_deg = st[ST_MAXDEG];
     P->ndir = st[ST_NDIR];
     if (tot[1] != P->ninc) return FE_EHIP;   // every incidence must be placed
+    if (P->nnz > P->nnz_max) return FE_EHIP;
     return FE_OK;
 }
 
 template <int NV> int plan_pattern(fe_plan *P, int32_t *rowptr, int32_t *colind, hipStream_t s)
 {
-    const int32_t N = (int32_t)P->N, NT = (int32_t)P->NT;
-    FE_HIP_CHECK(hipMemcpyAsync(rowptr, P->rowlen, sizeof(int32_t) * (size_t)(N + 1), hipMemcpyDeviceToDevice, s));
+    const int32_t N = (int32_t)P->N;
     constexpr int RB = RowCaps<NV>::BLOCK;
-    hipLaunchKernelGGL((k_sym_rows<NV, true>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, P->elem, P->bdflag, NT, N,
-                       P->pi, P->pincptr, P->pinc, (int32_t *)nullptr, (const int32_t *)P->rowlen, P->isd, colind,
-                       P->pmeta, P->prow_start, P->prow_info, P->status);
+    const RowArgs R = row_args(P);
+    hipLaunchKernelGGL((k_rows<NV, true>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R);
+    hipLaunchKernelGGL(k_label_rows, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, (const int32_t *)P->piinv,
+                       (const int4 *)P->precp, P->rowrec, P->rowlen);
+    int rc;
+    if ((rc = fe_launch_check())) return rc;
+    if ((rc = fe_scan_exclusive(P->rowlen, P->rowlen, N, P->totals + 3, P->part, P->status, s))) return rc;
+    FE_HIP_CHECK(hipMemcpyAsync(rowptr, P->rowlen, sizeof(int32_t) * (size_t)(N + 1), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_pattern_to_label, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N,
+                       (const int32_t *)P->rowlen, (const int4 *)P->rowrec, (const int32_t *)R.colindp, colind);
     return fe_launch_check();
 }
 
@@ -363,6 +847,7 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     fe_plan *P = new (std::nothrow) fe_plan();
     if (!P) return FE_EINVAL;
     char *base = static_cast<char *>(ws);
+    const Buckets Bk = choose_buckets(mesh->n_node, mesh->n_elem, nv);
     P->dim = mesh->dim;
     P->nv = nv;
     P->N = mesh->n_node;
@@ -370,22 +855,40 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     P->ninc = (int64_t)nv * mesh->n_elem;
     P->elem = mesh->elem;
     P->bdflag = mesh->bdflag;
-    P->status = reinterpret_cast<int32_t *>(base + L.off[0]);
-    P->totals = reinterpret_cast<int64_t *>(base + L.off[1]);
-    P->part = reinterpret_cast<int64_t *>(base + L.off[2]);
-    P->deg = reinterpret_cast<int32_t *>(base + L.off[3]);
-    P->owner = reinterpret_cast<int32_t *>(base + L.off[4]);
-    P->isd = reinterpret_cast<uint8_t *>(base + L.off[5]);
-    P->rank = reinterpret_cast<int32_t *>(base + L.off[6]);
-    P->owncnt = reinterpret_cast<int32_t *>(base + L.off[7]);
-    P->pi = reinterpret_cast<int32_t *>(base + L.off[8]);
-    P->piinv = reinterpret_cast<int32_t *>(base + L.off[9]);
-    P->pincptr = reinterpret_cast<int32_t *>(base + L.off[10]);
-    P->pinc = reinterpret_cast<int32_t *>(base + L.off[11]);
-    P->pmeta = reinterpret_cast<uint32_t *>(base + L.off[12]);
-    P->rowlen = reinterpret_cast<int32_t *>(base + L.off[13]);
-    P->prow_start = reinterpret_cast<int32_t *>(base + L.off[14]);
-    P->prow_info = reinterpret_cast<uint32_t *>(base + L.off[15]);
+    P->bs = Bk.bs;
+    P->nb = Bk.nb;
+    P->ncb = Bk.ncb;
+    P->nblk1 = Bk.nblk1;
+    P->status = reinterpret_cast<int32_t *>(base + L.off[W_STATUS]);
+    P->totals = reinterpret_cast<int64_t *>(base + L.off[W_TOTALS]);
+    P->part = reinterpret_cast<int64_t *>(base + L.off[W_PART]);
+    P->vinfo = reinterpret_cast<int2 *>(base + L.off[W_VINFO]);
+    P->inclp = reinterpret_cast<int32_t *>(base + L.off[W_INCLP]);
+    P->isd = reinterpret_cast<uint8_t *>(base + L.off[W_ISD]);
+    P->isdp = reinterpret_cast<uint8_t *>(base + L.off[W_ISDP]);
+    P->ownf = reinterpret_cast<uint8_t *>(base + L.off[W_OWNF]);
+    P->hist1 = reinterpret_cast<int32_t *>(base + L.off[W_HIST1]);
+    P->owncnt = reinterpret_cast<int32_t *>(base + L.off[W_OWNCNT]);
+    P->pi = reinterpret_cast<int32_t *>(base + L.off[W_PI]);
+    P->piinv = reinterpret_cast<int32_t *>(base + L.off[W_PIINV]);
+    P->pincptr = reinterpret_cast<int32_t *>(base + L.off[W_PINCPTR]);
+    P->pinc = reinterpret_cast<int32_t *>(base + L.off[W_PINC]);
+    P->pincm = reinterpret_cast<int2 *>(base + L.off[W_PINCM]);
+    P->pairs = P->pincm;
+    P->elemp = reinterpret_cast<int32_t *>(base + L.off[W_ELEMP]);
+    P->rowlen = reinterpret_cast<int32_t *>(base + L.off[W_ROWLEN]);
+    P->prowptr = reinterpret_cast<int32_t *>(base + L.off[W_PROWPTR]);
+    P->prow_info = reinterpret_cast<uint32_t *>(base + L.off[W_PROWINFO]);
+    P->precp = reinterpret_cast<int4 *>(base + L.off[W_PRECP]);
+    P->rowrec = reinterpret_cast<int4 *>(base + L.off[W_ROWREC]);
+    P->xyp = reinterpret_cast<double *>(base + L.off[W_XYP]);
+    P->fp = reinterpret_cast<double *>(base + L.off[W_FP]);
+    P->valp = reinterpret_cast<double *>(base + L.off[W_VALP]);
+    P->stat_part = reinterpret_cast<int64_t *>(base + L.off[W_STATPART]);
+    P->sorted_l = reinterpret_cast<int32_t *>(base + L.off[W_SORTED]);
+    P->pairs2 = reinterpret_cast<int2 *>(base + L.off[W_PAIRS2]);
+    P->fstart = reinterpret_cast<int32_t *>(base + L.off[W_FSTART]);
+    P->nnz_max = nnz_bound(mesh->n_node, mesh->n_elem, nv);
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = (nv == 3) ? plan_build<3>(P, s) : plan_build<4>(P, s);
     if (rc) {

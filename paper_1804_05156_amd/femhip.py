@@ -294,7 +294,7 @@ class Plan:
         return g
 
     def __del__(self):
-        if getattr(self, "handle", None) is not None:
+        if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.fe_plan_destroy(self.handle)
             self.handle = None
 
