@@ -42,7 +42,7 @@ typedef enum fe_status {
     FE_ESIZE = -5,         /* workspace smaller than the size query returned */
     FE_EHIP = -6,          /* a HIP runtime call failed */
     FE_ENOCONV = -7,       /* the iteration limit was reached before the tolerance */
-    FE_ELIMIT = -8         /* a vertex has more than 64 neighbours or 1024 incident elements */
+    FE_ELIMIT = -8         /* a fixed capacity exceeded: see the function */
 } fe_status;
 
 /* Boundary side types (Section 1.2).  Side a of an element is opposite local vertex a. */
@@ -111,7 +111,9 @@ int fe_plan_workspace_bytes(const fe_mesh *mesh, size_t *bytes);
  * mesh->bdflag, which must stay valid and unchanged while the plan lives.
  * Errors: FE_EINVAL (NULL, sizes, vertex index out of range, bdflag code not in
  * 0..3), FE_EUNSUPPORTED (dim, bdflag 3), FE_EMESH (repeated vertex in an
- * element), FE_EOVERFLOW, FE_ESIZE, FE_ELIMIT, FE_EHIP. */
+ * element), FE_EOVERFLOW, FE_ESIZE, FE_EHIP, and FE_ELIMIT when the mesh exceeds
+ * the fixed capacities: more than 2^26 vertices, or a vertex with more than 32
+ * (2D) or 64 (3D) distinct neighbours, itself included. */
 int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe_plan **plan, int64_t *nnz,
                    void *stream);
 
@@ -157,6 +159,14 @@ int fe_assemble(fe_plan *plan, const double *node, const double *kappa, const fe
 int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
             const double *x, double *y, void *stream);
 
+/* out[i] = mask[i] ? a[i] : b[i] for i < n (device arrays; a or b NULL reads as 0).
+ * With mask = is_dirichlet it forms the start vector of a solve (g_D at Dirichlet
+ * rows, 0 elsewhere: a = b from fe_assemble, b = NULL) and the adjoint right-hand
+ * side (dJ/du at free rows, 0 at Dirichlet rows: a = NULL, b = dJ/du).  out may
+ * alias a or b. */
+int fe_select(int64_t n, const uint8_t *mask, const double *a, const double *b, double *out,
+              void *stream);
+
 /* ---------------------------------------------------------------------------
  * Solve (replaces the direct solve of equation (directsolve)).
  * ------------------------------------------------------------------------- */
@@ -185,6 +195,79 @@ int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const doub
  * local stiffness of t (Section 3.1). */
 int fe_grad(fe_plan *plan, const double *node, const double *u, const double *lam, double *g,
             void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches of independent problems (many meshes, one launch).
+ *
+ * A batch is the disjoint union of its instances: the caller concatenates the
+ * instances' node arrays (vertex labels of instance k offset by off[k]) and element
+ * arrays (labels offset accordingly), and builds one plan for the union.  The
+ * union's A_bc is block diagonal, one block per instance, so one fe_assemble call
+ * assembles every instance at once (each instance's rows bitwise equal to those of
+ * its own plan).  The batched solve runs Jacobi-PCG on every block with its own
+ * scalars and stopping test in one persistent kernel; each instance's iterates are
+ * bitwise equal to fe_solve on that block alone.  At most 4096 instances.
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace for n rows in n_inst instances (FE_ELIMIT above 4096). */
+int fe_batch_solve_workspace_bytes(int64_t n, int32_t n_inst, size_t *bytes);
+
+/* Solve every diagonal block of the CSR matrix (rowptr, colind, val) (device, n =
+ * inst_row_off[n_inst] rows).  inst_row_off: host, n_inst + 1 nondecreasing row
+ * offsets starting at 0; block k is rows [inst_row_off[k], inst_row_off[k+1]) and
+ * must not couple to other rows.  u: x0 on entry, solutions on return.  Instance k
+ * stops when its recurrence residual drops to rtol times ||b_k||_2, or after maxit
+ * iterations.  blocks_per_cu: workgroups per compute unit of the persistent grid
+ * (0 picks a default; above what fits, FE_ELIMIT).  iters, relres: host arrays of
+ * n_inst (may be NULL).  ws: 256-byte aligned device workspace of at least the
+ * queried size.  Synchronizes.  Returns FE_ENOCONV if an instance hit maxit,
+ * FE_EINVAL for a non-positive diagonal entry, FE_ELIMIT if the device-wide wait
+ * timed out (the grid was not co-resident). */
+int fe_batch_solve(int32_t n_inst, const int64_t *inst_row_off, const int32_t *rowptr,
+                   const int32_t *colind, const double *val, const double *b, double *u,
+                   double rtol, int32_t maxit, int32_t blocks_per_cu, void *ws, size_t ws_bytes,
+                   int32_t *iters, double *relres, void *stream);
+
+typedef struct fe_batch fe_batch;   /* opaque; refers to the caller's plan and workspace */
+
+typedef struct fe_batch_info {
+    int32_t n_inst, n_units;        /* instances; 256-row reduction units over all of them */
+    int64_t n_rows;
+    int32_t grid;                   /* workgroups of the persistent solve kernel */
+    int32_t blocks_per_cu, max_blocks_per_cu;
+    int32_t cooperative;            /* 1 if the captured solve launch is a cooperative launch */
+    int32_t captures;               /* graph captures so far */
+} fe_batch_info;
+
+/* Batched assemble + solve replayed from one captured hipGraph.  plan: a plan of the
+ * union mesh with its pattern built (fe_plan_pattern); inst_node_off: host, n_inst
+ * + 1 vertex offsets with inst_node_off[n_inst] = N.  ws: as for fe_batch_solve
+ * with n = N.  The plan and ws stay owned by the caller and must outlive the batch.
+ * Synchronizes (uploads the instance table). */
+int fe_batch_create(fe_plan *plan, int32_t n_inst, const int64_t *inst_node_off,
+                    int32_t blocks_per_cu, void *ws, size_t ws_bytes, fe_batch **batch,
+                    void *stream);
+
+/* Change the persistent grid (workgroups per compute unit, 0 = default); the next
+ * fe_batch_assemble_solve captures a new graph. */
+int fe_batch_set_grid(fe_batch *batch, int32_t blocks_per_cu);
+
+int fe_batch_get_info(const fe_batch *batch, fe_batch_info *info);
+
+/* Assemble the union (as fe_assemble with b_load = NULL), set the start vector u =
+ * g_D at Dirichlet rows and 0 elsewhere (as fe_select), and solve every instance
+ * (as fe_batch_solve on val_bc, b), all as one graph launch.  The graph is captured
+ * on the first call and again whenever a pointer, function or scalar argument
+ * differs from the previous call; otherwise it is replayed.  u (device, N): the
+ * solutions on return.  iters, relres: host, n_inst each (may be NULL).
+ * Synchronizes; also reports fe_plan_status. */
+int fe_batch_assemble_solve(fe_batch *batch, const double *node, const double *kappa,
+                            const fe_fn *f, const fe_fn *g_d, const fe_fn *g_n,
+                            const int32_t *rowptr, const int32_t *colind, double *val,
+                            double *val_bc, double *b, double *u, double rtol, int32_t maxit,
+                            int32_t *iters, double *relres, void *stream);
+
+int fe_batch_destroy(fe_batch *batch);
 
 #ifdef __cplusplus
 }

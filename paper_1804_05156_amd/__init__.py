@@ -2,11 +2,13 @@
 
 The compute path lives in the HIP C-ABI library ``libfemhip.so`` (sources under
 ``csrc/``, declarations in ``include/femhip.h``); :mod:`.femhip` is its thin ctypes
-binding and :mod:`.meshgen` builds seeded synthetic meshes.
+binding, :mod:`.batch` batches many meshes into one graph launch (with the
+autotuner of its persistent solve), and :mod:`.meshgen` builds seeded synthetic
+meshes.
 """
 import importlib
 
-__all__ = ["femhip", "meshgen"]
+__all__ = ["femhip", "batch", "meshgen"]
 
 
 def __getattr__(name):

@@ -1,0 +1,115 @@
+"""Batches of independent meshes: their union, one graph launch that assembles and
+solves every instance, and the autotuner of the persistent solve grid.
+
+Only argument marshalling happens here (concatenating arrays and offsetting labels
+to form the union, allocating outputs); assembly and the solves run in the
+library's kernels through ``fe_batch_*``.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import femhip
+
+
+class Batch:
+    """Union of ``n_inst`` meshes.  nodes[k]: (dim, N_k) float64, elems[k]: (dim+1,
+    NT_k) int32 with labels local to instance k, bdflags[k]: (dim+1, NT_k) int8 (or
+    all None); all CUDA tensors.  Vertex labels of instance k are offset by
+    ``node_off[k]`` in the union, element labels by ``elem_off[k]``."""
+
+    def __init__(self, nodes, elems, bdflags=None, blocks_per_cu: int = 0, stream=None):
+        if not nodes or len(nodes) != len(elems):
+            raise ValueError("need one elem array per node array")
+        self.n_inst = len(nodes)
+        self.node_off = [0]
+        self.elem_off = [0]
+        for nd, el in zip(nodes, elems):
+            self.node_off.append(self.node_off[-1] + int(nd.shape[1]))
+            self.elem_off.append(self.elem_off[-1] + int(el.shape[1]))
+        self.node = torch.cat(list(nodes), 1).contiguous()
+        self.elem = torch.cat([el + off for el, off in zip(elems, self.node_off[:-1])], 1).to(torch.int32).contiguous()
+        self.bdflag = None if bdflags is None else torch.cat(list(bdflags), 1).contiguous()
+        self.handle = None
+        self.plan = femhip.Plan(self.node, self.elem, self.bdflag, stream)
+        self.N = self.plan.N
+        self.ws = torch.empty(femhip.fe_batch_solve_workspace_bytes(self.N, self.n_inst), dtype=torch.uint8,
+                              device=self.node.device)
+        self.handle = femhip.fe_batch_create(self.plan.handle, self.node_off, self.ws, blocks_per_cu, stream)
+        dev = self.node.device
+        nnz = max(self.plan.nnz, 1)
+        # outputs live as long as the batch, so that repeated calls replay one graph
+        self.val = torch.empty(nnz, dtype=torch.float64, device=dev)
+        self.val_bc = torch.empty(nnz, dtype=torch.float64, device=dev)
+        self.b = torch.empty(self.N, dtype=torch.float64, device=dev)
+        self.u = torch.empty(self.N, dtype=torch.float64, device=dev)
+
+    def assemble_solve(self, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=100000, stream=None,
+                       allow_noconv=False):
+        """Assemble and solve every instance; returns (u, iters, relres) with u the
+        union's solution vector (``split`` cuts it per instance)."""
+        it, rel, _ = femhip.fe_batch_assemble_solve(self.handle, self.node, kappa, f, gD, gN, self.plan.rowptr,
+                                                    self.plan.colind, self.val, self.val_bc, self.b, self.u, rtol,
+                                                    maxit, self.n_inst, stream, allow_noconv)
+        return self.u, it, rel
+
+    def split(self, x):
+        return [x[self.node_off[k]:self.node_off[k + 1]] for k in range(self.n_inst)]
+
+    def set_grid(self, blocks_per_cu: int):
+        femhip.fe_batch_set_grid(self.handle, blocks_per_cu)
+
+    def info(self) -> dict:
+        return femhip.fe_batch_get_info(self.handle)
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and femhip._lib is not None:
+            femhip._lib.fe_batch_destroy(self.handle)
+            self.handle = None
+
+
+def _time_call(fn, reps: int) -> float:
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=100000, candidates=None,
+             reps: int = 1, cache_path: str | None = None) -> dict:
+    """Pick the persistent grid (workgroups per compute unit) of the batched solve by
+    timing whole graph launches of this batch; results are bitwise independent of
+    the choice.  With ``cache_path`` the choice is stored in a JSON file keyed by
+    device and batch shape and reused on later calls.  Returns the choice and the
+    measured times (ms per launch)."""
+    info = batch.info()
+    key = f"{torch.cuda.get_device_name()}|{info['n_inst']}|{info['n_rows']}|{batch.plan.nnz}|{rtol}"
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            batch.set_grid(int(cache[key]["blocks_per_cu"]))
+            return dict(cache[key], cached=True)
+    hi = int(info["max_blocks_per_cu"])
+    cands = candidates or sorted({c for c in (1, 2, 3, 4, 6, 8) if c <= hi})
+    times = {}
+    for c in cands:
+        batch.set_grid(c)
+        batch.assemble_solve(kappa, f, gD, gN, rtol, maxit)          # capture + warm
+        times[c] = _time_call(lambda: batch.assemble_solve(kappa, f, gD, gN, rtol, maxit), reps)
+    best = min(times, key=times.get)
+    batch.set_grid(best)
+    out = {"blocks_per_cu": best, "ms": {str(k): v for k, v in times.items()}}
+    if cache_path:
+        cache[key] = out
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    return dict(out, cached=False)

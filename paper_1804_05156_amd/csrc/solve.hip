@@ -14,11 +14,11 @@
 // test, so every reduction has a fixed order and results are bitwise repeatable.
 // Scalars live in device memory; the host launches iterations in chunks and reads
 // the "done" flag once per chunk, kernels after convergence return at once.
-#include "fe_internal.h"
+#include "cg_common.h"
 
 namespace {
 
-constexpr int SB = 256;   // threads per block, one row per thread
+constexpr int SB = CG_UNIT;   // threads per block, one row per thread
 
 enum { S_RZ = 0, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_PQ, S_NSCAL = 8 };
 enum { F_DONE = 0, F_ITER, F_TICKET, F_BAD, F_NFLAG = 8 };
@@ -62,30 +62,6 @@ __global__ __launch_bounds__(SB) void k_spmv(int32_t n, const int32_t *__restric
     y[i] = s;
 }
 
-// Last-block reduction: returns true in every thread of the block that arrived
-// last; that block then sees all partials written before the ticket.
-FE_DEV bool last_block(int32_t *ticket)
-{
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int32_t prev = atomicAdd(ticket, 1);
-        is_last = (prev == (int32_t)gridDim.x - 1);
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last != 0;
-}
-
-// Sum part[k*stride] for k in [0, nb) in a fixed order (block-strided then tree).
-FE_DEV double sum_partials(const double *part, int32_t nb, double *lds)
-{
-    double v = 0.0;
-    for (int32_t k = threadIdx.x; k < nb; k += SB) v += part[k];
-    return block_sum<SB>(v, lds);
-}
-
 // diag(A)^-1, r = b - A x, z = r * dinv, p_old = 0; partials r.z, r.r, b.b.
 __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ colind, const double *__restrict__ val,
@@ -97,15 +73,10 @@ __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__rest
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     double rz = 0.0, rr = 0.0, bb = 0.0;
     if (i < n) {
-        double s = 0.0, d = 0.0;
-        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-            const int32_t c = colind[q];
-            s += val[q] * x[c];
-            if (c == i) d = val[q];
-        }
+        double ri, d;
+        cg_init_row(i, rowptr, colind, val, b, x, &ri, &d);
         if (!(d > 0.0)) atomicOr(flag + F_BAD, 1);
         const double di = 1.0 / d;
-        const double ri = b[i] - s;
         dinv[i] = di;
         r[i] = ri;
         z[i] = ri * di;
@@ -123,10 +94,10 @@ __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__rest
         part[nb + blockIdx.x] = s1;
         part[2 * nb + blockIdx.x] = s2;
     }
-    if (!last_block(flag + F_TICKET)) return;
-    const double RZ = sum_partials(part, nb, lds);
-    const double RR = sum_partials(part + nb, nb, lds);
-    const double BB = sum_partials(part + 2 * nb, nb, lds);
+    if (!cg_last_arrival(flag + F_TICKET, nb)) return;
+    const double RZ = cg_sum_partials(part, nb, lds);
+    const double RR = cg_sum_partials(part + nb, nb, lds);
+    const double BB = cg_sum_partials(part + 2 * nb, nb, lds);
     if (threadIdx.x == 0) {
         const double bn2 = BB > 0.0 ? BB : 1.0;
         scal[S_RZ] = RZ;
@@ -137,7 +108,6 @@ __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__rest
         scal[S_ALPHA] = 0.0;
         flag[F_ITER] = 0;
         flag[F_DONE] = (RR <= rtol * rtol * bn2) ? 1 : 0;
-        flag[F_TICKET] = 0;
     }
 }
 
@@ -154,11 +124,7 @@ __global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restric
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     double pq = 0.0;
     if (i < n) {
-        double s = 0.0;
-        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-            const int32_t c = colind[q];
-            s += val[q] * (z[c] + beta * pold[c]);
-        }
+        const double s = cg_apply_row(i, rowptr, colind, val, z, pold, beta);
         const double pi = z[i] + beta * pold[i];
         pnew[i] = pi;
         qv[i] = s;
@@ -166,12 +132,11 @@ __global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restric
     }
     const double bs = block_sum<SB>(pq, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = bs;
-    if (!last_block(flag + F_TICKET)) return;
-    const double PQ = sum_partials(part, gridDim.x, lds);
+    if (!cg_last_arrival(flag + F_TICKET, gridDim.x)) return;
+    const double PQ = cg_sum_partials(part, gridDim.x, lds);
     if (threadIdx.x == 0) {
         scal[S_PQ] = PQ;
         scal[S_ALPHA] = scal[S_RZ] / PQ;
-        flag[F_TICKET] = 0;
     }
 }
 
@@ -202,16 +167,15 @@ __global__ __launch_bounds__(SB) void k_cg_b(int32_t n, double *__restrict__ x, 
         part[blockIdx.x] = s0;
         part[nb + blockIdx.x] = s1;
     }
-    if (!last_block(flag + F_TICKET)) return;
-    const double RZ = sum_partials(part, nb, lds);
-    const double RR = sum_partials(part + nb, nb, lds);
+    if (!cg_last_arrival(flag + F_TICKET, nb)) return;
+    const double RZ = cg_sum_partials(part, nb, lds);
+    const double RR = cg_sum_partials(part + nb, nb, lds);
     if (threadIdx.x == 0) {
         scal[S_BETA] = RZ / scal[S_RZ];
         scal[S_RZ] = RZ;
         scal[S_RR] = RR;
         flag[F_ITER] += 1;
         if (RR <= scal[S_TOL2]) flag[F_DONE] = 1;
-        flag[F_TICKET] = 0;
     }
 }
 

@@ -122,7 +122,25 @@ template <typename T> int fill(T *p, int64_t n, T v, hipStream_t s)
     return fe_launch_check();
 }
 
+__global__ void k_select(int64_t n, const uint8_t *__restrict__ mask, const double *a, const double *b, double *out)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = mask[i] ? (a ? a[i] : 0.0) : (b ? b[i] : 0.0);
+}
+
 }  // namespace
+
+extern "C" int fe_select(int64_t n, const uint8_t *mask, const double *a, const double *b, double *out, void *stream)
+{
+    if (n < 0 || (n > 0 && (!mask || !out))) return FE_EINVAL;
+    if (n == 0) return FE_OK;
+    int64_t blocks = cdiv(n, 256);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_select, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), n, mask, a,
+                       b, out);
+    return fe_launch_check();
+}
 
 int64_t fe_scan_part_elems(int64_t n) { return cdiv(n > 0 ? n : 1, SCAN_TILE) + 1; }
 
@@ -165,7 +183,7 @@ extern "C" const char *fe_status_string(int status)
     case FE_ESIZE: return "workspace too small";
     case FE_EHIP: return "HIP runtime error";
     case FE_ENOCONV: return "iteration limit reached before the tolerance";
-    case FE_ELIMIT: return "a row exceeds the per-row capacity";
+    case FE_ELIMIT: return "a fixed capacity was exceeded (row width, vertex count, instances, or grid wait)";
     default: return "unknown status";
     }
 }

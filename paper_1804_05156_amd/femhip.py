@@ -25,7 +25,9 @@ FE_FN_ZERO, FE_FN_CONST, FE_FN_LINEAR, FE_FN_SINPROD, FE_FN_DUDN_SINPROD, FE_FN_
 ENTRY_POINTS = (
     "fe_version", "fe_status_string", "fe_plan_workspace_bytes", "fe_plan_create", "fe_plan_pattern",
     "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_spmv",
-    "fe_solve_workspace_bytes", "fe_solve", "fe_grad",
+    "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_grad", "fe_batch_solve_workspace_bytes",
+    "fe_batch_solve", "fe_batch_create", "fe_batch_set_grid", "fe_batch_get_info", "fe_batch_assemble_solve",
+    "fe_batch_destroy",
 )
 
 
@@ -42,6 +44,12 @@ class fe_plan_info(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_node", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
                 ("n_inc", C.c_int64), ("max_row", C.c_int32), ("max_deg", C.c_int32),
                 ("n_dirichlet", C.c_int64)]
+
+
+class fe_batch_info(C.Structure):
+    _fields_ = [("n_inst", C.c_int32), ("n_units", C.c_int32), ("n_rows", C.c_int64), ("grid", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("max_blocks_per_cu", C.c_int32), ("cooperative", C.c_int32),
+                ("captures", C.c_int32)]
 
 
 class FemhipError(RuntimeError):
@@ -71,6 +79,15 @@ def _load():
         "fe_solve_workspace_bytes": ([I64, C.POINTER(SZ)], C.c_int),
         "fe_solve": ([I64, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), P], C.c_int),
         "fe_grad": ([P, P, P, P, P, P], C.c_int),
+        "fe_select": ([I64, P, P, P, P, P], C.c_int),
+        "fe_batch_solve_workspace_bytes": ([I64, I32, C.POINTER(SZ)], C.c_int),
+        "fe_batch_solve": ([I32, P, P, P, P, P, P, D, I32, I32, P, SZ, P, P, P], C.c_int),
+        "fe_batch_create": ([P, I32, P, I32, P, SZ, C.POINTER(P), P], C.c_int),
+        "fe_batch_set_grid": ([P, I32], C.c_int),
+        "fe_batch_get_info": ([P, C.POINTER(fe_batch_info)], C.c_int),
+        "fe_batch_assemble_solve": ([P, P, P, C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), P, P, P, P, P,
+                                     P, D, I32, P, P, P], C.c_int),
+        "fe_batch_destroy": ([P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -194,6 +211,11 @@ def fe_spmv(rowptr, colind, val, x, y, stream=None):
            "fe_spmv")
 
 
+def fe_select(mask, a, b, out, stream=None):
+    _check(_lib.fe_select(out.numel(), _ptr(mask, torch.uint8, "mask"), _ptr(a, torch.float64, "a"),
+                          _ptr(b, torch.float64, "b"), _ptr(out, torch.float64, "out"), _stream(stream)), "fe_select")
+
+
 def fe_solve_workspace_bytes(n: int) -> int:
     s = C.c_size_t()
     _check(_lib.fe_solve_workspace_bytes(n, C.byref(s)), "fe_solve_workspace_bytes")
@@ -216,6 +238,68 @@ def fe_solve(rowptr, colind, val, b, u, rtol: float, maxit: int, ws, stream=None
 def fe_grad(plan, node, u, lam, g, stream=None):
     _check(_lib.fe_grad(plan, _ptr(node, torch.float64, "node"), _ptr(u, torch.float64, "u"),
                         _ptr(lam, torch.float64, "lam"), _ptr(g, torch.float64, "g"), _stream(stream)), "fe_grad")
+
+
+def fe_batch_solve_workspace_bytes(n: int, n_inst: int) -> int:
+    s = C.c_size_t()
+    _check(_lib.fe_batch_solve_workspace_bytes(n, n_inst, C.byref(s)), "fe_batch_solve_workspace_bytes")
+    return int(s.value)
+
+
+def _i64_array(off):
+    off = [int(v) for v in off]
+    return (C.c_int64 * len(off))(*off)
+
+
+def fe_batch_solve(inst_row_off, rowptr, colind, val, b, u, rtol: float, maxit: int, ws, blocks_per_cu: int = 0,
+                   stream=None, allow_noconv=False):
+    """Returns (iters list, relres list, status)."""
+    n_inst = len(inst_row_off) - 1
+    it = (C.c_int32 * n_inst)()
+    rel = (C.c_double * n_inst)()
+    rc = _lib.fe_batch_solve(n_inst, _i64_array(inst_row_off), _ptr(rowptr, torch.int32), _ptr(colind, torch.int32),
+                             _ptr(val, torch.float64), _ptr(b, torch.float64), _ptr(u, torch.float64), float(rtol),
+                             int(maxit), int(blocks_per_cu), _ptr(ws, torch.uint8, "ws"), ws.numel(), it, rel,
+                             _stream(stream))
+    if not (rc == FE_ENOCONV and allow_noconv):
+        _check(rc, "fe_batch_solve")
+    return list(it), list(rel), rc
+
+
+def fe_batch_create(plan, inst_node_off, ws, blocks_per_cu: int = 0, stream=None):
+    h = C.c_void_p()
+    _check(_lib.fe_batch_create(plan, len(inst_node_off) - 1, _i64_array(inst_node_off), int(blocks_per_cu),
+                                _ptr(ws, torch.uint8, "ws"), ws.numel(), C.byref(h), _stream(stream)),
+           "fe_batch_create")
+    return h
+
+
+def fe_batch_set_grid(batch, blocks_per_cu: int):
+    _check(_lib.fe_batch_set_grid(batch, int(blocks_per_cu)), "fe_batch_set_grid")
+
+
+def fe_batch_get_info(batch) -> dict:
+    info = fe_batch_info()
+    _check(_lib.fe_batch_get_info(batch, C.byref(info)), "fe_batch_get_info")
+    return {k: getattr(info, k) for k, _ in fe_batch_info._fields_}
+
+
+def fe_batch_assemble_solve(batch, node, kappa, f, gD, gN, rowptr, colind, val, val_bc, b, u, rtol: float,
+                            maxit: int, n_inst: int, stream=None, allow_noconv=False):
+    it = (C.c_int32 * n_inst)()
+    rel = (C.c_double * n_inst)()
+    rc = _lib.fe_batch_assemble_solve(batch, _ptr(node, torch.float64, "node"), _ptr(kappa, torch.float64, "kappa"),
+                                      _fnref(f), _fnref(gD), _fnref(gN), _ptr(rowptr, torch.int32),
+                                      _ptr(colind, torch.int32), _ptr(val, torch.float64, "val"),
+                                      _ptr(val_bc, torch.float64, "val_bc"), _ptr(b, torch.float64, "b"),
+                                      _ptr(u, torch.float64, "u"), float(rtol), int(maxit), it, rel, _stream(stream))
+    if not (rc == FE_ENOCONV and allow_noconv):
+        _check(rc, "fe_batch_assemble_solve")
+    return list(it), list(rel), rc
+
+
+def fe_batch_destroy(batch):
+    _check(_lib.fe_batch_destroy(batch), "fe_batch_destroy")
 
 
 # ----------------------------------------------------------------------------- conveniences
@@ -281,7 +365,8 @@ class Plan:
         """Solve val_bc u = rhs (default asm.b); u0 defaults to b at Dirichlet rows, 0 elsewhere."""
         b = asm.b if rhs is None else rhs
         if u0 is None:
-            u = torch.where(asm.is_dirichlet.bool(), b, torch.zeros_like(b))
+            u = torch.empty_like(b)
+            fe_select(asm.is_dirichlet, b, None, u, stream)
         else:
             u = u0.clone()
         it, rel, _ = fe_solve(self.rowptr, self.colind, asm.val_bc, b, u, rtol, maxit, self.solve_workspace(),
@@ -331,7 +416,8 @@ class PoissonSolve(torch.autograd.Function):
     def backward(ctx, grad_u):
         (u,) = ctx.saved_tensors
         plan, asm = ctx.plan, ctx.asm
-        rhs = torch.where(asm.is_dirichlet.bool(), torch.zeros_like(grad_u), grad_u).contiguous()
+        rhs = torch.empty_like(u)
+        fe_select(asm.is_dirichlet, None, grad_u.contiguous(), rhs)
         lam, _, _ = plan.solve(asm, u0=torch.zeros_like(rhs), rtol=ctx.rtol, rhs=rhs)
         g = plan.grad(u, lam)
         return g, None, None, None, None, None

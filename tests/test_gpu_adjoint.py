@@ -1,0 +1,108 @@
+"""Adjoint gradient dJ/dkappa on the GPU: kernel parity with the oracle, the
+autograd path against central finite differences of J through the GPU forward
+solve, and the homogeneity identity sum_t kappa_t dJ/dkappa_t = -(u - u_obs).u.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_05156_amd import meshgen
+from gpu_helpers import fns, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FE_FN_SINPROD = 3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_grad_kernel_matches_oracle(dim):
+    from paper_1804_05156_amd import femhip
+    log(f"case: grad kernel dim={dim}")
+    if dim == 2:
+        m = meshgen.square_mesh(21, jitter=0.2, permute=True, seed=41)
+    else:
+        m = meshgen.kuhn_cube(6, jitter=0.15, permute=True, seed=41)
+    rng = np.random.default_rng(42)
+    u = rng.standard_normal(m.n_node)
+    lam = rng.standard_normal(m.n_node)
+    node, elem, bd, _ = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    g = plan.grad(torch.from_numpy(u).cuda(), torch.from_numpy(lam).cuda())
+    plan.check()
+    g = g.cpu().numpy()
+    go = oracle.grad(m.node, m.elem, u, lam)
+    # rounding scale: |t| (sum_a |lam_a| |grad l_a|) (sum_b |u_b| |grad l_b|)
+    scale = np.zeros(m.n_elem)
+    for t in range(m.n_elem):
+        v = m.elem[:, t]
+        K, G, meas = oracle.local_stiffness(m.node[:, v].T)
+        gn = np.linalg.norm(G, axis=1)
+        scale[t] = meas * float(np.abs(lam[v]) @ gn) * float(np.abs(u[v]) @ gn)
+    assert np.all(np.abs(g - go) <= 1e-12 * scale)
+
+
+def _fd_problem():
+    m = meshgen.square_mesh(17, jitter=0.2, seed=517, kappa="lognormal")
+    rng = np.random.default_rng(518)
+    kobs = np.exp(rng.standard_normal(m.n_elem))
+    return m, kobs
+
+
+def test_autograd_matches_oracle_and_finite_differences():
+    from paper_1804_05156_amd import femhip
+    log("case: autograd adjoint vs oracle and FD")
+    m, kobs = _fd_problem()
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    f = femhip.Fn(femhip.FE_FN_SINPROD, (2 * math.pi ** 2,))
+    u_obs = femhip.PoissonSolve.apply(torch.from_numpy(kobs).cuda(), plan, f, None, None, 1e-14).detach()
+    kappa = kap.clone().requires_grad_(True)
+    u = femhip.PoissonSolve.apply(kappa, plan, f, None, None, 1e-14)
+    J = 0.5 * torch.sum((u - u_obs) ** 2)
+    J.backward()
+    g = kappa.grad.cpu().numpy()
+    # oracle adjoint on the same data
+    fo = oracle.Fn(oracle.FN_SINPROD, (2 * math.pi ** 2,))
+    Jo, go, uo, lamo = oracle.objective_and_grad(m.node, m.elem, m.bdflag, m.kappa, u_obs.cpu().numpy(), f=fo)
+    assert abs(float(J.detach()) - Jo) <= 1e-9 * abs(Jo)
+    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+    # central differences of J through the GPU forward solve, step 1e-4 kappa_t
+    gfd = np.zeros(m.n_elem)
+    with torch.no_grad():
+        for t in range(m.n_elem):
+            d = 1e-4 * m.kappa[t]
+            vals = []
+            for sgn in (1.0, -1.0):
+                kp = kap.clone()
+                kp[t] += sgn * d
+                up = femhip.PoissonSolve.apply(kp, plan, f, None, None, 1e-14)
+                vals.append(0.5 * float(torch.sum((up - u_obs) ** 2)))
+            gfd[t] = (vals[0] - vals[1]) / (2 * d)
+    big = np.abs(gfd) >= 1e-3 * np.abs(gfd).max()
+    rel = np.abs(g[big] - gfd[big]) / np.abs(gfd[big])
+    log(f"  FD: max componentwise relative error {rel.max():.2e} over {big.sum()} elements")
+    assert rel.max() < 1e-6
+
+
+def test_homogeneity_identity_full_size():
+    """1025^2 jittered mesh, lognormal kappa, u_obs from a second kappa: with g_D = 0
+    and g_N = 0, sum_t kappa_t dJ/dkappa_t = -(u - u_obs).u."""
+    from paper_1804_05156_amd import femhip
+    log("case: adjoint identity 1025^2")
+    m = meshgen.workload("jitter1025")
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    f = femhip.Fn(femhip.FE_FN_SINPROD, (2 * math.pi ** 2,))
+    kobs = torch.exp(torch.from_numpy(np.random.default_rng(55).standard_normal(m.n_elem)).cuda())
+    u_obs = femhip.PoissonSolve.apply(kobs, plan, f, None, None, 1e-12).detach()
+    kappa = kap.clone().requires_grad_(True)
+    u = femhip.PoissonSolve.apply(kappa, plan, f, None, None, 1e-12)
+    J = 0.5 * torch.sum((u - u_obs) ** 2)
+    J.backward()
+    lhs = float(torch.dot(kap, kappa.grad))
+    rhs = -float(torch.dot(u.detach() - u_obs, u.detach()))
+    log(f"  lhs {lhs:.12e} rhs {rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-6 * abs(rhs)
