@@ -1,23 +1,38 @@
-"""Benchmark: P1 stiffness/load assembly of the 2049^2 jittered, permuted mesh on one GPU.
+"""Benchmark of the P1 assembly path on one GPU, with the batched and adjoint
+extensions reported against the plain path.
 
-One step = the whole assembly path from the mesh arrays already in HBM to the CSR
-matrix and the right-hand side with boundary conditions, nothing cached between
-steps: fe_plan_create (symbolic phase: incidence lists, row pattern, Dirichlet set),
-fe_plan_pattern (rowptr/colind), fe_assemble (A, A_bc, b, b_load, Dirichlet flags).
-`value` = elements assembled per second over the timed steps.
+Headline step (``value``): the whole assembly of the 2049^2 jittered, permuted
+mesh from the mesh arrays already in HBM to the CSR matrix and the right-hand side
+with boundary conditions, nothing cached between steps: fe_plan_create (incidence
+lists, row pattern, Dirichlet set), fe_plan_pattern (rowptr/colind) and fe_assemble
+(A, A_bc, b, b_load, Dirichlet flags).  value = elements assembled per second.
 
-Also reported (extra keys): the warm numeric phase alone (plan reused, new kappa),
-the roofline of the dominant kernel measured with HIP events on its stream, the
-phase split, and the CPU oracle timed on a bounded sample of the same recipe.
+Also reported on the same JSON line:
+  warm         fe_assemble alone (plan reused, new kappa each call)
+  kernels      every kernel of the step timed with HIP events on its launch stream
+  roofline     the kernel with the largest time per step: its algorithmic bytes
+               (each array it must read or write, once) over its mean duration
+               against the 8 TB/s HBM peak; traffic from hardware counters when the
+               committed counter summary matches the current sources
+  batched      256 uneven jittered meshes assembled + Jacobi-PCG solved (1e-10) by
+               one graph launch, against a loop of the plain path over the same
+               instances (plans built beforehand in both)
+  adjoint      1025^2 mesh: forward solve + adjoint solve + gradient kernel against
+               the forward solve alone
+  cpu_baseline the CPU oracle (single thread) on a bounded sample of the recipe
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload jitter2049|kuhn129]
+                       [--no-cpu] [--no-batch] [--no-adjoint]
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -26,10 +41,69 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+COUNTERS = os.path.join(ROOT, "profiles", "counters_{workload}.txt")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    """Hash of the library sources; counter data is valid only for the sources it was taken on."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1804_05156_amd", "csrc", "*")) +
+                   [os.path.join(ROOT, "include", "femhip.h")])
+    for p in files:
+        with open(p, "rb") as fh:
+            h.update(os.path.basename(p).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_bytes(name, N, NT, nnz, dim, nodal):
+    """Algorithmic bytes of one launch of a kernel of the assembly step: every array
+    the kernel must read or write, each element counted once."""
+    nv = dim + 1
+    ninc = nv * NT
+    model = {
+        "k_l1_hist": 5 * ninc + N,
+        "k_l1_scatter": 4 * ninc + 8 * ninc,
+        "k_l1_fine": 8 * ninc + 8 * ninc,
+        "k_l2_bucket": 8 * ninc + N + 4 * ninc + 8 * N + N,
+        "k_own_count": ninc + 4 * NT,
+        "k_pi": ninc + 4 * NT + 4 * N + 8 * N + 17 * N,
+        "k_unused": 8 * N,
+        "k_rows_count": 12 * N + 4 * ninc + 4 * ninc + 4 * ninc + 16 * NT + 4 * N,
+        "k_stats_partial": 9 * N,
+        "k_rows_final": 12 * N + 4 * ninc + 16 * NT + 4 * ninc + ninc + N + 4 * nnz + 8 * ninc + 20 * N,
+        "k_label_rows": 40 * N,
+        "k_pattern_to_label": 20 * N + 8 * nnz,
+        "k_scatter_coords": 8 * dim * N + 4 * N + 32 * N + (16 * N if nodal else 0),
+        "k_assemble_2d": 8 * ninc + 8 * N + 32 * N + 8 * NT + 8 * (nnz + 2 * N) + (8 * N if nodal else 0),
+        "k_assemble_3d": 8 * ninc + 8 * N + 32 * N + 8 * NT + 8 * (nnz + 2 * N) + (8 * N if nodal else 0),
+        "k_values_to_label": 16 * N + 4 * N + 4 * N + 8 * (nnz + 2 * N) + 16 * nnz + 16 * N + N,
+    }
+    return model.get(name)
+
+
+def read_counters(workload):
+    """Per-dispatch FETCH/WRITE bytes from the committed counter summary, scaled by
+    its copy-kernel calibration; None if absent or taken on other sources."""
+    path = COUNTERS.format(workload=workload)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"sources_sha256:\s*(\w+)", text)
+    if not m or m.group(1) != source_hash():
+        return None
+    fcal = float(re.search(r"fetch_scale:\s*([\d.eE+-]+)", text).group(1))
+    wcal = float(re.search(r"write_scale:\s*([\d.eE+-]+)", text).group(1))
+    out = {}
+    for line in text.splitlines():
+        mm = re.match(r"\s*(k_\w+)\s+([\d.]+)\s+([\d.]+)\s*$", line)
+        if mm:
+            out[mm.group(1)] = (float(mm.group(2)) * 1024 * fcal, float(mm.group(3)) * 1024 * wcal)
+    return out
 
 
 def main():
@@ -37,8 +111,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="jitter2049")
+    ap.add_argument("--workload", default="jitter2049", choices=["jitter2049", "kuhn129"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (for counter calibration)")
     args = ap.parse_args()
@@ -46,8 +122,8 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): every figure here is a single-GPU "
+              "figure, and the multi-GPU sharding is a design note, not built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -70,6 +146,7 @@ def main():
         u = torch.prod(torch.sin(math.pi * node), dim=0)
         f = femhip.Fn(femhip.FE_FN_NODAL, (0,), (3 * math.pi ** 2 * u).contiguous())
         gn = femhip.Fn(femhip.FE_FN_DUDN_SINPROD, (1.0,))
+    nodal = f.kind == femhip.FE_FN_NODAL
 
     # buffers allocated once (the library allocates nothing)
     mesh = femhip.make_mesh(node, elem, bd)
@@ -85,7 +162,7 @@ def main():
     isd = torch.empty(N, dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
-    ev = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731  (events on the launch stream)
+    ev = lambda: torch.cuda.Event(enable_timing=True)   # noqa: E731  (recorded on the launch stream)
 
     def cold_step(times=None):
         e0, e1, e2, e3 = ev(), ev(), ev(), ev()
@@ -106,7 +183,6 @@ def main():
     torch.cuda.synchronize()
     plans, times = [], []
     log(f"[bench] timing {args.steps} cold steps")
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plans.append(cold_step(times))
@@ -115,16 +191,42 @@ def main():
     rc = femhip.fe_plan_status(plans[-1])
     if rc != 0:
         raise RuntimeError(f"kernel status {rc}")
-    for p in plans[:-1]:
+    for p in plans:
         femhip.fe_plan_destroy(p)
-    plan = plans[-1]
     ms_step = wall / args.steps * 1e3
-    sym_ms = np.median([a.elapsed_time(b_) for a, b_, _, _ in times])
-    pat_ms = np.median([b_.elapsed_time(c) for _, b_, c, _ in times])
-    num_ms = np.median([c.elapsed_time(d) for _, _, c, d in times])
+    sym_ms = float(np.median([a.elapsed_time(b_) for a, b_, _, _ in times]))
+    pat_ms = float(np.median([b_.elapsed_time(c) for _, b_, c, _ in times]))
+    num_ms = float(np.median([c.elapsed_time(d) for _, _, c, d in times]))
+
+    # the same steps with every kernel bracketed by events on its stream
+    log(f"[bench] timing {args.steps} cold steps kernel by kernel")
+    femhip.fe_prof_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        femhip.fe_plan_destroy(cold_step())
+    torch.cuda.synchronize()
+    ms_step_prof = (time.perf_counter() - t0) / args.steps * 1e3
+    kern = femhip.fe_prof_read()
+    femhip.fe_prof_enable(False)
+    kernels = {}
+    for name, k in kern.items():
+        nb = kernel_bytes(name, N, NT, nnz, dim, nodal)
+        kernels[name] = {"launches_per_step": k["launches"] / args.steps, "avg_us": k["avg_ms"] * 1e3,
+                         "us_per_step": k["total_ms"] * 1e3 / args.steps,
+                         "GBps": (nb / (k["avg_ms"] * 1e-3) / 1e9) if nb else None}
+    dom = max(kernels, key=lambda n: kernels[n]["us_per_step"])
+    dom_bytes = kernel_bytes(dom, N, NT, nnz, dim, nodal)
+    dom_us = kernels[dom]["avg_us"]
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    counters = read_counters(args.workload)
+    traffic = None
+    if counters and dom in counters:
+        traffic = counters[dom][0] + counters[dom][1]
 
     # warm numeric phase: plan reused, a different kappa each call
     log("[bench] timing warm numeric phase")
+    plan, _ = femhip.fe_plan_create(mesh, ws)
+    femhip.fe_plan_pattern(plan, rowptr, colind)
     for _ in range(3):
         femhip.fe_assemble(plan, node, kappa2, f, None, gn, val, val_bc, b, b_load, isd)
     torch.cuda.synchronize()
@@ -139,18 +241,14 @@ def main():
     warm_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in wev]))
     femhip.fe_plan_destroy(plan)
 
-    # algorithmic bytes of fe_assemble: inputs read once, outputs written once
-    in_bytes = dim * N * 8 + (dim + 1) * NT * 4 + NT * 8
-    out_bytes = 2 * nnz * 8 + 2 * N * 8 + N
-    if f.kind == femhip.FE_FN_NODAL:
-        in_bytes += N * 8
-    asm_bytes = in_bytes + out_bytes
-    achieved = asm_bytes / (warm_ms * 1e-3) / 1e9
-    cold_bytes = dim * N * 8 + (dim + 1) * NT * 5 + NT * 8 + (N + 1) * 4 + nnz * 4 + out_bytes
+    # compulsory bytes of the whole assembly (inputs once, outputs once)
+    in_bytes = dim * N * 8 + (dim + 1) * NT * 4 + (dim + 1) * NT + NT * 8 + (N * 8 if nodal else 0)
+    cold_bytes = in_bytes + (N + 1) * 4 + nnz * 4 + 2 * nnz * 8 + 2 * N * 8 + N
+    warm_bytes = in_bytes - (dim + 1) * NT + 2 * nnz * 8 + 2 * N * 8 + N
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(args.workload)
+    batched = None if args.no_batch else bench_batched(args)
+    adjoint = None if args.no_adjoint else bench_adjoint(args)
+    cpu = None if args.no_cpu else cpu_baseline(args.workload)
 
     out = {
         "metric": "assembled elements/s + HBM GB/s; batched & adjoint vs plain on 1 GPU",
@@ -168,14 +266,135 @@ def main():
         "config": {"workload": args.workload, "n_node": N, "n_elem": NT, "nnz": nnz, "dim": dim,
                    "step": "cold: plan + pattern + numeric assembly with boundary conditions"},
         "phases_ms": {"plan_create": sym_ms, "pattern": pat_ms, "assemble": num_ms},
-        "warm": {"ms": warm_ms, "elements_per_s": NT / (warm_ms * 1e-3)},
         "effective_GBps_cold": cold_bytes / (ms_step * 1e-3) / 1e9,
-        "roofline": {"kernel": "k_assemble (fe_assemble)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "bytes_per_launch": asm_bytes, "traffic": None},
+        "warm": {"ms": warm_ms, "elements_per_s": NT / (warm_ms * 1e-3),
+                 "effective_GBps": warm_bytes / (warm_ms * 1e-3) / 1e9},
+        "kernels": {"ms_per_step_with_events": ms_step_prof, "by_kernel": kernels},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
+                     "avg_us": dom_us},
+        "batched": batched,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """256 jittered meshes, sides uniform in [17, 513]: one graph launch (assembly of
+    the union + batched PCG) against the plain path looped over the instances."""
+    import numpy as np
+    import torch
+    from paper_1804_05156_amd import batch, femhip, meshgen
+    log("[bench] batched: generating 256 meshes")
+    sizes = meshgen.batch_sizes()
+    ms = meshgen.batch_meshes(sizes)
+    dev = torch.device("cuda:0")
+    nodes = [torch.from_numpy(m.node).to(dev) for m in ms]
+    elems = [torch.from_numpy(m.elem).to(dev) for m in ms]
+    bds = [torch.from_numpy(m.bdflag).to(dev) for m in ms]
+    kaps = [torch.from_numpy(m.kappa).to(dev) for m in ms]
+    kap = torch.cat(kaps).contiguous()
+    f = femhip.Fn(femhip.FE_FN_SINPROD, (2 * math.pi ** 2,))
+    rtol = 1e-10
+    NT = int(sum(m.n_elem for m in ms))
+    log("[bench] batched: building the union plan, autotuning the solve grid")
+    B = batch.Batch(nodes, elems, bds)
+    tune = batch.autotune(B, kap, f, None, None, rtol, log=lambda msg: log(f"[bench] batched: {msg}"))
+    log(f"[bench] batched: autotune {tune}")
+    B.assemble_solve(kap, f, None, None, rtol)
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 3))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        u, it, rel = B.assemble_solve(kap, f, None, None, rtol)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    # the plain path: one plan per instance (built beforehand), then assemble + solve each
+    log("[bench] batched: plain path over the instances")
+    plans = [femhip.Plan(n_, e_, b_) for n_, e_, b_ in zip(nodes, elems, bds)]
+    asms = [p.assemble(k_, f) for p, k_ in zip(plans, kaps)]
+    plans[0].solve(asms[0], rtol=rtol)   # first call of every kernel of the plain path
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = []
+    for k, (p, k_, a) in enumerate(zip(plans, kaps, asms)):
+        p.assemble(k_, f, out=a)
+        _, itk, _ = p.solve(a, rtol=rtol)
+        its.append(itk)
+        if k % 64 == 63:
+            log(f"[bench] batched: plain path, {k + 1} instances done")
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = its == list(it)
+    info = B.info()
+    return {"workload": "256 jittered meshes, sides U{17..513}, lognormal kappa, rtol 1e-10",
+            "n_inst": len(ms), "n_node": int(B.N), "n_elem": NT, "nnz": int(B.plan.nnz),
+            "ms_batched": t_batch * 1e3, "ms_plain_loop": t_plain * 1e3, "speedup": t_plain / t_batch,
+            "elements_per_s_batched": NT / t_batch, "iterations_max": int(max(it)),
+            "iterations_sum": int(sum(it)), "iterations_equal_plain": same, "grid": info["grid"],
+            "blocks_per_cu": info["blocks_per_cu"], "units_per_step": info["units_per_step"],
+            "cooperative_in_graph": bool(info["cooperative"]),
+            "autotune_ms": tune.get("ms")}
+
+
+def bench_adjoint(args):
+    """1025^2 mesh: forward solve vs forward + adjoint solve + gradient kernel."""
+    import numpy as np
+    import torch
+    from paper_1804_05156_amd import femhip, meshgen
+    log("[bench] adjoint: 1025^2 mesh")
+    m = meshgen.workload("jitter1025")
+    dev = torch.device("cuda:0")
+    node = torch.from_numpy(m.node).to(dev)
+    elem = torch.from_numpy(m.elem).to(dev)
+    bd = torch.from_numpy(m.bdflag).to(dev)
+    kap = torch.from_numpy(m.kappa).to(dev)
+    plan = femhip.Plan(node, elem, bd)
+    f = femhip.Fn(femhip.FE_FN_SINPROD, (2 * math.pi ** 2,))
+    rtol = 1e-10
+    kobs = torch.exp(torch.from_numpy(np.random.default_rng(55).standard_normal(m.n_elem)).to(dev))
+    u_obs = femhip.PoissonSolve.apply(kobs, plan, f, None, None, rtol).detach()
+    reps = max(1, min(args.steps, 3))
+
+    def forward():
+        return femhip.PoissonSolve.apply(kap, plan, f, None, None, rtol)
+
+    def forward_backward():
+        k = kap.clone().requires_grad_(True)
+        u = femhip.PoissonSolve.apply(k, plan, f, None, None, rtol)
+        J = 0.5 * torch.sum((u - u_obs) ** 2)
+        J.backward()
+        return k.grad
+
+    for fn in (forward, forward_backward):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        forward()
+    torch.cuda.synchronize()
+    t_f = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        forward_backward()
+    torch.cuda.synchronize()
+    t_fb = (time.perf_counter() - t0) / reps
+    # the gradient kernel alone
+    lam = torch.randn(m.n_node, dtype=torch.float64, device=dev)
+    u = forward().detach()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        plan.grad(u, lam)
+    e1.record()
+    e1.synchronize()
+    g_ms = e0.elapsed_time(e1) / 10
+    NT = m.n_elem
+    return {"workload": "1025^2 jittered mesh, lognormal kappa, u_obs from a second kappa, rtol 1e-10",
+            "ms_forward": t_f * 1e3, "ms_forward_adjoint_grad": t_fb * 1e3, "ratio": t_fb / t_f,
+            "ms_grad_kernel": g_ms, "grad_elements_per_s": NT / (g_ms * 1e-3),
+            "fd_equivalent_ms": 2 * NT * t_f * 1e3}
 
 
 def copy_calibration(mb):

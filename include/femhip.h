@@ -218,15 +218,17 @@ int fe_batch_solve_workspace_bytes(int64_t n, int32_t n_inst, size_t *bytes);
  * must not couple to other rows.  u: x0 on entry, solutions on return.  Instance k
  * stops when its recurrence residual drops to rtol times ||b_k||_2, or after maxit
  * iterations.  blocks_per_cu: workgroups per compute unit of the persistent grid
- * (0 picks a default; above what fits, FE_ELIMIT).  iters, relres: host arrays of
+ * (0 picks a default; above what fits, FE_ELIMIT); units_per_step: 256-row units
+ * each workgroup processes together (1, 2 or 4; 0 picks a default).  Neither
+ * changes any result bit.  iters, relres: host arrays of
  * n_inst (may be NULL).  ws: 256-byte aligned device workspace of at least the
  * queried size.  Synchronizes.  Returns FE_ENOCONV if an instance hit maxit,
  * FE_EINVAL for a non-positive diagonal entry, FE_ELIMIT if the device-wide wait
  * timed out (the grid was not co-resident). */
 int fe_batch_solve(int32_t n_inst, const int64_t *inst_row_off, const int32_t *rowptr,
                    const int32_t *colind, const double *val, const double *b, double *u,
-                   double rtol, int32_t maxit, int32_t blocks_per_cu, void *ws, size_t ws_bytes,
-                   int32_t *iters, double *relres, void *stream);
+                   double rtol, int32_t maxit, int32_t blocks_per_cu, int32_t units_per_step,
+                   void *ws, size_t ws_bytes, int32_t *iters, double *relres, void *stream);
 
 typedef struct fe_batch fe_batch;   /* opaque; refers to the caller's plan and workspace */
 
@@ -234,7 +236,7 @@ typedef struct fe_batch_info {
     int32_t n_inst, n_units;        /* instances; 256-row reduction units over all of them */
     int64_t n_rows;
     int32_t grid;                   /* workgroups of the persistent solve kernel */
-    int32_t blocks_per_cu, max_blocks_per_cu;
+    int32_t blocks_per_cu, max_blocks_per_cu, units_per_step;
     int32_t cooperative;            /* 1 if the captured solve launch is a cooperative launch */
     int32_t captures;               /* graph captures so far */
 } fe_batch_info;
@@ -245,12 +247,12 @@ typedef struct fe_batch_info {
  * with n = N.  The plan and ws stay owned by the caller and must outlive the batch.
  * Synchronizes (uploads the instance table). */
 int fe_batch_create(fe_plan *plan, int32_t n_inst, const int64_t *inst_node_off,
-                    int32_t blocks_per_cu, void *ws, size_t ws_bytes, fe_batch **batch,
-                    void *stream);
+                    int32_t blocks_per_cu, int32_t units_per_step, void *ws, size_t ws_bytes,
+                    fe_batch **batch, void *stream);
 
-/* Change the persistent grid (workgroups per compute unit, 0 = default); the next
+/* Change the persistent grid (as for fe_batch_solve, 0 = default); the next
  * fe_batch_assemble_solve captures a new graph. */
-int fe_batch_set_grid(fe_batch *batch, int32_t blocks_per_cu);
+int fe_batch_set_grid(fe_batch *batch, int32_t blocks_per_cu, int32_t units_per_step);
 
 int fe_batch_get_info(const fe_batch *batch, fe_batch_info *info);
 
@@ -268,6 +270,27 @@ int fe_batch_assemble_solve(fe_batch *batch, const double *node, const double *k
                             int32_t *iters, double *relres, void *stream);
 
 int fe_batch_destroy(fe_batch *batch);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (measurement support).
+ * ------------------------------------------------------------------------- */
+
+typedef struct fe_prof_entry {
+    char name[40];                  /* kernel name */
+    int64_t launches;
+    double total_ms, min_ms, max_ms;  /* per launch, from HIP events on the launch stream */
+} fe_prof_entry;
+
+/* Enable (on != 0) or disable timing and drop the records kept so far.  While
+ * enabled, each launch of the library's kernels is bracketed by two HIP events
+ * recorded on its stream (launches into a capturing stream are skipped).  Process
+ * wide; do not call it while another thread launches library work. */
+int fe_prof_enable(int on);
+
+/* Synchronize the recorded events, aggregate them by kernel name into out[0..cap)
+ * (*count receives the number of distinct kernels, which may exceed cap), and drop
+ * the records. */
+int fe_prof_read(fe_prof_entry *out, int32_t cap, int32_t *count);
 
 #ifdef __cplusplus
 }

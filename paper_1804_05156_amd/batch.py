@@ -21,7 +21,7 @@ class Batch:
     all None); all CUDA tensors.  Vertex labels of instance k are offset by
     ``node_off[k]`` in the union, element labels by ``elem_off[k]``."""
 
-    def __init__(self, nodes, elems, bdflags=None, blocks_per_cu: int = 0, stream=None):
+    def __init__(self, nodes, elems, bdflags=None, blocks_per_cu: int = 0, units_per_step: int = 0, stream=None):
         if not nodes or len(nodes) != len(elems):
             raise ValueError("need one elem array per node array")
         self.n_inst = len(nodes)
@@ -38,7 +38,8 @@ class Batch:
         self.N = self.plan.N
         self.ws = torch.empty(femhip.fe_batch_solve_workspace_bytes(self.N, self.n_inst), dtype=torch.uint8,
                               device=self.node.device)
-        self.handle = femhip.fe_batch_create(self.plan.handle, self.node_off, self.ws, blocks_per_cu, stream)
+        self.handle = femhip.fe_batch_create(self.plan.handle, self.node_off, self.ws, blocks_per_cu, units_per_step,
+                                             stream)
         dev = self.node.device
         nnz = max(self.plan.nnz, 1)
         # outputs live as long as the batch, so that repeated calls replay one graph
@@ -59,14 +60,14 @@ class Batch:
     def split(self, x):
         return [x[self.node_off[k]:self.node_off[k + 1]] for k in range(self.n_inst)]
 
-    def set_grid(self, blocks_per_cu: int):
-        femhip.fe_batch_set_grid(self.handle, blocks_per_cu)
+    def set_grid(self, blocks_per_cu: int, units_per_step: int = 0):
+        femhip.fe_batch_set_grid(self.handle, blocks_per_cu, units_per_step)
 
     def info(self) -> dict:
         return femhip.fe_batch_get_info(self.handle)
 
     def __del__(self):
-        if getattr(self, "handle", None) is not None and femhip._lib is not None:
+        if getattr(self, "handle", None) is not None and femhip is not None and femhip._lib is not None:
             femhip._lib.fe_batch_destroy(self.handle)
             self.handle = None
 
@@ -82,12 +83,17 @@ def _time_call(fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+# (workgroups per compute unit, 256-row units per workgroup step) tried by autotune
+CANDIDATES = ((4, 1), (6, 1), (2, 2), (4, 2), (4, 4), (2, 4))
+
+
 def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=100000, candidates=None,
-             reps: int = 1, cache_path: str | None = None) -> dict:
-    """Pick the persistent grid (workgroups per compute unit) of the batched solve by
-    timing whole graph launches of this batch; results are bitwise independent of
-    the choice.  With ``cache_path`` the choice is stored in a JSON file keyed by
-    device and batch shape and reused on later calls.  Returns the choice and the
+             reps: int = 1, cache_path: str | None = None, log=None) -> dict:
+    """Pick the persistent solve grid of the batch: workgroups per compute unit and
+    units processed together per workgroup, by timing whole graph launches of this
+    batch (results are bitwise independent of the choice).  A candidate the device
+    rejects is skipped.  With ``cache_path`` the choice is stored in a JSON file
+    keyed by device and batch shape and reused later.  Returns the choice and the
     measured times (ms per launch)."""
     info = batch.info()
     key = f"{torch.cuda.get_device_name()}|{info['n_inst']}|{info['n_rows']}|{batch.plan.nnz}|{rtol}"
@@ -96,18 +102,27 @@ def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=10
         with open(cache_path) as fh:
             cache = json.load(fh)
         if key in cache:
-            batch.set_grid(int(cache[key]["blocks_per_cu"]))
+            batch.set_grid(*cache[key]["grid"])
             return dict(cache[key], cached=True)
     hi = int(info["max_blocks_per_cu"])
-    cands = candidates or sorted({c for c in (1, 2, 3, 4, 6, 8) if c <= hi})
+    cands = [c for c in (candidates or CANDIDATES) if c[0] <= hi]
     times = {}
     for c in cands:
-        batch.set_grid(c)
-        batch.assemble_solve(kappa, f, gD, gN, rtol, maxit)          # capture + warm
-        times[c] = _time_call(lambda: batch.assemble_solve(kappa, f, gD, gN, rtol, maxit), reps)
+        try:
+            batch.set_grid(*c)
+            batch.assemble_solve(kappa, f, gD, gN, rtol, maxit)          # capture + warm
+            times[c] = _time_call(lambda: batch.assemble_solve(kappa, f, gD, gN, rtol, maxit), reps)
+        except femhip.FemhipError as e:
+            if log:
+                log(f"autotune: {c} rejected ({e})")
+            continue
+        if log:
+            log(f"autotune: blocks/CU {c[0]}, units/step {c[1]}: {times[c]:.2f} ms")
+    if not times:
+        raise RuntimeError("autotune: no candidate grid ran")
     best = min(times, key=times.get)
-    batch.set_grid(best)
-    out = {"blocks_per_cu": best, "ms": {str(k): v for k, v in times.items()}}
+    batch.set_grid(*best)
+    out = {"grid": list(best), "ms": {f"{k[0]}x{k[1]}": v for k, v in times.items()}}
     if cache_path:
         cache[key] = out
         with open(cache_path, "w") as fh:

@@ -438,8 +438,10 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
 template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream_t s)
 {
     const unsigned g = (unsigned)cdiv(A.N, BLOCK);
-    if (dim == 2) hipLaunchKernelGGL((k_assemble_2d<ROWCAP, BLOCK, 4>), dim3(g), dim3(BLOCK), 0, s, A);
-    else hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2>), dim3(g), dim3(BLOCK), 0, s, A);
+    if (dim == 2) FE_TIMED("k_assemble_2d", s,
+             hipLaunchKernelGGL((k_assemble_2d<ROWCAP, BLOCK, 4>), dim3(g), dim3(BLOCK), 0, s, A));
+    else FE_TIMED("k_assemble_3d", s,
+             hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2>), dim3(g), dim3(BLOCK), 0, s, A));
     return fe_launch_check();
 }
 
@@ -473,11 +475,13 @@ extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kapp
     const unsigned gg = (unsigned)cdiv(A.N, 256);
     const double *fnodal = (A.f.kind == FE_FN_NODAL) ? A.f.nodal : nullptr;
     if (plan->dim == 2)
-        hipLaunchKernelGGL(k_scatter_coords<2>, dim3(gg), dim3(256), 0, s, A.N, plan->piinv, node, plan->xyp, fnodal,
-                           plan->fp);
+        FE_TIMED("k_scatter_coords", s,
+                 hipLaunchKernelGGL(k_scatter_coords<2>, dim3(gg), dim3(256), 0, s, A.N, plan->piinv, node, plan->xyp, fnodal,
+                               plan->fp));
     else
-        hipLaunchKernelGGL(k_scatter_coords<3>, dim3(gg), dim3(256), 0, s, A.N, plan->piinv, node, plan->xyp, fnodal,
-                           plan->fp);
+        FE_TIMED("k_scatter_coords", s,
+                 hipLaunchKernelGGL(k_scatter_coords<3>, dim3(gg), dim3(256), 0, s, A.N, plan->piinv, node, plan->xyp, fnodal,
+                               plan->fp));
     int rc = fe_launch_check();
     if (rc) return rc;
     const int mr = plan->max_row;
@@ -485,8 +489,9 @@ extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kapp
     else if (mr <= 32) rc = launch<32, 128>(plan->dim, A, s);
     else rc = launch<64, 64>(plan->dim, A, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_values_to_label, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,
-                       (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,
-                       (const double *)plan->valp, val, val_bc, b, b_load, is_dirichlet);
+    FE_TIMED("k_values_to_label", s,
+             hipLaunchKernelGGL(k_values_to_label, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,
+                           (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,
+                           (const double *)plan->valp, val, val_bc, b, b_load, is_dirichlet));
     return fe_launch_check();
 }

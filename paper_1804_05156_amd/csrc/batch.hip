@@ -33,60 +33,94 @@ namespace {
 constexpr int BB = CG_UNIT;
 constexpr int32_t MAX_INST = 4096;
 
-enum { BS_RZ = 0, BS_RR, BS_BB, BS_ALPHA, BS_BETA, BS_TOL2, BS_COUNT = 8 };   // doubles per instance
-enum { BF_DONE = 0, BF_ITER, BF_TICKET, BF_BAD, BF_COUNT = 4 };                // ints per instance
-enum { BAR_COUNT = 0, BAR_GEN, BAR_ABORT, BAR_ACTIVE, BAR_WORDS = 8 };
+enum { BS_RR = 0, BS_BB, BS_COUNT = 2 };                 // doubles per instance (reported)
+enum { BF_DONE = 0, BF_ITER, BF_BAD, BF_COUNT = 4 };     // ints per instance
+// Barrier words: top-level count, generation, abort flag, running instances, then
+// one arrival counter per group of blocks (blocks b with b % NGROUP == g), each in
+// its own 256-byte line.
+constexpr int NGROUP = 8;
+enum { BAR_TOP = 0, BAR_GEN = 1, BAR_ABORT = 2, BAR_ACTIVE = 3, BAR_GROUP = 64, BAR_GSTRIDE = 64 };
+constexpr int BAR_WORDS = BAR_GROUP + NGROUP * BAR_GSTRIDE;
 
 struct BatchArgs {
-    int32_t n_inst;
+    int32_t n_inst, n_units;
     const int4 *inst;     // per instance: (first unit, unit count, first row, end row)
     const int32_t *rowptr, *colind;
     const double *val, *b;
     double *x, *r, *z, *p0, *p1, *q, *dinv;
-    double *part;         // 3 * total units
+    double *pq, *rz[2], *rr[2], *bbp;   // per-unit partial sums
     double *scal;         // BS_COUNT * n_inst
     int32_t *flag;        // BF_COUNT * n_inst
     uint32_t *bar;        // BAR_WORDS
-    int32_t n_units;
     double rtol;
     int32_t maxit;
     int64_t spin_limit;   // in s_memrealtime ticks (100 MHz)
 };
 
-FE_DEV uint32_t ld_acquire(const uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
+FE_DEV uint32_t ld_u32(const uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 FE_DEV int32_t ld_i32(const int32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-FE_DEV double ld_f64(const double *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-// Generation barrier over the whole grid with a bounded wait.  Every thread
-// publishes its own writes before the arrival and acquires after the release.
+// Device-wide barrier with a bounded wait.  Arrivals count first per group of
+// blocks, then the last block of each group counts at the top; only thread 0 of a
+// block issues the device-scope release and acquire (the block's other threads are
+// ordered through the workgroup barriers around it).
 FE_DEV void grid_barrier(uint32_t *bar, int64_t spin_limit)
 {
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t gen = ld_acquire(bar + BAR_GEN);
-        const uint32_t arrived = __hip_atomic_fetch_add(bar + BAR_COUNT, 1u, __ATOMIC_ACQ_REL,
-                                                        __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == gridDim.x - 1) {
-            __hip_atomic_store(bar + BAR_COUNT, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(bar + BAR_GEN, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t G = gridDim.x;
+        const uint32_t g = blockIdx.x % NGROUP;
+        const uint32_t ng = G / NGROUP + (g < G % NGROUP ? 1u : 0u);
+        const uint32_t ngroups = G < (uint32_t)NGROUP ? G : (uint32_t)NGROUP;
+        uint32_t *cnt = bar + BAR_GROUP + BAR_GSTRIDE * g;
+        const uint32_t gen = ld_u32(bar + BAR_GEN);
+        bool released = false;
+        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ng - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (__hip_atomic_fetch_add(bar + BAR_TOP, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                ngroups - 1) {
+                __hip_atomic_store(bar + BAR_TOP, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(bar + BAR_GEN, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
             const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-            while (ld_acquire(bar + BAR_GEN) == gen) {
-                if (ld_acquire(bar + BAR_ABORT)) break;
-                __builtin_amdgcn_s_sleep(2);
+            while (ld_u32(bar + BAR_GEN) == gen) {
+                if (ld_u32(bar + BAR_ABORT)) break;
+                __builtin_amdgcn_s_sleep(1);
                 if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > spin_limit) {
                     __hip_atomic_fetch_or(bar + BAR_ABORT, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    __threadfence();
+}
+
+// NV block sums at once, each with block_sum's wavefront tree and wave order, so each
+// result equals block_sum of that value.  Results valid in thread 0.
+template <int NV> FE_DEV void block_sum_n(double *v, double *lds)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+        if (lane == 0) lds[k * (BB / 64) + wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < BB / 64; ++w) s += lds[k * (BB / 64) + w];
+            v[k] = s;
+        }
+    __syncthreads();
 }
 
 // LDS list of running instances: ainst[j] = (instance, first unit, first row, end
@@ -124,8 +158,12 @@ FE_DEV void build_active(const BatchArgs &A, Active &L, int32_t *scan_lds)
     L.units = base;
 }
 
-// Virtual unit v -> running-instance slot j (largest j with pre[j] <= v).
-FE_DEV int32_t find_slot(const Active &L, int32_t v)
+struct Unit {
+    int32_t inst, u0, u, row0, row1, count;   // u0: the instance's first unit
+};
+
+// Virtual unit v (0 <= v < L.units) -> its instance and rows.
+FE_DEV Unit unit_of(const Active &L, int32_t v)
 {
     int32_t lo = 0, hi = L.nact - 1;
     while (lo < hi) {
@@ -133,172 +171,271 @@ FE_DEV int32_t find_slot(const Active &L, int32_t v)
         if (L.pre[mid] <= v) lo = mid;
         else hi = mid - 1;
     }
-    return lo;
-}
-
-struct Unit {
-    int32_t inst, u0, u, row0, row1, count;   // u0: the instance's first unit
-};
-
-FE_DEV Unit unit_of(const Active &L, int32_t v)
-{
-    const int32_t j = find_slot(L, v);
-    const int4 a = L.ainst[j];
-    const int32_t local = v - L.pre[j];
+    const int4 a = L.ainst[lo];
+    const int32_t local = v - L.pre[lo];
     Unit t;
     t.inst = a.x;
     t.u0 = a.y;
     t.u = a.y + local;
     t.row0 = a.z + local * BB;
     t.row1 = (a.w - t.row0 < BB) ? a.w : t.row0 + BB;
-    t.count = L.pre[j + 1] - L.pre[j];
+    t.count = L.pre[lo + 1] - L.pre[lo];
     return t;
 }
 
+// Sums over an instance's units of up to four partial arrays, each in the fixed
+// order of cg_sum_partials; broadcast to every thread through `bc`.
+template <int NV>
+FE_DEV void instance_sums(const double *const *arr, int32_t u0, int32_t count, double *lds, double *bc, double *out)
+{
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        v[k] = 0.0;
+        for (int32_t j = threadIdx.x; j < count; j += BB) v[k] += arr[k][u0 + j];
+    }
+    block_sum_n<NV>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) bc[k] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = bc[k];
+    __syncthreads();
+}
+
+// This block's contiguous share of the running units.
+FE_DEV void block_range(int32_t units, int32_t vb, int32_t *v0, int32_t *v1)
+{
+    const int32_t per = (int32_t)((units + gridDim.x - 1) / gridDim.x);
+    const int64_t a = (int64_t)vb * per;
+    *v0 = (int32_t)(a < units ? a : units);
+    *v1 = (*v0 + per < units) ? *v0 + per : units;
+}
+
+// Record the stopping state of instance k (one block per instance does this).
+FE_DEV void record(const BatchArgs &A, int32_t k, bool done, int32_t iters, double RR, double BBv)
+{
+    int32_t *fl = A.flag + BF_COUNT * k;
+    A.scal[BS_COUNT * k + BS_RR] = RR;
+    A.scal[BS_COUNT * k + BS_BB] = BBv;
+    fl[BF_ITER] = iters;
+    if (done) {
+        fl[BF_DONE] = 1;
+        __hip_atomic_fetch_sub(A.bar + BAR_ACTIVE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// K units per step: every thread owns row t of each of the K units, so K independent
+// row walks overlap their loads; reductions stay per unit.
+template <int K>
 __global__ __launch_bounds__(BB) void k_batch_pcg(BatchArgs A)
 {
     extern __shared__ int4 dyn[];
-    __shared__ double lds[BB / 64];
-    __shared__ int32_t scan_lds[2 * BB / 64];
-    __shared__ int s_stop;
+    __shared__ double lds[4 * K * (BB / 64)];
+    __shared__ double bc[4];
+    __shared__ int32_t scan_lds[2 * (BB / 64)];
+    __shared__ int32_t s_flag;
     Active L;
     L.ainst = dyn;
     L.pre = reinterpret_cast<int32_t *>(dyn + A.n_inst);
-    const int32_t U = A.n_units;
     const int32_t G = gridDim.x;
     // blocks b and b + 8 run on the same XCD: give each XCD a contiguous range of units
     const int32_t vb = (G % 8 == 0) ? (int32_t)(blockIdx.x % 8) * (G / 8) + (int32_t)(blockIdx.x / 8)
                                     : (int32_t)blockIdx.x;
+    const int tid = threadIdx.x;
+    uint32_t seen = 0;
+    if (tid == 0) seen = ld_u32(A.bar + BAR_ACTIVE);
     build_active(A, L, scan_lds);
-    // ---- initial residual, diagonal, z = r / diag, p_old = 0
-    for (int32_t v = vb; v < L.units; v += G) {
-        const Unit t = unit_of(L, v);
-        const int32_t i = t.row0 + threadIdx.x;
-        double rz = 0.0, rr = 0.0, bb = 0.0;
-        if (i < t.row1) {
-            double ri, d;
-            cg_init_row(i, A.rowptr, A.colind, A.val, A.b, A.x, &ri, &d);
-            if (!(d > 0.0)) atomicOr(A.flag + BF_COUNT * t.inst + BF_BAD, 1);
-            const double di = 1.0 / d;
-            A.dinv[i] = di;
-            A.r[i] = ri;
-            A.z[i] = ri * di;
-            A.p0[i] = 0.0;
-            rz = ri * ri * di;
-            rr = ri * ri;
-            bb = A.b[i] * A.b[i];
-        }
-        const double s0 = block_sum<BB>(rz, lds);
-        const double s1 = block_sum<BB>(rr, lds);
-        const double s2 = block_sum<BB>(bb, lds);
-        if (threadIdx.x == 0) {
-            A.part[t.u] = s0;
-            A.part[U + t.u] = s1;
-            A.part[2 * U + t.u] = s2;
-        }
-        if (cg_last_arrival(A.flag + BF_COUNT * t.inst + BF_TICKET, t.count)) {
-            const double RZ = cg_sum_partials(A.part + t.u0, t.count, lds);
-            const double RR = cg_sum_partials(A.part + U + t.u0, t.count, lds);
-            const double BBv = cg_sum_partials(A.part + 2 * U + t.u0, t.count, lds);
-            if (threadIdx.x == 0) {
-                double *sc = A.scal + BS_COUNT * t.inst;
-                int32_t *fl = A.flag + BF_COUNT * t.inst;
-                const double bn2 = BBv > 0.0 ? BBv : 1.0;
-                sc[BS_RZ] = RZ;
-                sc[BS_RR] = RR;
-                sc[BS_BB] = bn2;
-                sc[BS_TOL2] = A.rtol * A.rtol * bn2;
-                sc[BS_BETA] = 0.0;
-                sc[BS_ALPHA] = 0.0;
-                fl[BF_ITER] = 0;
-                if (RR <= A.rtol * A.rtol * bn2) {
-                    fl[BF_DONE] = 1;
-                    __hip_atomic_fetch_sub(A.bar + BAR_ACTIVE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+    int32_t v0, v1;
+    block_range(L.units, vb, &v0, &v1);
+
+    // ---- r = b - A x, diag, z = r / diag, p_old = 0; partials r.z, r.r, b.b
+    for (int32_t v = v0; v < v1; v += K) {
+        Unit t[K];
+        double red[3 * K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            red[3 * j] = red[3 * j + 1] = red[3 * j + 2] = 0.0;
+            if (v + j >= v1) continue;
+            t[j] = unit_of(L, v + j);
+            const int32_t i = t[j].row0 + tid;
+            if (i < t[j].row1) {
+                double ri, d;
+                cg_init_row(i, A.rowptr, A.colind, A.val, A.b, A.x, &ri, &d);
+                if (!(d > 0.0)) atomicOr(A.flag + BF_COUNT * t[j].inst + BF_BAD, 1);
+                const double di = 1.0 / d;
+                A.dinv[i] = di;
+                A.r[i] = ri;
+                A.z[i] = ri * di;
+                A.p0[i] = 0.0;
+                red[3 * j] = ri * ri * di;
+                red[3 * j + 1] = ri * ri;
+                red[3 * j + 2] = A.b[i] * A.b[i];
             }
         }
+        block_sum_n<3 * K>(red, lds);
+        if (tid == 0)
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if (v + j < v1) {
+                    A.rz[0][t[j].u] = red[3 * j];
+                    A.rr[0][t[j].u] = red[3 * j + 1];
+                    A.bbp[t[j].u] = red[3 * j + 2];
+                }
     }
     grid_barrier(A.bar, A.spin_limit);
-    uint32_t seen = 0xffffffffu;
-    for (int32_t it = 0; it < A.maxit; ++it) {
-        if (threadIdx.x == 0) {
-            const uint32_t act = ld_acquire(A.bar + BAR_ACTIVE);
-            s_stop = ld_acquire(A.bar + BAR_ABORT) ? 2 : (act == 0 ? 1 : 0);
-            if (act != seen) s_stop |= 4;
+
+    int32_t it = 0;
+    for (; it < A.maxit; ++it) {
+        if (tid == 0) {
+            const uint32_t act = ld_u32(A.bar + BAR_ACTIVE);
+            s_flag = (ld_u32(A.bar + BAR_ABORT) ? 2 : 0) | (act == 0 ? 1 : 0) | (act != seen ? 4 : 0);
             seen = act;
         }
         __syncthreads();
-        const int stop = s_stop;
+        const int32_t fl = s_flag;
         __syncthreads();
-        if (stop & 3) break;
-        if (stop & 4) build_active(A, L, scan_lds);
-        const double *pold = (it & 1) ? A.p1 : A.p0;
-        double *pnew = (it & 1) ? A.p0 : A.p1;
-        // ---- phase A
-        for (int32_t v = vb; v < L.units; v += G) {
-            const Unit t = unit_of(L, v);
-            const double beta = ld_f64(A.scal + BS_COUNT * t.inst + BS_BETA);
-            const int32_t i = t.row0 + threadIdx.x;
-            double pq = 0.0;
-            if (i < t.row1) {
-                const double s = cg_apply_row(i, A.rowptr, A.colind, A.val, A.z, pold, beta);
-                const double pi = A.z[i] + beta * pold[i];
-                pnew[i] = pi;
-                A.q[i] = s;
-                pq = pi * s;
+        if (fl & 3) break;
+        if (fl & 4) {
+            build_active(A, L, scan_lds);
+            block_range(L.units, vb, &v0, &v1);
+        }
+        const int cur = it & 1;
+        const double *pold = cur ? A.p1 : A.p0;
+        double *pnew = cur ? A.p0 : A.p1;
+        // ---- phase A: stopping test and beta per instance; p = z + beta p_old, q = A p
+        int32_t ci = -1;
+        double c_beta = 0.0;
+        bool c_done = false;
+        for (int32_t v = v0; v < v1; v += K) {
+            Unit t[K];
+            bool ok[K];
+            double beta[K];
+            int32_t rows[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                ok[j] = false;
+                beta[j] = 0.0;
+                rows[j] = 0;
+                if (v + j >= v1) continue;
+                t[j] = unit_of(L, v + j);
+                if (t[j].inst != ci) {
+                    const double *arr[4] = {A.rz[cur], A.rr[cur], A.bbp, A.rz[cur ^ 1]};
+                    double S[4];
+                    instance_sums<4>(arr, t[j].u0, t[j].count, lds, bc, S);
+                    const double bn2 = S[2] > 0.0 ? S[2] : 1.0;
+                    ci = t[j].inst;
+                    c_done = S[1] <= A.rtol * A.rtol * bn2;
+                    c_beta = it == 0 ? 0.0 : S[0] / S[3];
+                    // the block holding the instance's first unit records the result
+                    if (c_done && tid == 0 && t[j].u == t[j].u0) record(A, ci, true, it, S[1], bn2);
+                }
+                rows[j] = t[j].row0 + tid;
+                ok[j] = !c_done && rows[j] < t[j].row1;
+                beta[j] = c_beta;
+                if (c_done) t[j].count = 0;   // mark: no partial for this slot
             }
-            const double bs = block_sum<BB>(pq, lds);
-            if (threadIdx.x == 0) A.part[t.u] = bs;
-            if (cg_last_arrival(A.flag + BF_COUNT * t.inst + BF_TICKET, t.count)) {
-                const double PQ = cg_sum_partials(A.part + t.u0, t.count, lds);
-                if (threadIdx.x == 0) {
-                    double *sc = A.scal + BS_COUNT * t.inst;
-                    sc[BS_ALPHA] = sc[BS_RZ] / PQ;
+            double s[K];
+            cg_apply_rows<K>(rows, ok, A.rowptr, A.colind, A.val, A.z, pold, beta, s);
+            double red[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                red[j] = 0.0;
+                if (ok[j]) {
+                    const int32_t i = rows[j];
+                    const double pi = A.z[i] + beta[j] * pold[i];
+                    pnew[i] = pi;
+                    A.q[i] = s[j];
+                    red[j] = pi * s[j];
                 }
             }
+            block_sum_n<K>(red, lds);
+            if (tid == 0)
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if (v + j < v1 && t[j].count > 0) A.pq[t[j].u] = red[j];
         }
         grid_barrier(A.bar, A.spin_limit);
-        if (ld_acquire(A.bar + BAR_ABORT)) break;
-        // ---- phase B
-        for (int32_t v = vb; v < L.units; v += G) {
-            const Unit t = unit_of(L, v);
-            const double alpha = ld_f64(A.scal + BS_COUNT * t.inst + BS_ALPHA);
-            const int32_t i = t.row0 + threadIdx.x;
-            double rz = 0.0, rr = 0.0;
-            if (i < t.row1) {
-                A.x[i] += alpha * pnew[i];
-                const double ri = A.r[i] - alpha * A.q[i];
-                const double zi = ri * A.dinv[i];
-                A.r[i] = ri;
-                A.z[i] = zi;
-                rz = ri * zi;
-                rr = ri * ri;
-            }
-            const double s0 = block_sum<BB>(rz, lds);
-            const double s1 = block_sum<BB>(rr, lds);
-            if (threadIdx.x == 0) {
-                A.part[U + t.u] = s0;
-                A.part[2 * U + t.u] = s1;
-            }
-            if (cg_last_arrival(A.flag + BF_COUNT * t.inst + BF_TICKET, t.count)) {
-                const double RZ = cg_sum_partials(A.part + U + t.u0, t.count, lds);
-                const double RR = cg_sum_partials(A.part + 2 * U + t.u0, t.count, lds);
-                if (threadIdx.x == 0) {
-                    double *sc = A.scal + BS_COUNT * t.inst;
-                    int32_t *fl = A.flag + BF_COUNT * t.inst;
-                    sc[BS_BETA] = RZ / sc[BS_RZ];
-                    sc[BS_RZ] = RZ;
-                    sc[BS_RR] = RR;
-                    fl[BF_ITER] += 1;
-                    if (RR <= sc[BS_TOL2]) {
-                        fl[BF_DONE] = 1;
-                        __hip_atomic_fetch_sub(A.bar + BAR_ACTIVE, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ld_u32(A.bar + BAR_ABORT)) break;
+        // ---- phase B: alpha per instance; x += alpha p, r -= alpha q, z = r / diag
+        ci = -1;
+        double c_alpha = 0.0;
+        c_done = false;
+        for (int32_t v = v0; v < v1; v += K) {
+            Unit t[K];
+            bool ok[K];
+            double alpha[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                ok[j] = false;
+                alpha[j] = 0.0;
+                if (v + j >= v1) continue;
+                t[j] = unit_of(L, v + j);
+                if (t[j].inst != ci) {
+                    ci = t[j].inst;
+                    c_done = ld_i32(A.flag + BF_COUNT * ci + BF_DONE) != 0;
+                    if (!c_done) {
+                        const double *arr[2] = {A.pq, A.rz[cur]};
+                        double S[2];
+                        instance_sums<2>(arr, t[j].u0, t[j].count, lds, bc, S);
+                        c_alpha = S[1] / S[0];
                     }
                 }
+                ok[j] = !c_done && t[j].row0 + tid < t[j].row1;
+                alpha[j] = c_alpha;
+                if (c_done) t[j].count = 0;
             }
+            double red[2 * K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                red[2 * j] = red[2 * j + 1] = 0.0;
+                if (ok[j]) {
+                    const int32_t i = t[j].row0 + tid;
+                    A.x[i] += alpha[j] * pnew[i];
+                    const double ri = A.r[i] - alpha[j] * A.q[i];
+                    const double zi = ri * A.dinv[i];
+                    A.r[i] = ri;
+                    A.z[i] = zi;
+                    red[2 * j] = ri * zi;
+                    red[2 * j + 1] = ri * ri;
+                }
+            }
+            block_sum_n<2 * K>(red, lds);
+            if (tid == 0)
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if (v + j < v1 && t[j].count > 0) {
+                        A.rz[cur ^ 1][t[j].u] = red[2 * j];
+                        A.rr[cur ^ 1][t[j].u] = red[2 * j + 1];
+                    }
         }
         grid_barrier(A.bar, A.spin_limit);
-        if (ld_acquire(A.bar + BAR_ABORT)) break;
+        if (ld_u32(A.bar + BAR_ABORT)) break;
+    }
+    // ---- iteration limit reached: final stopping test of the instances still running
+    if (it == A.maxit && !ld_u32(A.bar + BAR_ABORT)) {
+        if (tid == 0) {
+            const uint32_t act = ld_u32(A.bar + BAR_ACTIVE);
+            s_flag = act != seen ? 4 : 0;
+        }
+        __syncthreads();
+        const int32_t fl = s_flag;
+        __syncthreads();
+        if (fl & 4) {
+            build_active(A, L, scan_lds);
+            block_range(L.units, vb, &v0, &v1);
+        }
+        const int cur = it & 1;
+        for (int32_t v = v0; v < v1; ++v) {
+            const Unit t = unit_of(L, v);
+            if (t.u != t.u0) continue;
+            const double *arr[2] = {A.rr[cur], A.bbp};
+            double S[2];
+            instance_sums<2>(arr, t.u0, t.count, lds, bc, S);
+            const double bn2 = S[1] > 0.0 ? S[1] : 1.0;
+            if (tid == 0) record(A, t.inst, S[0] <= A.rtol * A.rtol * bn2, it, S[0], bn2);
+        }
     }
 }
 
@@ -319,6 +456,8 @@ struct BatchWs {
     uint8_t *isd;         // Dirichlet mask of the graph path
 };
 
+constexpr int NPART = 6;   // pq, rz[2], rr[2], bb
+
 int64_t max_units(int64_t n, int32_t n_inst) { return n / CG_UNIT + n_inst; }
 
 size_t batch_layout(int64_t n, int32_t n_inst, BatchWs *w, char *base)
@@ -331,7 +470,7 @@ size_t batch_layout(int64_t n, int32_t n_inst, BatchWs *w, char *base)
         return base ? base + at : nullptr;
     };
     char *r = take(8 * (size_t)n), *z = take(8 * (size_t)n), *p0 = take(8 * (size_t)n), *p1 = take(8 * (size_t)n),
-         *q = take(8 * (size_t)n), *d = take(8 * (size_t)n), *part = take(8 * 3 * (size_t)U),
+         *q = take(8 * (size_t)n), *d = take(8 * (size_t)n), *part = take(8 * NPART * (size_t)U),
          *scal = take(8 * BS_COUNT * (size_t)n_inst), *flag = take(4 * BF_COUNT * (size_t)n_inst),
          *bar = take(4 * BAR_WORDS), *inst = take(16 * (size_t)n_inst), *isd = take((size_t)n);
     if (w) {
@@ -344,11 +483,20 @@ size_t batch_layout(int64_t n, int32_t n_inst, BatchWs *w, char *base)
 
 size_t dyn_lds_bytes(int32_t n_inst) { return 16 * (size_t)n_inst + 4 * ((size_t)n_inst + 1); }
 
+const void *pcg_kernel(int K)
+{
+    switch (K) {
+    case 1: return reinterpret_cast<const void *>(&k_batch_pcg<1>);
+    case 2: return reinterpret_cast<const void *>(&k_batch_pcg<2>);
+    default: return reinterpret_cast<const void *>(&k_batch_pcg<4>);
+    }
+}
+
 }  // namespace
 
 // Host side of one batched solve: the instance table, the grid, the launch.
 struct fe_batch_solver {
-    int32_t n_inst = 0, n_units = 0, grid = 0, blocks_per_cu = 0, max_per_cu = 0;
+    int32_t n_inst = 0, n_units = 0, grid = 0, blocks_per_cu = 0, max_per_cu = 0, units_per_step = 0;
     int64_t n = 0;
     size_t lds = 0;
     BatchWs W{};
@@ -356,17 +504,21 @@ struct fe_batch_solver {
     uint32_t active = 0;
 };
 
-static int batch_set_grid(fe_batch_solver *S, int32_t blocks_per_cu)
+// Grid of the persistent kernel: blocks_per_cu workgroups per compute unit (0: 2)
+// and units_per_step units processed together by each workgroup (1, 2 or 4; 0: 2).
+static int batch_set_grid(fe_batch_solver *S, int32_t blocks_per_cu, int32_t units_per_step)
 {
     if (blocks_per_cu < 0) return FE_EINVAL;
+    if (units_per_step == 0) units_per_step = 2;
+    if (units_per_step != 1 && units_per_step != 2 && units_per_step != 4) return FE_EINVAL;
     int dev = 0, cus = 0, per = 0;
     FE_HIP_CHECK(hipGetDevice(&dev));
     FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void *>(&k_batch_pcg), BB,
-                                                              S->lds));
+    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel(units_per_step), BB, S->lds));
     if (per < 1) return FE_ELIMIT;
     S->max_per_cu = per;
-    int32_t want = blocks_per_cu ? blocks_per_cu : (per < 4 ? per : 4);
+    S->units_per_step = units_per_step;
+    int32_t want = blocks_per_cu ? blocks_per_cu : (per < 2 ? per : 2);
     if (want > per) return FE_ELIMIT;
     int64_t g = (int64_t)cus * want;
     if (g > S->n_units) g = S->n_units;
@@ -376,7 +528,7 @@ static int batch_set_grid(fe_batch_solver *S, int32_t blocks_per_cu)
 }
 
 static int batch_prepare(fe_batch_solver *S, int32_t n_inst, const int64_t *off, void *ws, size_t ws_bytes,
-                         int32_t blocks_per_cu)
+                         int32_t blocks_per_cu, int32_t units_per_step)
 {
     if (n_inst <= 0 || n_inst > MAX_INST || !off || !ws) return n_inst > MAX_INST ? FE_ELIMIT : FE_EINVAL;
     const int64_t n = off[n_inst];
@@ -400,7 +552,7 @@ static int batch_prepare(fe_batch_solver *S, int32_t n_inst, const int64_t *off,
     }
     S->n_units = units;
     S->lds = dyn_lds_bytes(n_inst);
-    return batch_set_grid(S, blocks_per_cu);
+    return batch_set_grid(S, blocks_per_cu, units_per_step);
 }
 
 static int batch_upload(fe_batch_solver *S, hipStream_t s)
@@ -414,8 +566,9 @@ static int batch_enqueue(fe_batch_solver *S, const int32_t *rowptr, const int32_
                          const double *b, double *u, double rtol, int32_t maxit, hipStream_t s, bool cooperative)
 {
     const int32_t nfill = BF_COUNT * S->n_inst > BAR_WORDS ? BF_COUNT * S->n_inst : BAR_WORDS;
-    hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)cdiv(nfill, 256)), dim3(256), 0, s, S->W.bar, S->W.flag,
-                       S->n_inst, S->active);
+    FE_TIMED("k_batch_reset", s,
+             hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)cdiv(nfill, 256)), dim3(256), 0, s, S->W.bar, S->W.flag,
+                           S->n_inst, S->active));
     FE_HIP_CHECK(hipGetLastError());
     BatchArgs A{};
     A.n_inst = S->n_inst;
@@ -431,7 +584,13 @@ static int batch_enqueue(fe_batch_solver *S, const int32_t *rowptr, const int32_
     A.p1 = S->W.p1;
     A.q = S->W.q;
     A.dinv = S->W.dinv;
-    A.part = S->W.part;
+    const int64_t U = S->n_units;
+    A.pq = S->W.part;
+    A.rz[0] = S->W.part + U;
+    A.rz[1] = S->W.part + 2 * U;
+    A.rr[0] = S->W.part + 3 * U;
+    A.rr[1] = S->W.part + 4 * U;
+    A.bbp = S->W.part + 5 * U;
     A.scal = S->W.scal;
     A.flag = S->W.flag;
     A.bar = S->W.bar;
@@ -441,11 +600,18 @@ static int batch_enqueue(fe_batch_solver *S, const int32_t *rowptr, const int32_
     A.spin_limit = 500000000;   // 5 s at 100 MHz
     if (cooperative) {
         void *args[] = {&A};
-        FE_HIP_CHECK(hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_batch_pcg),
-                                                dim3((unsigned)S->grid), dim3(BB), args, (unsigned)S->lds, s));
+        hipError_t e = hipSuccess;
+        FE_TIMED("k_batch_pcg", s,
+                 e = hipLaunchCooperativeKernel(pcg_kernel(S->units_per_step), dim3((unsigned)S->grid), dim3(BB),
+                                                args, (unsigned)S->lds, s));
+        if (e != hipSuccess) return FE_EHIP;
     } else {
-        hipLaunchKernelGGL(k_batch_pcg, dim3((unsigned)S->grid), dim3(BB), S->lds, s, A);
-        FE_HIP_CHECK(hipGetLastError());
+        void *args[] = {&A};
+        hipError_t e = hipSuccess;
+        FE_TIMED("k_batch_pcg", s,
+                 e = hipLaunchKernel(pcg_kernel(S->units_per_step), dim3((unsigned)S->grid), dim3(BB), args,
+                                     S->lds, s));
+        if (e != hipSuccess) return FE_EHIP;
     }
     return FE_OK;
 }
@@ -484,12 +650,12 @@ extern "C" int fe_batch_solve_workspace_bytes(int64_t n, int32_t n_inst, size_t 
 
 extern "C" int fe_batch_solve(int32_t n_inst, const int64_t *inst_row_off, const int32_t *rowptr,
                               const int32_t *colind, const double *val, const double *b, double *u, double rtol,
-                              int32_t maxit, int32_t blocks_per_cu, void *ws, size_t ws_bytes, int32_t *iters,
-                              double *relres, void *stream)
+                              int32_t maxit, int32_t blocks_per_cu, int32_t units_per_step, void *ws,
+                              size_t ws_bytes, int32_t *iters, double *relres, void *stream)
 {
     if (!rowptr || !colind || !val || !b || !u || maxit < 0 || !(rtol >= 0.0)) return FE_EINVAL;
     fe_batch_solver S;
-    int rc = batch_prepare(&S, n_inst, inst_row_off, ws, ws_bytes, blocks_per_cu);
+    int rc = batch_prepare(&S, n_inst, inst_row_off, ws, ws_bytes, blocks_per_cu, units_per_step);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = batch_upload(&S, s))) return rc;
@@ -562,13 +728,13 @@ static int capture(fe_batch *B, const double *node, const double *kappa, const f
 }
 
 extern "C" int fe_batch_create(fe_plan *plan, int32_t n_inst, const int64_t *inst_node_off, int32_t blocks_per_cu,
-                               void *ws, size_t ws_bytes, fe_batch **out, void *stream)
+                               int32_t units_per_step, void *ws, size_t ws_bytes, fe_batch **out, void *stream)
 {
     if (!plan || !out || !inst_node_off || n_inst <= 0) return FE_EINVAL;
     if (inst_node_off[n_inst] != plan->N) return FE_EINVAL;
     fe_batch *B = new (std::nothrow) fe_batch();
     if (!B) return FE_EINVAL;
-    int rc = batch_prepare(&B->S, n_inst, inst_node_off, ws, ws_bytes, blocks_per_cu);
+    int rc = batch_prepare(&B->S, n_inst, inst_node_off, ws, ws_bytes, blocks_per_cu, units_per_step);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (rc == FE_OK) rc = batch_upload(&B->S, s);
     if (rc == FE_OK && hipStreamSynchronize(s) != hipSuccess) rc = FE_EHIP;
@@ -581,13 +747,13 @@ extern "C" int fe_batch_create(fe_plan *plan, int32_t n_inst, const int64_t *ins
     return FE_OK;
 }
 
-extern "C" int fe_batch_set_grid(fe_batch *B, int32_t blocks_per_cu)
+extern "C" int fe_batch_set_grid(fe_batch *B, int32_t blocks_per_cu, int32_t units_per_step)
 {
     if (!B) return FE_EINVAL;
-    const int32_t old = B->S.blocks_per_cu;
-    int rc = batch_set_grid(&B->S, blocks_per_cu);
+    const int32_t old = B->S.blocks_per_cu, oldk = B->S.units_per_step;
+    int rc = batch_set_grid(&B->S, blocks_per_cu, units_per_step);
     if (rc) {
-        batch_set_grid(&B->S, old);
+        batch_set_grid(&B->S, old, oldk);
         return rc;
     }
     drop_graph(B);
@@ -602,6 +768,7 @@ extern "C" int fe_batch_get_info(const fe_batch *B, fe_batch_info *info)
     info->n_rows = B->S.n;
     info->grid = B->S.grid;
     info->blocks_per_cu = B->S.blocks_per_cu;
+    info->units_per_step = B->S.units_per_step;
     info->max_blocks_per_cu = B->S.max_per_cu;
     info->cooperative = B->cooperative;
     info->captures = B->captures;

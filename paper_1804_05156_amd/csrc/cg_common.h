@@ -23,17 +23,31 @@ FE_DEV void cg_init_row(int32_t i, const int32_t *__restrict__ rowptr, const int
     *ri = b[i] - s;
 }
 
-// (A p_new)_i with p_new = z + beta p_old formed on the fly.
-FE_DEV double cg_apply_row(int32_t i, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
-                           const double *__restrict__ val, const double *__restrict__ z,
-                           const double *__restrict__ pold, double beta)
+// s[j] = (A p_new)_{i[j]} with p_new = z + beta[j] p_old formed on the fly, for K rows
+// at once (rows with ok[j] false are skipped).  The K rows are walked in lockstep so
+// that their loads overlap; each row is summed in its own column order.
+template <int K>
+FE_DEV void cg_apply_rows(const int32_t *i, const bool *ok, const int32_t *__restrict__ rowptr,
+                          const int32_t *__restrict__ colind, const double *__restrict__ val,
+                          const double *__restrict__ z, const double *__restrict__ pold, const double *beta, double *s)
 {
-    double s = 0.0;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
-        const int32_t c = colind[q];
-        s += val[q] * (z[c] + beta * pold[c]);
+    int32_t q[K], e[K];
+    int32_t len = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        s[j] = 0.0;
+        q[j] = ok[j] ? rowptr[i[j]] : 0;
+        e[j] = ok[j] ? rowptr[i[j] + 1] : 0;
+        len = max(len, e[j] - q[j]);
     }
-    return s;
+    for (int32_t m = 0; m < len; ++m) {
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (q[j] + m < e[j]) {
+                const int32_t c = colind[q[j] + m];
+                s[j] += val[q[j] + m] * (z[c] + beta[j] * pold[c]);
+            }
+    }
 }
 
 // Sum of part[0..nb) in a fixed order: thread t adds part[t], part[t+256], ...,
@@ -46,19 +60,18 @@ FE_DEV double cg_sum_partials(const double *part, int32_t nb, double *lds)
 }
 
 // True in every thread of the block that arrives last at `ticket` among `count`
-// arrivals; it then sees every partial written before the other arrivals.  The
-// last block resets the ticket.
+// arrivals.  Only thread 0's writes (the block's partial sums) are published by the
+// arrival, and the last block then sees every other block's partials.  The last
+// block resets the ticket.
 FE_DEV bool cg_last_arrival(int32_t *ticket, int32_t count)
 {
     __shared__ int is_last;
-    __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int32_t prev = atomicAdd(ticket, 1);
+        const int32_t prev = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         is_last = (prev == count - 1);
-        if (is_last) *ticket = 0;
+        if (is_last) __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    if (is_last) __threadfence();
     return is_last != 0;
 }

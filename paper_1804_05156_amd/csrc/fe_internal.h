@@ -237,6 +237,17 @@ static inline int fe_launch_check()
     return hipGetLastError() == hipSuccess ? FE_OK : FE_EHIP;
 }
 
+// Optional per-kernel event timing (prof.hip): FE_TIMED(name, stream, launch...)
+// brackets one launch with events on its stream when timing is enabled.
+int fe_prof_begin(const char *name, hipStream_t s);
+void fe_prof_end(int tok, hipStream_t s);
+#define FE_TIMED(name, stream, ...)                          \
+    do {                                                     \
+        const int fe_prof_tok_ = fe_prof_begin(name, stream); \
+        __VA_ARGS__;                                         \
+        fe_prof_end(fe_prof_tok_, stream);                   \
+    } while (0)
+
 static inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 

@@ -103,10 +103,12 @@ extern "C" int fe_grad(fe_plan *plan, const double *node, const double *u, const
     const unsigned nb = (unsigned)cdiv(plan->NT, GB);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (plan->dim == 2)
-        hipLaunchKernelGGL(k_grad_2d, dim3(nb), dim3(GB), 0, s, (int32_t)plan->N, (int32_t)plan->NT, plan->elem, node,
-                           u, lam, g, plan->status);
+        FE_TIMED("k_grad_2d", s,
+                 hipLaunchKernelGGL(k_grad_2d, dim3(nb), dim3(GB), 0, s, (int32_t)plan->N, (int32_t)plan->NT, plan->elem, node,
+                               u, lam, g, plan->status));
     else
-        hipLaunchKernelGGL(k_grad_3d, dim3(nb), dim3(GB), 0, s, (int32_t)plan->N, (int32_t)plan->NT, plan->elem, node,
-                           u, lam, g, plan->status);
+        FE_TIMED("k_grad_3d", s,
+                 hipLaunchKernelGGL(k_grad_3d, dim3(nb), dim3(GB), 0, s, (int32_t)plan->N, (int32_t)plan->NT, plan->elem, node,
+                               u, lam, g, plan->status));
     return fe_launch_check();
 }

@@ -739,8 +739,9 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     if ((rc = fe_fill_u8(P->ownf, P->ninc, 0, s))) return rc;
     if ((rc = fe_fill_i32(reinterpret_cast<int32_t *>(P->vinfo), 2 * (int64_t)N, 0, s))) return rc;
     if (NT > 0)
-        hipLaunchKernelGGL(k_l1_hist<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, P->bdflag, NT, N,
-                           P->bs, P->ncb, P->nblk1, P->hist1, P->isd, P->status);
+        FE_TIMED("k_l1_hist", s,
+                 hipLaunchKernelGGL(k_l1_hist<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, P->bdflag, NT, N,
+                               P->bs, P->ncb, P->nblk1, P->hist1, P->isd, P->status));
     if ((rc = fe_launch_check())) return rc;
     // Vertex indices are validated by the histogram kernel only: stop here, before
     // any kernel uses elem entries as addresses, if one was out of range.
@@ -750,10 +751,12 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     if (err) return fe_status_from_bits(err);
     if (NT > 0) {
         if ((rc = fe_scan_exclusive(P->hist1, P->hist1, nh, P->totals + 4, P->part, P->status, s))) return rc;
-        hipLaunchKernelGGL(k_l1_scatter<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, NT, P->bs,
-                           P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs);
-        hipLaunchKernelGGL(k_l1_fine, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
-                           (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs, P->pairs2, P->fstart);
+        FE_TIMED("k_l1_scatter", s,
+                 hipLaunchKernelGGL(k_l1_scatter<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, NT, P->bs,
+                               P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
+        FE_TIMED("k_l1_fine", s,
+                 hipLaunchKernelGGL(k_l1_fine, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
+                               (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs, P->pairs2, P->fstart));
         // LDS capacity per bucket: twice the average bucket, at least 2048 keys
         int64_t cap = cdiv(2 * P->ninc, P->nb);
         cap = cdiv(cap, 1024) * 1024;
@@ -762,33 +765,41 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         const size_t lds = sizeof(int32_t) * ((size_t)cap + 2 * ((size_t)1 << P->bs));
         FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_l2_bucket),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        hipLaunchKernelGGL(k_l2_bucket, dim3((unsigned)P->nb), dim3(BKB), lds, s, N, P->bs, (int32_t)cap,
-                           (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd, P->sorted_l,
-                           P->vinfo, P->ownf);
-        hipLaunchKernelGGL(k_l2_bucket_global, dim3((unsigned)P->nb), dim3(BKB), 0, s, N, P->bs, (int32_t)cap,
-                           (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd,
-                           P->sorted_l, P->vinfo, P->rowlen, P->prowptr, P->ownf);
-        hipLaunchKernelGGL(k_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, (const uint8_t *)P->ownf, P->owncnt);
+        FE_TIMED("k_l2_bucket", s,
+                 hipLaunchKernelGGL(k_l2_bucket, dim3((unsigned)P->nb), dim3(BKB), lds, s, N, P->bs, (int32_t)cap,
+                               (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd, P->sorted_l,
+                               P->vinfo, P->ownf));
+        FE_TIMED("k_l2_bucket_global", s,
+                 hipLaunchKernelGGL(k_l2_bucket_global, dim3((unsigned)P->nb), dim3(BKB), 0, s, N, P->bs, (int32_t)cap,
+                               (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd,
+                               P->sorted_l, P->vinfo, P->rowlen, P->prowptr, P->ownf));
+        FE_TIMED("k_own_count", s,
+                 hipLaunchKernelGGL(k_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, (const uint8_t *)P->ownf, P->owncnt));
         if ((rc = fe_launch_check())) return rc;
     }
     if ((rc = fe_scan_exclusive(P->owncnt, P->owncnt, NT, P->totals + 0, P->part, P->status, s))) return rc;
     if (NT > 0)
-        hipLaunchKernelGGL(k_pi<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, (const uint8_t *)P->ownf,
-                           (const int32_t *)P->owncnt, (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp,
-                           P->isdp);
-    hipLaunchKernelGGL(k_unused, dim3(ng), dim3(EBLOCK), 0, s, N, (const int2 *)P->vinfo,
-                       (const int64_t *)(P->totals + 0), P->pi, P->piinv, P->pincptr, P->inclp, P->isdp, P->status);
+        FE_TIMED("k_pi", s,
+                 hipLaunchKernelGGL(k_pi<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, (const uint8_t *)P->ownf,
+                               (const int32_t *)P->owncnt, (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp,
+                               P->isdp));
+    FE_TIMED("k_unused", s,
+             hipLaunchKernelGGL(k_unused, dim3(ng), dim3(EBLOCK), 0, s, N, (const int2 *)P->vinfo,
+                           (const int64_t *)(P->totals + 0), P->pi, P->piinv, P->pincptr, P->inclp, P->isdp, P->status));
     if ((rc = fe_launch_check())) return rc;
     if ((rc = fe_scan_exclusive(P->pincptr, P->pincptr, N, P->totals + 1, P->part, P->status, s))) return rc;
     constexpr int RB = RowCaps<NV>::BLOCK;
     const RowArgs R = row_args(P);
-    hipLaunchKernelGGL((k_rows<NV, false>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R);
+    FE_TIMED("k_rows_count", s,
+             hipLaunchKernelGGL((k_rows<NV, false>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R));
     if ((rc = fe_launch_check())) return rc;
     if ((rc = fe_scan_exclusive(P->prowptr, P->prowptr, N, P->totals + 2, P->part, P->status, s))) return rc;
     const unsigned sb = (unsigned)cdiv(N, STB);
-    hipLaunchKernelGGL(k_stats_partial, dim3(sb), dim3(STB), 0, s, N, (const int32_t *)P->prowptr,
-                       (const int32_t *)P->pincptr, (const uint8_t *)P->isdp, P->stat_part);
-    hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STB), 0, s, (int32_t)sb, (const int64_t *)P->stat_part, P->status);
+    FE_TIMED("k_stats_partial", s,
+             hipLaunchKernelGGL(k_stats_partial, dim3(sb), dim3(STB), 0, s, N, (const int32_t *)P->prowptr,
+                           (const int32_t *)P->pincptr, (const uint8_t *)P->isdp, P->stat_part));
+    FE_TIMED("k_stats_final", s,
+             hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STB), 0, s, (int32_t)sb, (const int64_t *)P->stat_part, P->status));
     if ((rc = fe_launch_check())) return rc;
     int32_t st[ST_COUNT];
     int64_t tot[8];
@@ -811,15 +822,18 @@ template <int NV> int plan_pattern(fe_plan *P, int32_t *rowptr, int32_t *colind,
     const int32_t N = (int32_t)P->N;
     constexpr int RB = RowCaps<NV>::BLOCK;
     const RowArgs R = row_args(P);
-    hipLaunchKernelGGL((k_rows<NV, true>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R);
-    hipLaunchKernelGGL(k_label_rows, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, (const int32_t *)P->piinv,
-                       (const int4 *)P->precp, P->rowrec, P->rowlen);
+    FE_TIMED("k_rows_final", s,
+             hipLaunchKernelGGL((k_rows<NV, true>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R));
+    FE_TIMED("k_label_rows", s,
+             hipLaunchKernelGGL(k_label_rows, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, (const int32_t *)P->piinv,
+                           (const int4 *)P->precp, P->rowrec, P->rowlen));
     int rc;
     if ((rc = fe_launch_check())) return rc;
     if ((rc = fe_scan_exclusive(P->rowlen, P->rowlen, N, P->totals + 3, P->part, P->status, s))) return rc;
     FE_HIP_CHECK(hipMemcpyAsync(rowptr, P->rowlen, sizeof(int32_t) * (size_t)(N + 1), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_pattern_to_label, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N,
-                       (const int32_t *)P->rowlen, (const int4 *)P->rowrec, (const int32_t *)R.colindp, colind);
+    FE_TIMED("k_pattern_to_label", s,
+             hipLaunchKernelGGL(k_pattern_to_label, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N,
+                           (const int32_t *)P->rowlen, (const int4 *)P->rowrec, (const int32_t *)R.colindp, colind));
     return fe_launch_check();
 }
 

@@ -12,6 +12,8 @@
 // Each block writes its partial sums; the last block to finish (integer ticket)
 // adds all partials in index order and derives alpha, or beta and the stopping
 // test, so every reduction has a fixed order and results are bitwise repeatable.
+// Only thread 0 of each block takes part in the ticket, so a block issues one
+// device-scope release/acquire per kernel, not one per wavefront.
 // Scalars live in device memory; the host launches iterations in chunks and reads
 // the "done" flag once per chunk, kernels after convergence return at once.
 #include "cg_common.h"
@@ -124,7 +126,9 @@ __global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restric
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     double pq = 0.0;
     if (i < n) {
-        const double s = cg_apply_row(i, rowptr, colind, val, z, pold, beta);
+        const bool ok = true;
+        double s;
+        cg_apply_rows<1>(&i, &ok, rowptr, colind, val, z, pold, &beta, &s);
         const double pi = z[i] + beta * pold[i];
         pnew[i] = pi;
         qv[i] = s;
@@ -187,8 +191,9 @@ extern "C" int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, 
     if (n < 0 || n >= INT32_MAX) return FE_EINVAL;
     if (n == 0) return FE_OK;
     if (!rowptr || !colind || !val || !x || !y) return FE_EINVAL;
-    hipLaunchKernelGGL(k_spmv, dim3((unsigned)cdiv(n, SB)), dim3(SB), 0, static_cast<hipStream_t>(stream),
-                       (int32_t)n, rowptr, colind, val, x, y);
+    FE_TIMED("k_spmv", static_cast<hipStream_t>(stream),
+             hipLaunchKernelGGL(k_spmv, dim3((unsigned)cdiv(n, SB)), dim3(SB), 0, static_cast<hipStream_t>(stream),
+                           (int32_t)n, rowptr, colind, val, x, y));
     return fe_launch_check();
 }
 
@@ -214,8 +219,9 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
     const unsigned nb = (unsigned)cdiv(n, SB);
     int rc;
     if ((rc = fe_fill_i32(W.flag, F_NFLAG, 0, s))) return rc;
-    hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, b, (const double *)u, W.r, W.z,
-                       W.p0, W.dinv, W.part, W.scal, W.flag, rtol);
+    FE_TIMED("k_cg_init", s,
+             hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, b, (const double *)u, W.r, W.z,
+                           W.p0, W.dinv, W.part, W.scal, W.flag, rtol));
     if ((rc = fe_launch_check())) return rc;
     int32_t fl[F_NFLAG];
     double sc[S_NSCAL];
@@ -231,10 +237,12 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
         for (int32_t c = 0; c < chunk; ++c) {
             double *pold = parity ? W.p1 : W.p0;
             double *pnew = parity ? W.p0 : W.p1;
-            hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, (const double *)W.z,
-                               (const double *)pold, pnew, W.q, W.part, W.scal, W.flag);
-            hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(SB), 0, s, nn, u, (const double *)pnew, (const double *)W.q,
-                               W.r, W.z, (const double *)W.dinv, W.part, W.scal, W.flag);
+            FE_TIMED("k_cg_a", s,
+                     hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, (const double *)W.z,
+                                   (const double *)pold, pnew, W.q, W.part, W.scal, W.flag));
+            FE_TIMED("k_cg_b", s,
+                     hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(SB), 0, s, nn, u, (const double *)pnew, (const double *)W.q,
+                                   W.r, W.z, (const double *)W.dinv, W.part, W.scal, W.flag));
             parity ^= 1;
         }
         if ((rc = fe_launch_check())) return rc;

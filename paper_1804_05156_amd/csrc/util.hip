@@ -118,7 +118,8 @@ template <typename T> int fill(T *p, int64_t n, T v, hipStream_t s)
     if (n <= 0) return FE_OK;
     int64_t blocks = cdiv(n, 256);
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    FE_TIMED("k_fill", s,
+             hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v));
     return fe_launch_check();
 }
 
@@ -137,8 +138,9 @@ extern "C" int fe_select(int64_t n, const uint8_t *mask, const double *a, const 
     if (n == 0) return FE_OK;
     int64_t blocks = cdiv(n, 256);
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_select, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), n, mask, a,
-                       b, out);
+    FE_TIMED("k_select", static_cast<hipStream_t>(stream),
+             hipLaunchKernelGGL(k_select, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream), n, mask, a,
+                           b, out));
     return fe_launch_check();
 }
 
@@ -150,9 +152,12 @@ int fe_scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int64_t *total
     // in/out must be 16-byte aligned (workspace arrays are 256-byte aligned).
     if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return FE_EINVAL;
     const int64_t nb = cdiv(n > 0 ? n : 1, SCAN_TILE);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_BLOCK), 0, s, part, nb, total_dev, out, n, status);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part);
+    FE_TIMED("k_scan_reduce", s,
+             hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part));
+    FE_TIMED("k_scan_partials", s,
+             hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_BLOCK), 0, s, part, nb, total_dev, out, n, status));
+    FE_TIMED("k_scan_apply", s,
+             hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part));
     return fe_launch_check();
 }
 

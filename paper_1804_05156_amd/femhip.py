@@ -27,7 +27,7 @@ ENTRY_POINTS = (
     "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_spmv",
     "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_grad", "fe_batch_solve_workspace_bytes",
     "fe_batch_solve", "fe_batch_create", "fe_batch_set_grid", "fe_batch_get_info", "fe_batch_assemble_solve",
-    "fe_batch_destroy",
+    "fe_batch_destroy", "fe_prof_enable", "fe_prof_read",
 )
 
 
@@ -48,8 +48,14 @@ class fe_plan_info(C.Structure):
 
 class fe_batch_info(C.Structure):
     _fields_ = [("n_inst", C.c_int32), ("n_units", C.c_int32), ("n_rows", C.c_int64), ("grid", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("max_blocks_per_cu", C.c_int32), ("cooperative", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("max_blocks_per_cu", C.c_int32), ("units_per_step", C.c_int32),
+                ("cooperative", C.c_int32),
                 ("captures", C.c_int32)]
+
+
+class fe_prof_entry(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double), ("min_ms", C.c_double),
+                ("max_ms", C.c_double)]
 
 
 class FemhipError(RuntimeError):
@@ -81,13 +87,15 @@ def _load():
         "fe_grad": ([P, P, P, P, P, P], C.c_int),
         "fe_select": ([I64, P, P, P, P, P], C.c_int),
         "fe_batch_solve_workspace_bytes": ([I64, I32, C.POINTER(SZ)], C.c_int),
-        "fe_batch_solve": ([I32, P, P, P, P, P, P, D, I32, I32, P, SZ, P, P, P], C.c_int),
-        "fe_batch_create": ([P, I32, P, I32, P, SZ, C.POINTER(P), P], C.c_int),
-        "fe_batch_set_grid": ([P, I32], C.c_int),
+        "fe_batch_solve": ([I32, P, P, P, P, P, P, D, I32, I32, I32, P, SZ, P, P, P], C.c_int),
+        "fe_batch_create": ([P, I32, P, I32, I32, P, SZ, C.POINTER(P), P], C.c_int),
+        "fe_batch_set_grid": ([P, I32, I32], C.c_int),
         "fe_batch_get_info": ([P, C.POINTER(fe_batch_info)], C.c_int),
         "fe_batch_assemble_solve": ([P, P, P, C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), P, P, P, P, P,
                                      P, D, I32, P, P, P], C.c_int),
         "fe_batch_destroy": ([P], C.c_int),
+        "fe_prof_enable": ([C.c_int], C.c_int),
+        "fe_prof_read": ([C.POINTER(fe_prof_entry), I32, C.POINTER(I32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -252,30 +260,31 @@ def _i64_array(off):
 
 
 def fe_batch_solve(inst_row_off, rowptr, colind, val, b, u, rtol: float, maxit: int, ws, blocks_per_cu: int = 0,
-                   stream=None, allow_noconv=False):
+                   units_per_step: int = 0, stream=None, allow_noconv=False):
     """Returns (iters list, relres list, status)."""
     n_inst = len(inst_row_off) - 1
     it = (C.c_int32 * n_inst)()
     rel = (C.c_double * n_inst)()
     rc = _lib.fe_batch_solve(n_inst, _i64_array(inst_row_off), _ptr(rowptr, torch.int32), _ptr(colind, torch.int32),
                              _ptr(val, torch.float64), _ptr(b, torch.float64), _ptr(u, torch.float64), float(rtol),
-                             int(maxit), int(blocks_per_cu), _ptr(ws, torch.uint8, "ws"), ws.numel(), it, rel,
-                             _stream(stream))
+                             int(maxit), int(blocks_per_cu), int(units_per_step), _ptr(ws, torch.uint8, "ws"),
+                             ws.numel(), it, rel, _stream(stream))
     if not (rc == FE_ENOCONV and allow_noconv):
         _check(rc, "fe_batch_solve")
     return list(it), list(rel), rc
 
 
-def fe_batch_create(plan, inst_node_off, ws, blocks_per_cu: int = 0, stream=None):
+def fe_batch_create(plan, inst_node_off, ws, blocks_per_cu: int = 0, units_per_step: int = 0, stream=None):
     h = C.c_void_p()
     _check(_lib.fe_batch_create(plan, len(inst_node_off) - 1, _i64_array(inst_node_off), int(blocks_per_cu),
-                                _ptr(ws, torch.uint8, "ws"), ws.numel(), C.byref(h), _stream(stream)),
+                                int(units_per_step), _ptr(ws, torch.uint8, "ws"), ws.numel(), C.byref(h),
+                                _stream(stream)),
            "fe_batch_create")
     return h
 
 
-def fe_batch_set_grid(batch, blocks_per_cu: int):
-    _check(_lib.fe_batch_set_grid(batch, int(blocks_per_cu)), "fe_batch_set_grid")
+def fe_batch_set_grid(batch, blocks_per_cu: int, units_per_step: int = 0):
+    _check(_lib.fe_batch_set_grid(batch, int(blocks_per_cu), int(units_per_step)), "fe_batch_set_grid")
 
 
 def fe_batch_get_info(batch) -> dict:
@@ -300,6 +309,23 @@ def fe_batch_assemble_solve(batch, node, kappa, f, gD, gN, rowptr, colind, val, 
 
 def fe_batch_destroy(batch):
     _check(_lib.fe_batch_destroy(batch), "fe_batch_destroy")
+
+
+def fe_prof_enable(on: bool):
+    _check(_lib.fe_prof_enable(1 if on else 0), "fe_prof_enable")
+
+
+def fe_prof_read() -> dict:
+    """{kernel name: {"launches", "total_ms", "min_ms", "max_ms", "avg_ms"}} since the last read."""
+    cap = 64
+    buf = (fe_prof_entry * cap)()
+    n = C.c_int32()
+    _check(_lib.fe_prof_read(buf, cap, C.byref(n)), "fe_prof_read")
+    out = {}
+    for e in buf[:min(n.value, cap)]:
+        out[e.name.decode()] = {"launches": int(e.launches), "total_ms": e.total_ms, "min_ms": e.min_ms,
+                                "max_ms": e.max_ms, "avg_ms": e.total_ms / max(e.launches, 1)}
+    return out
 
 
 # ----------------------------------------------------------------------------- conveniences

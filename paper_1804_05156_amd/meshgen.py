@@ -240,7 +240,7 @@ def batch_sizes(n_inst: int = 256, lo: int = 17, hi: int = 513, seed: int = 4) -
     return rng.integers(lo, hi + 1, n_inst)
 
 
-def batch_meshes(sizes, *, seed_base: int = 4000, jitter: float = 0.2, permute: bool = True,
+def batch_meshes(sizes, *, seed_base: int = 4000, jitter: float = 0.2, permute: bool = False,
                  kappa: str = "lognormal"):
     """Instance i is ``square_mesh(sizes[i], seed=seed_base+i, ...)``."""
     return [square_mesh(int(n), jitter=jitter, permute=permute, seed=seed_base + i, kappa=kappa)

@@ -56,7 +56,7 @@ def _check_instance(B, k, m, u, it, rel, f, gd, rtol, fo=None, gdo=None, oracle_
 
 def test_batch_matches_plain_bitwise_and_oracle():
     log("case: batch of 6 meshes vs plain path and oracle")
-    ms = meshgen.batch_meshes([17, 9, 33, 12, 25, 40], seed_base=7000)
+    ms = meshgen.batch_meshes([17, 9, 33, 12, 25, 40], seed_base=7000, permute=True)
     (f, fo), (gd, gdo), _ = fns(*SPECS)
     B, kap = _batch(ms)
     u, it, rel = B.assemble_solve(kap, f, gd, None, rtol=1e-10)
@@ -70,21 +70,20 @@ def test_batch_solve_grid_independent():
     """fe_batch_solve (no graph) gives the same bits for every persistent grid size."""
     from paper_1804_05156_amd import femhip
     log("case: fe_batch_solve over grid sizes")
-    ms = meshgen.batch_meshes([30, 7, 52, 19], seed_base=7100)
+    ms = meshgen.batch_meshes([30, 7, 52, 19], seed_base=7100, permute=True)
     (f, _), (gd, _), _ = fns(*SPECS)
     B, kap = _batch(ms)
     u_ref, it_ref, rel_ref = B.assemble_solve(kap, f, gd, None, rtol=1e-11)
     u_ref = u_ref.clone()
     ws = torch.empty(femhip.fe_batch_solve_workspace_bytes(B.N, B.n_inst), dtype=torch.uint8, device="cuda")
-    hi = B.info()["max_blocks_per_cu"]
-    for bpc in sorted({1, 2, hi}):
+    for bpc, ups in ((1, 1), (1, 4), (2, 2), (4, 1), (4, 4)):
         asm = B.plan.assemble(kap, f, gd, None)
         u = torch.empty(B.N, dtype=torch.float64, device="cuda")
         femhip.fe_select(asm.is_dirichlet, asm.b, None, u)
         it, rel, rc = femhip.fe_batch_solve(B.node_off, B.plan.rowptr, B.plan.colind, asm.val_bc, asm.b, u, 1e-11,
-                                            100000, ws, blocks_per_cu=bpc)
+                                            100000, ws, blocks_per_cu=bpc, units_per_step=ups)
         torch.cuda.synchronize()
-        log(f"  blocks/CU {bpc}: iterations {it}")
+        log(f"  blocks/CU {bpc}, units/step {ups}: iterations {it}")
         assert rc == femhip.FE_OK and it == it_ref and rel == rel_ref
         assert torch.equal(u, u_ref)
 
@@ -152,7 +151,7 @@ def test_batch_edge_cases():
 
 
 def test_full_size_batch_sampled():
-    """The 256-instance batch (grid sides uniform in [17, 513], jittered, permuted,
+    """The 256-instance batch (grid sides uniform in [17, 513], jittered,
     lognormal kappa, rtol 1e-10) in the launch configuration of the benchmark: every
     instance converges; sampled instances equal the plain path bit for bit, the
     smallest ones also satisfy the oracle residual bound."""
