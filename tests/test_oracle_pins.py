@@ -48,6 +48,28 @@ def test_sparse_worked_example():
     assert listed == list(zip(g["i_one_based"], g["j_one_based"]))
 
 
+def test_spmv_worked_example_and_row_sums():
+    """Section 2.1: the printed 4x3 matrix applied to unit vectors gives its printed
+    columns; an assembled stiffness matrix maps constants to zero (the gradients
+    of the barycentric coordinates sum to zero, Section 3.1.1)."""
+    g = _gold("sparse_example.json")
+    i = np.array(g["i_one_based"]) - 1
+    j = np.array(g["j_one_based"]) - 1
+    rowptr, colind, val = oracle.coo_to_csr(g["m"], g["n"], i, j, np.array(g["s"], float))
+    dense = np.array(g["dense"], float)
+    for c in range(g["n"]):
+        e = np.zeros(g["n"])
+        e[c] = 1.0
+        assert np.array_equal(oracle.spmv(rowptr, colind, val, e), dense[:, c])
+    x = np.array([0.5, -2.0, 3.0])
+    expect = [sum(dense[r, c] * x[c] for c in range(g["n"])) for r in range(g["m"])]
+    assert np.array_equal(oracle.spmv(rowptr, colind, val, x), np.array(expect))
+    m = meshgen.square_mesh(9, jitter=0.2, permute=True, seed=61, kappa="lognormal")
+    a = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa)
+    y = oracle.spmv(a.rowptr, a.colind, a.val, np.ones(m.n_node))
+    assert np.abs(y).max() <= 1e-13 * np.abs(a.val).max()
+
+
 def test_sparse_adds_duplicates_in_order():
     """Section 2.2: a repeated (i, j) pair is added; entries summing to zero stay stored."""
     i = np.array([1, 0, 1, 1, 0])
