@@ -58,20 +58,3 @@ FE_DEV double cg_sum_partials(const double *part, int32_t nb, double *lds)
     for (int32_t k = threadIdx.x; k < nb; k += CG_UNIT) v += part[k];
     return block_sum<CG_UNIT>(v, lds);
 }
-
-// True in every thread of the block that arrives last at `ticket` among `count`
-// arrivals.  Only thread 0's writes (the block's partial sums) are published by the
-// arrival, and the last block then sees every other block's partials.  The last
-// block resets the ticket.
-FE_DEV bool cg_last_arrival(int32_t *ticket, int32_t count)
-{
-    __shared__ int is_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int32_t prev = __hip_atomic_fetch_add(ticket, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        is_last = (prev == count - 1);
-        if (is_last) __hip_atomic_store(ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    return is_last != 0;
-}

@@ -5,15 +5,17 @@
 // there, A_bc u = b is the same system at full size and is symmetric positive
 // definite, so CG applies.
 //
-// One CG iteration is two kernels:
+// One CG iteration is two row kernels, each followed by a one-block kernel that
+// adds its partial sums:
 //   K_A: p = z + beta p_old (row i), q = A p computed as A (z + beta p_old) on the
 //        fly (so no grid-wide barrier is needed between the two), partial p.q
+//   K_A': alpha = r.z / p.q
 //   K_B: x += alpha p, r -= alpha q, z = r / diag(A), partials r.z and r.r
-// Each block writes its partial sums; the last block to finish (integer ticket)
-// adds all partials in index order and derives alpha, or beta and the stopping
-// test, so every reduction has a fixed order and results are bitwise repeatable.
-// Only thread 0 of each block takes part in the ticket, so a block issues one
-// device-scope release/acquire per kernel, not one per wavefront.
+//   K_B': beta, the stopping test, the iteration count
+// Partials are added in index order, so every reduction has a fixed order and
+// results are bitwise repeatable.  The kernel boundaries make every block's
+// partial visible to the summing kernel; no device-scope fence or atomic runs
+// inside the row kernels (one per workgroup would serialize on the L2s).
 // Scalars live in device memory; the host launches iterations in chunks and reads
 // the "done" flag once per chunk, kernels after convergence return at once.
 #include "cg_common.h"
@@ -23,7 +25,7 @@ namespace {
 constexpr int SB = CG_UNIT;   // threads per block, one row per thread
 
 enum { S_RZ = 0, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_PQ, S_NSCAL = 8 };
-enum { F_DONE = 0, F_ITER, F_TICKET, F_BAD, F_NFLAG = 8 };
+enum { F_DONE = 0, F_ITER, F_BAD, F_NFLAG = 8 };
 
 struct SolveWs {
     double *r, *z, *p0, *p1, *q, *dinv;
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__rest
                                                 const int32_t *__restrict__ colind, const double *__restrict__ val,
                                                 const double *__restrict__ b, const double *__restrict__ x,
                                                 double *r, double *z, double *p0, double *dinv, double *part,
-                                                double *scal, int32_t *flag, double rtol)
+                                                int32_t *flag)
 {
     __shared__ double lds[SB / 64];
     const int32_t i = blockIdx.x * SB + threadIdx.x;
@@ -96,7 +98,13 @@ __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__rest
         part[nb + blockIdx.x] = s1;
         part[2 * nb + blockIdx.x] = s2;
     }
-    if (!cg_last_arrival(flag + F_TICKET, nb)) return;
+}
+
+// One block: r.z, r.r, b.b from the partials; tolerance and initial stopping test.
+__global__ __launch_bounds__(SB) void k_cg_init_sum(int32_t nb, const double *part, double *scal, int32_t *flag,
+                                                    double rtol)
+{
+    __shared__ double lds[SB / 64];
     const double RZ = cg_sum_partials(part, nb, lds);
     const double RR = cg_sum_partials(part + nb, nb, lds);
     const double BB = cg_sum_partials(part + 2 * nb, nb, lds);
@@ -113,15 +121,15 @@ __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__rest
     }
 }
 
-// p = z + beta p_old; q = A p (as A z + beta A p_old); partial p.q -> alpha.
+// p = z + beta p_old; q = A p (as A z + beta A p_old); partial p.q.
 __global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restrict__ rowptr,
                                              const int32_t *__restrict__ colind, const double *__restrict__ val,
                                              const double *__restrict__ z, const double *__restrict__ pold,
                                              double *__restrict__ pnew, double *__restrict__ qv, double *part,
-                                             double *scal, int32_t *flag)
+                                             const double *scal, const int32_t *flag)
 {
     __shared__ double lds[SB / 64];
-    if (*(volatile int32_t *)(flag + F_DONE)) return;
+    if (*(volatile const int32_t *)(flag + F_DONE)) return;
     const double beta = scal[S_BETA];
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     double pq = 0.0;
@@ -136,22 +144,28 @@ __global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restric
     }
     const double bs = block_sum<SB>(pq, lds);
     if (threadIdx.x == 0) part[blockIdx.x] = bs;
-    if (!cg_last_arrival(flag + F_TICKET, gridDim.x)) return;
-    const double PQ = cg_sum_partials(part, gridDim.x, lds);
+}
+
+// One block: alpha = r.z / p.q.
+__global__ __launch_bounds__(SB) void k_cg_a_sum(int32_t nb, const double *part, double *scal, const int32_t *flag)
+{
+    __shared__ double lds[SB / 64];
+    if (*(volatile const int32_t *)(flag + F_DONE)) return;
+    const double PQ = cg_sum_partials(part, nb, lds);
     if (threadIdx.x == 0) {
         scal[S_PQ] = PQ;
         scal[S_ALPHA] = scal[S_RZ] / PQ;
     }
 }
 
-// x += alpha p; r -= alpha q; z = r dinv; partials r.z, r.r -> beta, stopping test.
+// x += alpha p; r -= alpha q; z = r dinv; partials r.z, r.r.
 __global__ __launch_bounds__(SB) void k_cg_b(int32_t n, double *__restrict__ x, const double *__restrict__ p,
                                              const double *__restrict__ qv, double *__restrict__ r,
                                              double *__restrict__ z, const double *__restrict__ dinv, double *part,
-                                             double *scal, int32_t *flag)
+                                             const double *scal, const int32_t *flag)
 {
     __shared__ double lds[SB / 64];
-    if (*(volatile int32_t *)(flag + F_DONE)) return;
+    if (*(volatile const int32_t *)(flag + F_DONE)) return;
     const double alpha = scal[S_ALPHA];
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     double rz = 0.0, rr = 0.0;
@@ -171,7 +185,13 @@ __global__ __launch_bounds__(SB) void k_cg_b(int32_t n, double *__restrict__ x, 
         part[blockIdx.x] = s0;
         part[nb + blockIdx.x] = s1;
     }
-    if (!cg_last_arrival(flag + F_TICKET, nb)) return;
+}
+
+// One block: beta = r.z_new / r.z_old, the stopping test and the iteration count.
+__global__ __launch_bounds__(SB) void k_cg_b_sum(int32_t nb, const double *part, double *scal, int32_t *flag)
+{
+    __shared__ double lds[SB / 64];
+    if (*(volatile const int32_t *)(flag + F_DONE)) return;
     const double RZ = cg_sum_partials(part, nb, lds);
     const double RR = cg_sum_partials(part + nb, nb, lds);
     if (threadIdx.x == 0) {
@@ -220,8 +240,11 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
     int rc;
     if ((rc = fe_fill_i32(W.flag, F_NFLAG, 0, s))) return rc;
     FE_TIMED("k_cg_init", s,
-             hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, b, (const double *)u, W.r, W.z,
-                           W.p0, W.dinv, W.part, W.scal, W.flag, rtol));
+             hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, b, (const double *)u,
+                                W.r, W.z, W.p0, W.dinv, W.part, W.flag));
+    FE_TIMED("k_cg_init_sum", s,
+             hipLaunchKernelGGL(k_cg_init_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part, W.scal,
+                                W.flag, rtol));
     if ((rc = fe_launch_check())) return rc;
     int32_t fl[F_NFLAG];
     double sc[S_NSCAL];
@@ -239,10 +262,18 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
             double *pnew = parity ? W.p0 : W.p1;
             FE_TIMED("k_cg_a", s,
                      hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, (const double *)W.z,
-                                   (const double *)pold, pnew, W.q, W.part, W.scal, W.flag));
+                                        (const double *)pold, pnew, W.q, W.part, (const double *)W.scal,
+                                        (const int32_t *)W.flag));
+            FE_TIMED("k_cg_a_sum", s,
+                     hipLaunchKernelGGL(k_cg_a_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part,
+                                        W.scal, (const int32_t *)W.flag));
             FE_TIMED("k_cg_b", s,
-                     hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(SB), 0, s, nn, u, (const double *)pnew, (const double *)W.q,
-                                   W.r, W.z, (const double *)W.dinv, W.part, W.scal, W.flag));
+                     hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(SB), 0, s, nn, u, (const double *)pnew,
+                                        (const double *)W.q, W.r, W.z, (const double *)W.dinv, W.part,
+                                        (const double *)W.scal, (const int32_t *)W.flag));
+            FE_TIMED("k_cg_b_sum", s,
+                     hipLaunchKernelGGL(k_cg_b_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part,
+                                        W.scal, W.flag));
             parity ^= 1;
         }
         if ((rc = fe_launch_check())) return rc;
