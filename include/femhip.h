@@ -218,7 +218,7 @@ int fe_batch_solve_workspace_bytes(int64_t n, int32_t n_inst, size_t *bytes);
  * must not couple to other rows.  u: x0 on entry, solutions on return.  Instance k
  * stops when its recurrence residual drops to rtol times ||b_k||_2, or after maxit
  * iterations.  blocks_per_cu: workgroups per compute unit of the persistent grid
- * (0 picks a default; above what fits, FE_ELIMIT); units_per_step: 256-row units
+ * (0 picks a default; above what fits, FE_EINVAL); units_per_step: 256-row units
  * each workgroup processes together (1, 2 or 4; 0 picks a default).  Neither
  * changes any result bit.  iters, relres: host arrays of
  * n_inst (may be NULL).  ws: 256-byte aligned device workspace of at least the

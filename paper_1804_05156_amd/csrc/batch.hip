@@ -519,7 +519,7 @@ static int batch_set_grid(fe_batch_solver *S, int32_t blocks_per_cu, int32_t uni
     S->max_per_cu = per;
     S->units_per_step = units_per_step;
     int32_t want = blocks_per_cu ? blocks_per_cu : (per < 2 ? per : 2);
-    if (want > per) return FE_ELIMIT;
+    if (want > per) return FE_EINVAL;   // more workgroups per compute unit than fit
     int64_t g = (int64_t)cus * want;
     if (g > S->n_units) g = S->n_units;
     S->grid = (int32_t)(g > 0 ? g : 1);

@@ -24,13 +24,16 @@ FE_DEV void cg_init_row(int32_t i, const int32_t *__restrict__ rowptr, const int
 }
 
 // s[j] = (A p_new)_{i[j]} with p_new = z + beta[j] p_old formed on the fly, for K rows
-// at once (rows with ok[j] false are skipped).  The K rows are walked in lockstep so
-// that their loads overlap; each row is summed in its own column order.
+// at once (rows with ok[j] false are skipped).  Each row is walked in chunks of CH
+// entries: all column indices and values of a chunk are loaded, then all gathers
+// of z and p_old, then the products are added in column order, so the loads of a
+// chunk overlap instead of forming one dependent chain per entry.
 template <int K>
 FE_DEV void cg_apply_rows(const int32_t *i, const bool *ok, const int32_t *__restrict__ rowptr,
                           const int32_t *__restrict__ colind, const double *__restrict__ val,
                           const double *__restrict__ z, const double *__restrict__ pold, const double *beta, double *s)
 {
+    constexpr int CH = K >= 4 ? 2 : (K == 2 ? 4 : 8);
     int32_t q[K], e[K];
     int32_t len = 0;
 #pragma unroll
@@ -40,13 +43,30 @@ FE_DEV void cg_apply_rows(const int32_t *i, const bool *ok, const int32_t *__res
         e[j] = ok[j] ? rowptr[i[j] + 1] : 0;
         len = max(len, e[j] - q[j]);
     }
-    for (int32_t m = 0; m < len; ++m) {
+    for (int32_t m0 = 0; m0 < len; m0 += CH) {
+        int32_t c[K][CH];
+        double v[K][CH], zz[K][CH], pp[K][CH];
 #pragma unroll
         for (int j = 0; j < K; ++j)
-            if (q[j] + m < e[j]) {
-                const int32_t c = colind[q[j] + m];
-                s[j] += val[q[j] + m] * (z[c] + beta[j] * pold[c]);
-            }
+#pragma unroll
+            for (int t = 0; t < CH; ++t)
+                if (q[j] + m0 + t < e[j]) {
+                    c[j][t] = colind[q[j] + m0 + t];
+                    v[j][t] = val[q[j] + m0 + t];
+                }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int t = 0; t < CH; ++t)
+                if (q[j] + m0 + t < e[j]) {
+                    zz[j][t] = z[c[j][t]];
+                    pp[j][t] = pold[c[j][t]];
+                }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int t = 0; t < CH; ++t)
+                if (q[j] + m0 + t < e[j]) s[j] += v[j][t] * (zz[j][t] + beta[j] * pp[j][t]);
     }
 }
 

@@ -76,16 +76,24 @@ def test_batch_solve_grid_independent():
     u_ref, it_ref, rel_ref = B.assemble_solve(kap, f, gd, None, rtol=1e-11)
     u_ref = u_ref.clone()
     ws = torch.empty(femhip.fe_batch_solve_workspace_bytes(B.N, B.n_inst), dtype=torch.uint8, device="cuda")
-    for bpc, ups in ((1, 1), (1, 4), (2, 2), (4, 1), (4, 4)):
+    ran = 0
+    for bpc, ups in ((1, 1), (1, 4), (2, 2), (4, 1), (2, 4), (4, 4)):
         asm = B.plan.assemble(kap, f, gd, None)
         u = torch.empty(B.N, dtype=torch.float64, device="cuda")
         femhip.fe_select(asm.is_dirichlet, asm.b, None, u)
-        it, rel, rc = femhip.fe_batch_solve(B.node_off, B.plan.rowptr, B.plan.colind, asm.val_bc, asm.b, u, 1e-11,
-                                            100000, ws, blocks_per_cu=bpc, units_per_step=ups)
+        try:
+            it, rel, rc = femhip.fe_batch_solve(B.node_off, B.plan.rowptr, B.plan.colind, asm.val_bc, asm.b, u,
+                                                1e-11, 100000, ws, blocks_per_cu=bpc, units_per_step=ups)
+        except femhip.FemhipError as e:
+            assert e.code == femhip.FE_EINVAL   # a grid that does not fit this kernel's occupancy
+            log(f"  blocks/CU {bpc}, units/step {ups}: does not fit")
+            continue
         torch.cuda.synchronize()
+        ran += 1
         log(f"  blocks/CU {bpc}, units/step {ups}: iterations {it}")
         assert rc == femhip.FE_OK and it == it_ref and rel == rel_ref
         assert torch.equal(u, u_ref)
+    assert ran >= 4
 
 
 def test_graph_replay_and_recapture():
