@@ -19,10 +19,11 @@ Also reported on the same JSON line:
                instances (plans built beforehand in both)
   adjoint      1025^2 mesh: forward solve + adjoint solve + gradient kernel against
                the forward solve alone
+  next         assembly on the L-shaped domain, and the pure Neumann solve
   cpu_baseline the CPU oracle (single thread) on a bounded sample of the recipe
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload jitter2049|kuhn129]
-                       [--no-cpu] [--no-batch] [--no-adjoint]
+                       [--no-cpu] [--no-batch] [--no-adjoint] [--no-next]
 """
 from __future__ import annotations
 
@@ -115,6 +116,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-next", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (for counter calibration)")
     args = ap.parse_args()
@@ -248,6 +250,7 @@ def main():
     cold_bytes = in_bytes + (N + 1) * 4 + nnz * 4 + 2 * nnz * 8 + 2 * N * 8 + N
     warm_bytes = in_bytes - (dim + 1) * NT + 2 * nnz * 8 + 2 * N * 8 + N
 
+    nxt = None if args.no_next else bench_next(args)
     batched = None if args.no_batch else bench_batched(args)
     adjoint = None if args.no_adjoint else bench_adjoint(args)
     cpu = None if args.no_cpu else cpu_baseline(args.workload)
@@ -276,6 +279,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
                      "avg_us": dom_us},
         "batched": batched,
+        "next": nxt,
         "adjoint": adjoint,
         "cpu_baseline": cpu,
     }
@@ -338,6 +342,56 @@ def bench_batched(args):
             "blocks_per_cu": info["blocks_per_cu"], "units_per_step": info["units_per_step"],
             "cooperative_in_graph": bool(info["cooperative"]),
             "autotune_ms": tune.get("ms")}
+
+
+def bench_next(args):
+    """The rows next to the core path: assembly on the L-shaped domain (cold and warm)
+    and the pure Neumann solve (mean shift, pinned PCG, zero-mean shift)."""
+    import numpy as np
+    import torch
+    from paper_1804_05156_amd import femhip, meshgen
+    dev = torch.device("cuda:0")
+    log("[bench] next: L-shape 1025 x 1025 bounding grid")
+    m = meshgen.lshape_mesh(513, seed=9, kappa="lognormal")
+    node = torch.from_numpy(m.node).to(dev)
+    elem = torch.from_numpy(m.elem).to(dev)
+    bd = torch.from_numpy(m.bdflag).to(dev)
+    kap = torch.from_numpy(m.kappa).to(dev)
+    f = femhip.Fn(femhip.FE_FN_CONST, (1.0,))
+    reps = max(1, min(args.steps, 10))
+    femhip.Plan(node, elem, bd).assemble(kap, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p = femhip.Plan(node, elem, bd)
+        a = p.assemble(kap, f)
+    torch.cuda.synchronize()
+    cold = (time.perf_counter() - t0) / reps
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        p.assemble(kap, f, out=a)
+    ev1.record()
+    ev1.synchronize()
+    warm = ev0.elapsed_time(ev1) / reps * 1e-3
+    lshape = {"workload": "L-shape, 1025^2 bounding grid, lognormal kappa, f = 1, Dirichlet",
+              "n_elem": m.n_elem, "cold_ms": cold * 1e3, "cold_elements_per_s": m.n_elem / cold,
+              "warm_ms": warm * 1e3, "warm_elements_per_s": m.n_elem / warm}
+    log("[bench] next: pure Neumann 1025^2")
+    m = meshgen.square_mesh(1025, jitter=0.2, seed=5, kappa="lognormal", sides=(2, 2, 2, 2))
+    fv = 2 * math.pi ** 2 * np.cos(math.pi * m.node[0]) * np.cos(math.pi * m.node[1])
+    node = torch.from_numpy(m.node).to(dev)
+    p = femhip.Plan(node, torch.from_numpy(m.elem).to(dev), torch.from_numpy(m.bdflag).to(dev))
+    a = p.assemble(torch.from_numpy(m.kappa).to(dev), femhip.Fn(femhip.FE_FN_NODAL, (0.0,), torch.from_numpy(fv).to(dev)))
+    p.neumann_solve(a, rtol=1e-10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, it, rel, mb = p.neumann_solve(a, rtol=1e-10)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    neumann = {"workload": "1025^2 jittered, lognormal kappa, all sides Neumann, f = 2 pi^2 cos cos (nodal), rtol 1e-10",
+               "ms": t * 1e3, "iterations": it, "relres": rel, "mean_b": mb, "us_per_iteration": t / max(it, 1) * 1e6}
+    return {"lshape": lshape, "pure_neumann": neumann}
 
 
 def bench_adjoint(args):

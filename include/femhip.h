@@ -186,6 +186,28 @@ int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const doub
              int32_t *iters, double *relres, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Pure Neumann problem (Section 3.3, equations (compatible) and (meanb)).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of device workspace fe_neumann_solve needs for this plan and nnz stored
+ * entries. */
+int fe_neumann_workspace_bytes(const fe_plan *plan, int64_t nnz, size_t *bytes);
+
+/* Solve A u = b when every boundary side is Neumann (the plan has no Dirichlet
+ * vertex, else FE_EINVAL).  val, b: from fe_assemble (A, not A_bc).  The method's
+ * steps: b' = b - mean(b) (the discrete compatibility condition); u = 0 at vertex
+ * 0 and Jacobi-PCG on the other rows (A with row and column 0 replaced by the
+ * identity, b'_0 = 0); then u <- u - c with c = sum_t |t| mean(u(elem_t)) / sum_t
+ * |t|, so u has zero mean.  u (device, N) is output only.  *iters and *relres as for
+ * fe_solve (relative to ||b'||), *mean_b receives mean(b) (may be NULL).  node:
+ * device coordinates; ws: 256-byte aligned, at least the queried size.
+ * Synchronizes.  FE_ENOCONV if maxit was reached (u is still shifted). */
+int fe_neumann_solve(fe_plan *plan, const double *node, const int32_t *rowptr,
+                     const int32_t *colind, const double *val, const double *b, double *u,
+                     double rtol, int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters,
+                     double *relres, double *mean_b, void *stream);
+
+/* ---------------------------------------------------------------------------
  * Adjoint gradient.
  * ------------------------------------------------------------------------- */
 

@@ -252,3 +252,47 @@ def objective_and_grad(node, elem, bdflag, kappa, u_obs, f=None, gD=None, gN=Non
     rhs = np.where(asm.is_d.astype(bool), 0.0, r)
     lam, _, _ = solve_rhs(asm, rhs, rtol=rtol)
     return J, grad(node, elem, u, lam), u, lam
+
+
+def measures(node, elem):
+    """|t| of every simplex: |det(x_1 - x_0, ..., x_d - x_0)| / d!."""
+    node = np.asarray(node, np.float64)
+    elem = np.asarray(elem)
+    dim = node.shape[0]
+    out = np.zeros(elem.shape[1])
+    for t in range(elem.shape[1]):
+        x0 = node[:, elem[0, t]]
+        M = np.array([node[:, elem[a, t]] - x0 for a in range(1, dim + 1)])
+        out[t] = abs(np.linalg.det(M)) / (2.0 if dim == 2 else 6.0)
+    return out
+
+
+def neumann_solve(asm: Assembled, node, elem, rtol: float = 1e-13, method: str = "auto"):
+    """Pure Neumann problem (Section 3.3, equations (compatible) and (meanb)).
+
+    1. b <- b - mean(b), the discrete compatibility condition;
+    2. fix u = 0 at the first vertex and solve A(free, free) u(free) = b(free) with
+       free = all other vertices (equation (directsolve) with freeNode = 2:N);
+    3. shift u by c = sum_t |t| mean(u(elem_t)) / sum_t |t|, so that u has zero mean.
+    Returns (u, iters, relres, mean_b)."""
+    if asm.is_d.any():
+        raise ValueError("a pure Neumann problem has no Dirichlet vertex")
+    N = asm.b.size
+    mean_b = float(asm.b.sum()) / N
+    b = asm.b - mean_b
+    b[0] = 0.0
+    pin = np.zeros(N, np.uint8)
+    pin[0] = 1
+    val_pin = asm.val.copy()
+    for i in range(N):
+        for q in range(asm.rowptr[i], asm.rowptr[i + 1]):
+            if i == 0:
+                val_pin[q] = 1.0 if asm.colind[q] == 0 else 0.0
+            elif asm.colind[q] == 0:
+                val_pin[q] = 0.0
+    tmp = Assembled(asm.rowptr, asm.colind, asm.val, val_pin, b, asm.b_load, pin, asm.b_scale)
+    u, it, rel = solve(tmp, np.zeros(N), rtol=rtol, method=method)
+    area = measures(node, elem)
+    elem = np.asarray(elem)
+    c = float(np.sum(area * u[elem].mean(axis=0))) / float(np.sum(area))
+    return u - c, it, rel, mean_b

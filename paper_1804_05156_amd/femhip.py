@@ -25,7 +25,8 @@ FE_FN_ZERO, FE_FN_CONST, FE_FN_LINEAR, FE_FN_SINPROD, FE_FN_DUDN_SINPROD, FE_FN_
 ENTRY_POINTS = (
     "fe_version", "fe_status_string", "fe_plan_workspace_bytes", "fe_plan_create", "fe_plan_pattern",
     "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_spmv",
-    "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_grad", "fe_batch_solve_workspace_bytes",
+    "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_neumann_workspace_bytes", "fe_neumann_solve",
+    "fe_grad", "fe_batch_solve_workspace_bytes",
     "fe_batch_solve", "fe_batch_create", "fe_batch_set_grid", "fe_batch_get_info", "fe_batch_assemble_solve",
     "fe_batch_destroy", "fe_prof_enable", "fe_prof_read",
 )
@@ -85,6 +86,9 @@ def _load():
         "fe_solve_workspace_bytes": ([I64, C.POINTER(SZ)], C.c_int),
         "fe_solve": ([I64, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), P], C.c_int),
         "fe_grad": ([P, P, P, P, P, P], C.c_int),
+        "fe_neumann_workspace_bytes": ([P, I64, C.POINTER(SZ)], C.c_int),
+        "fe_neumann_solve": ([P, P, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), C.POINTER(D), P],
+                             C.c_int),
         "fe_select": ([I64, P, P, P, P, P], C.c_int),
         "fe_batch_solve_workspace_bytes": ([I64, I32, C.POINTER(SZ)], C.c_int),
         "fe_batch_solve": ([I32, P, P, P, P, P, P, D, I32, I32, I32, P, SZ, P, P, P], C.c_int),
@@ -243,6 +247,27 @@ def fe_solve(rowptr, colind, val, b, u, rtol: float, maxit: int, ws, stream=None
     return int(it.value), float(rel.value), rc
 
 
+def fe_neumann_workspace_bytes(plan, nnz: int) -> int:
+    s = C.c_size_t()
+    _check(_lib.fe_neumann_workspace_bytes(plan, int(nnz), C.byref(s)), "fe_neumann_workspace_bytes")
+    return int(s.value)
+
+
+def fe_neumann_solve(plan, node, rowptr, colind, val, b, u, rtol: float, maxit: int, ws, stream=None,
+                     allow_noconv=False):
+    """Returns (iters, relres, mean_b, status)."""
+    it = C.c_int32()
+    rel = C.c_double()
+    mb = C.c_double()
+    rc = _lib.fe_neumann_solve(plan, _ptr(node, torch.float64, "node"), _ptr(rowptr, torch.int32),
+                               _ptr(colind, torch.int32), _ptr(val, torch.float64, "val"), _ptr(b, torch.float64, "b"),
+                               _ptr(u, torch.float64, "u"), float(rtol), int(maxit), _ptr(ws, torch.uint8, "ws"),
+                               ws.numel(), C.byref(it), C.byref(rel), C.byref(mb), _stream(stream))
+    if not (rc == FE_ENOCONV and allow_noconv):
+        _check(rc, "fe_neumann_solve")
+    return int(it.value), float(rel.value), float(mb.value), rc
+
+
 def fe_grad(plan, node, u, lam, g, stream=None):
     _check(_lib.fe_grad(plan, _ptr(node, torch.float64, "node"), _ptr(u, torch.float64, "u"),
                         _ptr(lam, torch.float64, "lam"), _ptr(g, torch.float64, "g"), _stream(stream)), "fe_grad")
@@ -398,6 +423,14 @@ class Plan:
         it, rel, _ = fe_solve(self.rowptr, self.colind, asm.val_bc, b, u, rtol, maxit, self.solve_workspace(),
                               stream)
         return u, it, rel
+
+    def neumann_solve(self, asm: Assembly, rtol=1e-10, maxit=100000, node=None, stream=None):
+        """Pure Neumann problem: zero-mean u with A u = b - mean(b); returns (u, iters, relres, mean_b)."""
+        ws = torch.empty(fe_neumann_workspace_bytes(self.handle, self.nnz), dtype=torch.uint8, device=asm.b.device)
+        u = torch.empty_like(asm.b)
+        it, rel, mb, _ = fe_neumann_solve(self.handle, self.node if node is None else node, self.rowptr,
+                                          self.colind, asm.val, asm.b, u, rtol, maxit, ws, stream)
+        return u, it, rel, mb
 
     def grad(self, u, lam, node=None, stream=None):
         g = torch.empty(self.NT, dtype=torch.float64, device=u.device)

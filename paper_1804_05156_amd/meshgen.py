@@ -213,8 +213,8 @@ def lshape_mesh(n: int, *, seed: int | None = None, kappa: str = "one") -> Mesh:
     used[elem.ravel()] = True
     newid = -np.ones(full.n_node, np.int64)
     newid[used] = np.arange(int(used.sum()))
-    node = full.node[:, used]
-    elem = newid[elem].astype(np.int32)
+    node = np.ascontiguousarray(full.node[:, used])
+    elem = np.ascontiguousarray(newid[elem].astype(np.int32))
     # boundary faces: faces that belong to exactly one element
     nt = elem.shape[1]
     bd = np.zeros((3, nt), np.int8)

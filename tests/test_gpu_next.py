@@ -1,0 +1,136 @@
+"""Rows next to the core path: the pure Neumann problem (Section 3.3, equations
+(compatible) and (meanb)) and the L-shaped domain of Section 1.1, on the GPU
+against the oracle.
+
+Pure Neumann: the oracle fixes vertex 0, solves directly and shifts u to zero
+mean; the GPU runs the same steps with PCG.  Both results are the unique zero-mean
+solution of A u = b - mean(b), so they agree to the solver tolerance:
+||u - u*|| <= cond rtol ||u*||, checked with the generous cond <= 1e4 N used by the
+other solve tests.  L-shape: assembly parity (pattern bit-exact, values in the
+1e-12 scale of the other parity tests) and the solve against the direct solve.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1804_05156_amd import meshgen
+from gpu_helpers import compare, data_scale, fns, host, log, run_gpu, to_dev
+
+pytestmark = pytest.mark.gpu
+
+FE_FN_CONST, FE_FN_LINEAR, FE_FN_NODAL = 1, 2, 5
+
+
+def _cos_nodal(m):
+    exact = np.prod(np.cos(math.pi * m.node), axis=0)
+    return exact, m.dim * math.pi ** 2 * exact
+
+
+def _area_mean(m, u):
+    area = oracle.measures(m.node, m.elem)
+    return float(np.sum(area * u[m.elem].mean(axis=0))) / float(np.sum(area))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_pure_neumann_matches_oracle(dim):
+    log(f"case: pure Neumann vs oracle dim={dim}")
+    if dim == 2:
+        m = meshgen.square_mesh(25, jitter=0.2, permute=True, seed=71, kappa="lognormal", sides=(2, 2, 2, 2))
+    else:
+        m = meshgen.kuhn_cube(7, jitter=0.15, permute=True, seed=71, kappa="lognormal", faces=(2,) * 6)
+    _, fv = _cos_nodal(m)
+    specs = [(FE_FN_NODAL, (0.0,), fv)]
+    (f, fo), _, _ = fns(*specs)
+    plan, asm = run_gpu(m, None, f)
+    u, it, rel, mb = plan.neumann_solve(asm, rtol=1e-13)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy()
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo)
+    compare(host(plan, asm), ora, data=data_scale(m, specs))
+    uo, _, _, mbo = oracle.neumann_solve(ora, m.node, m.elem, method="direct")
+    log(f"  iterations {it}, relres {rel:.2e}, mean(b) {mb:.3e} vs {mbo:.3e}")
+    assert rel <= 1e-13 and it > 0
+    assert abs(mb - mbo) <= 1e-12 * np.abs(ora.b).max()
+    assert np.abs(u - uo).max() <= 1e-13 * 1e4 * m.n_node * np.abs(uo).max()
+    assert abs(_area_mean(m, u)) <= 1e-12 * np.abs(u).max()
+    # A u = b - mean(b) at every row, the fixed one included
+    r = oracle.spmv(ora.rowptr, ora.colind, ora.val, u) - (ora.b - mbo)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(ora.b - mbo)
+
+
+def test_pure_neumann_second_order_convergence_gpu():
+    """u = cos(pi x) cos(pi y) (zero mean, du/dn = 0): L2 error decays like h^2."""
+    log("case: pure Neumann convergence")
+    errs = []
+    for n in (17, 33, 65, 129):
+        m = meshgen.square_mesh(n, sides=(2, 2, 2, 2))
+        exact, fv = _cos_nodal(m)
+        (f, _), _, _ = fns((FE_FN_NODAL, (0.0,), fv))
+        plan, asm = run_gpu(m, None, f)
+        u, _, _, _ = plan.neumann_solve(asm, rtol=1e-12)
+        u = u.cpu().numpy()
+        x, y = m.node
+        X, Y = x[m.elem], y[m.elem]
+        area = 0.5 * np.abs((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]))
+        U = u[m.elem]
+        s = 0.0
+        for k in range(3):
+            i, j = (k + 1) % 3, (k + 2) % 3
+            e = np.cos(math.pi * (X[i] + X[j]) / 2) * np.cos(math.pi * (Y[i] + Y[j]) / 2) - (U[i] + U[j]) / 2
+            s += float(np.sum(area / 3 * e * e))
+        errs.append(math.sqrt(s))
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    log(f"  L2 errors {errs} rates {rates}")
+    assert all(1.9 < r < 2.1 for r in rates)
+
+
+def test_pure_neumann_rejects_dirichlet_and_repeats_bitwise():
+    from paper_1804_05156_amd import femhip
+    log("case: pure Neumann argument checks, determinism")
+    m = meshgen.square_mesh(9)
+    plan, asm = run_gpu(m)
+    with pytest.raises(femhip.FemhipError) as e:
+        plan.neumann_solve(asm)
+    assert e.value.code == femhip.FE_EINVAL
+    m = meshgen.square_mesh(65, jitter=0.2, permute=True, seed=72, kappa="lognormal", sides=(2, 2, 2, 2))
+    _, fv = _cos_nodal(m)
+    (f, _), _, _ = fns((FE_FN_NODAL, (0.0,), fv))
+    plan, asm = run_gpu(m, None, f)
+    u1, i1, r1, m1 = plan.neumann_solve(asm, rtol=1e-10)
+    u2, i2, r2, m2 = plan.neumann_solve(asm, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert (i1, r1, m1) == (i2, r2, m2) and torch.equal(u1, u2)
+
+
+@pytest.mark.parametrize("n", [9, 17])
+def test_lshape_assembly_and_solve(n):
+    """The L-shaped domain (-1,1)^2 minus the lower right quadrant, lognormal kappa,
+    f = 1, g_D = 0: assembly parity and the solve against the direct solve."""
+    log(f"case: L-shape n={n}")
+    m = meshgen.lshape_mesh(n, seed=80 + n, kappa="lognormal")
+    specs = [(FE_FN_CONST, (1.0,))]
+    (f, fo), _, _ = fns(*specs)
+    plan, asm = run_gpu(m, None, f)
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo)
+    worst = compare(host(plan, asm), ora, data=data_scale(m, specs))
+    u, it, rel = plan.solve(asm, rtol=1e-13)
+    u = u.cpu().numpy()
+    uo, _, _ = oracle.solve(ora, method="direct")
+    log(f"  worst scaled value error {worst:.2e}, iterations {it}")
+    assert np.abs(u - uo).max() <= 1e-13 * 1e4 * m.n_node * np.abs(uo).max()
+
+
+def test_lshape_linear_solution_reproduced():
+    """f = 0, constant kappa, linear g_D on the L-shape: u_h is the linear function
+    (the re-entrant corner does not matter for a function in the finite element space)."""
+    log("case: L-shape linear reproduction")
+    m = meshgen.lshape_mesh(21)
+    c = (0.25, -1.5, 0.75)
+    (f, _), (gd, _), _ = fns(None, (FE_FN_LINEAR, c))
+    plan, asm = run_gpu(m, None, None, gd)
+    u, _, _ = plan.solve(asm, rtol=1e-14)
+    exact = c[0] + c[1] * m.node[0] + c[2] * m.node[1]
+    assert np.abs(u.cpu().numpy() - exact).max() < 1e-10

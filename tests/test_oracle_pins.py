@@ -484,6 +484,63 @@ def test_second_order_convergence_3d_mixed():
     assert all(1.9 < r < 2.3 for r in rates), rates
 
 
+# --------------------------------------------------------------------------- pure Neumann problem
+def _cos_problem(n, seed=None, jitter=0.0):
+    """u = cos(pi x) cos(pi y) on the unit square: f = 2 pi^2 u, du/dn = 0 on every side,
+    zero mean.  f enters as nodal values (its P1 interpolant)."""
+    m = meshgen.square_mesh(n, jitter=jitter, permute=seed is not None, seed=seed, sides=(2, 2, 2, 2))
+    exact = np.cos(math.pi * m.node[0]) * np.cos(math.pi * m.node[1])
+    f = Fn(FN_NODAL, (0.0,), 2 * math.pi ** 2 * exact)
+    return m, f, exact
+
+
+def test_pure_neumann_second_order_convergence():
+    """Section 3.3: with b shifted to mean zero, one vertex fixed and the zero-mean
+    shift applied, the discrete solution converges like h^2 to the zero-mean exact
+    solution u = cos(pi x) cos(pi y)."""
+    errs = []
+    for n in (9, 17, 33):
+        m, f, exact = _cos_problem(n)
+        a = oracle.assemble(m.node, m.elem, m.bdflag, None, f=f)
+        u, _, _, _ = oracle.neumann_solve(a, m.node, m.elem, method="direct")
+        errs.append(_l2_error_cos(m, u))
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    assert all(1.8 < r < 2.2 for r in rates), rates
+
+
+def _l2_error_cos(m, u_h):
+    s = 0.0
+    x, y = m.node
+    for t in range(m.n_elem):
+        v = m.elem[:, t]
+        area = 0.5 * abs((x[v[1]] - x[v[0]]) * (y[v[2]] - y[v[0]]) - (x[v[2]] - x[v[0]]) * (y[v[1]] - y[v[0]]))
+        for k in range(3):
+            i, j = v[(k + 1) % 3], v[(k + 2) % 3]
+            mx, my = (x[i] + x[j]) / 2, (y[i] + y[j]) / 2
+            e = math.cos(math.pi * mx) * math.cos(math.pi * my) - (u_h[i] + u_h[j]) / 2
+            s += area / 3 * e * e
+    return math.sqrt(s)
+
+
+def test_pure_neumann_properties():
+    """Equation (meanb): after the shift b sums to zero, so A u = b - mean(b) holds at
+    every row, the fixed one included (the rows of A sum to zero); the result has
+    zero area-weighted mean; constant kappa scaling divides u by the constant."""
+    m, f, _ = _cos_problem(13, seed=5, jitter=0.2)
+    a = oracle.assemble(m.node, m.elem, m.bdflag, None, f=f)
+    u, _, _, mean_b = oracle.neumann_solve(a, m.node, m.elem, method="direct")
+    r = oracle.spmv(a.rowptr, a.colind, a.val, u) - (a.b - mean_b)
+    assert np.abs(r).max() <= 1e-12 * np.abs(a.b).max()
+    area = oracle.measures(m.node, m.elem)
+    assert abs(float(np.sum(area * u[m.elem].mean(axis=0)))) <= 1e-14 * np.abs(u).max()
+    a3 = oracle.assemble(m.node, m.elem, m.bdflag, np.full(m.n_elem, 3.0), f=f)
+    u3, _, _, _ = oracle.neumann_solve(a3, m.node, m.elem, method="direct")
+    assert np.abs(3.0 * u3 - u).max() <= 1e-12 * np.abs(u).max()
+    with pytest.raises(ValueError):
+        md = meshgen.square_mesh(5)
+        oracle.neumann_solve(oracle.assemble(md.node, md.elem, md.bdflag), md.node, md.elem)
+
+
 # --------------------------------------------------------------------------- adjoint gradient
 def _fd_setup():
     m = meshgen.square_mesh(17, jitter=0.2, seed=517, kappa="lognormal")
