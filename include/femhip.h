@@ -37,7 +37,7 @@ typedef enum fe_status {
     FE_OK = 0,
     FE_EINVAL = -1,        /* bad argument: NULL pointer, bad size, index out of range, kappa <= 0 */
     FE_EMESH = -2,         /* element with non-positive or non-finite measure, repeated vertex */
-    FE_EUNSUPPORTED = -3,  /* dim not 2 or 3, boundary type 3 (Robin) */
+    FE_EUNSUPPORTED = -3,  /* dim not 2 or 3 */
     FE_EOVERFLOW = -4,     /* a count exceeds the int32 index space */
     FE_ESIZE = -5,         /* workspace smaller than the size query returned */
     FE_EHIP = -6,          /* a HIP runtime call failed */
@@ -110,7 +110,7 @@ int fe_plan_workspace_bytes(const fe_mesh *mesh, size_t *bytes);
  * and returns nnz in *nnz (host).  The plan keeps pointers to mesh->elem and
  * mesh->bdflag, which must stay valid and unchanged while the plan lives.
  * Errors: FE_EINVAL (NULL, sizes, vertex index out of range, bdflag code not in
- * 0..3), FE_EUNSUPPORTED (dim, bdflag 3), FE_EMESH (repeated vertex in an
+ * 0..3), FE_EUNSUPPORTED (dim), FE_EMESH (repeated vertex in an
  * element), FE_EOVERFLOW, FE_ESIZE, FE_EHIP, and FE_ELIMIT when the mesh exceeds
  * the fixed capacities: more than 2^26 vertices, or a vertex with more than 32
  * (2D) or 64 (3D) distinct neighbours, itself included. */
@@ -150,10 +150,22 @@ int fe_plan_destroy(fe_plan *plan);
  * node: device coordinates (same layout as fe_mesh.node).  kappa: device, NT values
  * > 0, or NULL for kappa = 1.  f, g_d, g_n: host structs, NULL = zero.  val and b are
  * required; val_bc, b_load and is_dirichlet may be NULL.  Duplicates are added in
- * ascending element order, so results are bitwise reproducible. */
+ * ascending element order, so results are bitwise reproducible.  Robin sides (bdflag
+ * 3) are treated as kappa grad(u).n = 0 here; see fe_assemble_robin. */
 int fe_assemble(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
                 const fe_fn *g_d, const fe_fn *g_n, double *val, double *val_bc, double *b,
                 double *b_load, uint8_t *is_dirichlet, void *stream);
+
+/* As fe_assemble, with Robin sides (bdflag 3, Section 1.2) carrying
+ * kappa grad(u).n + robin_alpha u = g_r: the side mass term robin_alpha |F| (1 +
+ * delta_ij) / (d (d+1)) joins A on the side's vertices (and is lifted like the
+ * stiffness at Dirichlet vertices), and g_r enters b_load by the midpoint (2-D) /
+ * centroid (3-D) rule, as g_n does.  robin_alpha >= 0 (else FE_EINVAL); g_r may be
+ * NULL (zero).  fe_assemble is this call with robin_alpha = 0 and g_r = NULL. */
+int fe_assemble_robin(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                      const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
+                      double *val, double *val_bc, double *b, double *b_load,
+                      uint8_t *is_dirichlet, void *stream);
 
 /* y = A x for a CSR matrix (device arrays; n rows). */
 int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,

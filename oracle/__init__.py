@@ -78,11 +78,13 @@ def lib():
         _lib.oracle_local_stiffness.argtypes = [C.c_int, P, P, P, P, P]
         _lib.oracle_assemble.argtypes = [C.c_int, I64, I64, P, P, P, P, P, P, P, I64,
                                          P, P, P, P, P, P, P, P, P]
+        _lib.oracle_assemble_robin.argtypes = [C.c_int, I64, I64, P, P, P, P, P, P, P, P, C.c_double, I64,
+                                               P, P, P, P, P, P, P, P, P]
         _lib.oracle_solve.argtypes = [I64, P, P, P, P, P, P, C.c_double, I64, C.c_int, P, P]
         _lib.oracle_grad.argtypes = [C.c_int, I64, I64, P, P, P, P, P]
         _lib.oracle_spmv.argtypes = [I64, P, P, P, P, P]
         for name in ("oracle_coo_to_csr", "oracle_local_stiffness", "oracle_assemble",
-                     "oracle_solve", "oracle_grad", "oracle_spmv"):
+                     "oracle_assemble_robin", "oracle_solve", "oracle_grad", "oracle_spmv"):
             getattr(_lib, name).restype = C.c_int
     return _lib
 
@@ -163,8 +165,9 @@ class Assembled:
 
 
 def assemble(node, elem, bdflag=None, kappa=None, f: Fn | None = None, gD: Fn | None = None,
-             gN: Fn | None = None) -> Assembled:
-    """Assemble A (CSR), the lifted right-hand side b and the boundary data."""
+             gN: Fn | None = None, gR: Fn | None = None, alpha: float = 0.0) -> Assembled:
+    """Assemble A (CSR), the lifted right-hand side b and the boundary data.  Robin
+    sides (bdflag 3) use kappa grad(u).n + alpha u = g_R."""
     node = np.ascontiguousarray(node, np.float64)
     elem = np.ascontiguousarray(elem, np.int32)
     dim = node.shape[0]
@@ -182,11 +185,11 @@ def assemble(node, elem, bdflag=None, kappa=None, f: Fn | None = None, gD: Fn | 
     is_d = np.zeros(N, np.uint8)
     b_scale = np.zeros(N)
     nnz = np.zeros(1, np.int64)
-    fs = [x._c() if x is not None else None for x in (f, gD, gN)]
+    fs = [x._c() if x is not None else None for x in (f, gD, gN, gR)]
     refs = [C.byref(x) if x is not None else None for x in fs]
-    st = lib().oracle_assemble(dim, N, NT, _p(node), _p(elem), _p(bd), _p(kp), refs[0], refs[1],
-                               refs[2], cap, _p(rowptr), _p(colind), _p(val), _p(val_bc), _p(b),
-                               _p(b_load), _p(is_d), _p(b_scale), _p(nnz))
+    st = lib().oracle_assemble_robin(dim, N, NT, _p(node), _p(elem), _p(bd), _p(kp), refs[0], refs[1],
+                                     refs[2], refs[3], C.c_double(alpha), cap, _p(rowptr), _p(colind), _p(val),
+                                     _p(val_bc), _p(b), _p(b_load), _p(is_d), _p(b_scale), _p(nnz))
     if st:
         raise OracleError(st, "assemble")
     k = int(nnz[0])

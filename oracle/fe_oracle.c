@@ -279,27 +279,59 @@ static void gather_coords(int dim, int64_t N, int64_t NT, const double *node, co
  *               rounding tolerances)
  *   *nnz        number of stored entries
  */
+/* Robin sides (bdflag 3) carry kappa grad(u).n + alpha u = g_R: the side mass term
+ * alpha int_F u v joins A and int_F g_R v joins b.  oracle_assemble is the case
+ * alpha = 0, g_R = 0. */
+int oracle_assemble_robin(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
+                          const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
+                          const or_fn *gN, const or_fn *gR, double alpha_r, int64_t nnz_cap,
+                          int64_t *rowptr, int64_t *colind, double *val, double *val_bc, double *b,
+                          double *b_load, uint8_t *is_d, double *b_scale, int64_t *nnz);
+
 int oracle_assemble(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
                     const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
                     const or_fn *gN, int64_t nnz_cap, int64_t *rowptr, int64_t *colind, double *val,
                     double *val_bc, double *b, double *b_load, uint8_t *is_d, double *b_scale,
                     int64_t *nnz)
 {
+    return oracle_assemble_robin(dim, N, NT, node, elem, bdflag, kappa, f, gD, gN, NULL, 0.0, nnz_cap,
+                                 rowptr, colind, val, val_bc, b, b_load, is_d, b_scale, nnz);
+}
+
+/* Measure of the side opposite local vertex a and its outward unit normal, from the
+ * gradient of lambda_a: |t| = |F| h / d with h = 1 / |grad lambda_a|. */
+static double side_measure(int dim, double meas, const double *G, int a, double *nrm)
+{
+    double gn = 0.0;
+    for (int c = 0; c < dim; ++c) gn += G[a * dim + c] * G[a * dim + c];
+    gn = sqrt(gn);
+    for (int c = 0; c < dim; ++c) nrm[c] = -G[a * dim + c] / gn;
+    return dim * meas * gn;
+}
+
+int oracle_assemble_robin(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
+                          const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
+                          const or_fn *gN, const or_fn *gR, double alpha_r, int64_t nnz_cap,
+                          int64_t *rowptr, int64_t *colind, double *val, double *val_bc, double *b,
+                          double *b_load, uint8_t *is_d, double *b_scale, int64_t *nnz)
+{
     if (dim != 2 && dim != 3) return OR_EUNSUPPORTED;
     const int nv = dim + 1;
     if (N <= 0 || NT < 0 || nnz_cap < (int64_t)nv * nv * NT) return OR_EINVAL;
+    if (!(alpha_r >= 0.0) || !isfinite(alpha_r)) return OR_EINVAL;
     for (int64_t k = 0; k < (int64_t)nv * NT; ++k)
         if (elem[k] < 0 || elem[k] >= N) return OR_EINVAL;
+    int64_t nrobin = 0;
     if (bdflag)
         for (int64_t k = 0; k < (int64_t)nv * NT; ++k) {
-            if (bdflag[k] == 3) return OR_EUNSUPPORTED;
             if (bdflag[k] < 0 || bdflag[k] > 3) return OR_EINVAL;
+            if (bdflag[k] == 3) ++nrobin;
         }
     if (kappa)
         for (int64_t t = 0; t < NT; ++t)
             if (!(kappa[t] > 0.0) || !isfinite(kappa[t])) return OR_EINVAL;
 
-    const int64_t ns = (int64_t)nv * nv * NT;
+    const int64_t ns = (int64_t)nv * nv * NT + nrobin * dim * dim;
     int64_t *ii = malloc((size_t)(ns > 0 ? ns : 1) * sizeof(int64_t));
     int64_t *jj = malloc((size_t)(ns > 0 ? ns : 1) * sizeof(int64_t));
     double *ss = malloc((size_t)(ns > 0 ? ns : 1) * sizeof(double));
@@ -330,7 +362,29 @@ int oracle_assemble(int dim, int64_t N, int64_t NT, const double *node, const in
             }
     }
     if (status != OR_OK) goto done;
-    status = oracle_coo_to_csr(N, N, ns, ii, jj, ss, rowptr, colind, val, nnz);
+    /* Robin side mass matrices alpha |F| (1 + delta_ij) / (d (d+1)) on the side's d
+     * vertices, in the stacked side order (sides opposite vertex 1, then 2, ...). */
+    for (int a = 0; a < nv && status == OR_OK && nrobin > 0; ++a)
+        for (int64_t t = 0; t < NT; ++t) {
+            if (bdflag[(int64_t)a * NT + t] != 3) continue;
+            gather_coords(dim, N, NT, node, elem, t, p, verts);
+            status = oracle_local_stiffness(dim, p, K, G, &meas, &sgn);
+            if (status != OR_OK) break;
+            double nrm[3];
+            const double fmeas = side_measure(dim, meas, G, a, nrm);
+            for (int e = 0; e < nv; ++e) {
+                if (e == a) continue;
+                for (int e2 = 0; e2 < nv; ++e2) {
+                    if (e2 == a) continue;
+                    ii[idx] = verts[e];
+                    jj[idx] = verts[e2];
+                    ss[idx] = alpha_r * fmeas * (e == e2 ? 2.0 : 1.0) / (dim * (dim + 1));
+                    ++idx;
+                }
+            }
+        }
+    if (status != OR_OK) goto done;
+    status = oracle_coo_to_csr(N, N, idx, ii, jj, ss, rowptr, colind, val, nnz);
     if (status != OR_OK) goto done;
 
     /* Load vector (Section 3.2): per-element contributions bt[a*NT + t]. */
@@ -379,28 +433,26 @@ int oracle_assemble(int dim, int64_t N, int64_t NT, const double *node, const in
             b_scale[v] += fabs(bt[a * NT + t]);
         }
 
-    /* Neumann sides (Section 3.3): midpoint (2-D) / centroid (3-D) rule.  Sides are
-     * taken in the stacked order [faces opposite vertex 1; opposite vertex 2; ...]. */
+    /* Neumann (type 2) and Robin (type 3) sides (Section 3.3): midpoint (2-D) /
+     * centroid (3-D) rule for g_N, g_R.  Sides are taken in the stacked order [faces
+     * opposite vertex 1; opposite vertex 2; ...]. */
     if (bdflag) {
         for (int a = 0; a < nv; ++a)
             for (int64_t t = 0; t < NT; ++t) {
-                if (bdflag[(int64_t)a * NT + t] != 2) continue;
+                const int8_t code = bdflag[(int64_t)a * NT + t];
+                if (code != 2 && code != 3) continue;
                 gather_coords(dim, N, NT, node, elem, t, p, verts);
                 status = oracle_local_stiffness(dim, p, K, G, &meas, &sgn);
                 if (status != OR_OK) goto done;
-                /* outward unit normal of the face opposite a: -grad(lambda_a)/|grad(lambda_a)| */
-                double gn = 0.0, nrm[3];
-                for (int c = 0; c < dim; ++c) gn += G[a * dim + c] * G[a * dim + c];
-                gn = sqrt(gn);
-                for (int c = 0; c < dim; ++c) nrm[c] = -G[a * dim + c] / gn;
-                /* face measure: |t| = |F| h / d and h = 1/|grad lambda_a| */
-                double fmeas = dim * meas * gn;
+                /* outward unit normal of the face opposite a, and the face measure */
+                double nrm[3];
+                const double fmeas = side_measure(dim, meas, G, a, nrm);
                 double x[3] = {0, 0, 0}, bary[4];
                 for (int e = 0; e < nv; ++e) {
                     bary[e] = (e == a) ? 0.0 : 1.0 / dim;
                     for (int c = 0; c < dim; ++c) x[c] += bary[e] * p[e * dim + c];
                 }
-                double g = fn_eval(gN, dim, x, nv, bary, verts, nrm);
+                double g = fn_eval(code == 2 ? gN : gR, dim, x, nv, bary, verts, nrm);
                 double share = fmeas * g / dim;
                 for (int e = 0; e < nv; ++e) {
                     if (e == a) continue;

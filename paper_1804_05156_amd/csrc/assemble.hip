@@ -20,6 +20,8 @@
 // the main kernel (elemp[t], kappa[t], xyp[p]) are then spatially coherent even
 // when the vertex labels are a random permutation; the only label-ordered
 // accesses left are the row's own outputs.
+#include <cmath>
+
 #include "fe_internal.h"
 
 namespace {
@@ -31,7 +33,8 @@ struct AsmArgs {
     const int2 *pincm;
     const uint32_t *prow_info;
     const double *xyp, *fp;
-    DevFn f, gd, gn;
+    DevFn f, gd, gn, gr;
+    double ralpha;         // Robin coefficient alpha (kappa grad(u).n + alpha u = g_R)
     double *valp;          // rows in processing order: row k at prowptr[k] + 2k, its values
                            // followed by (b, b_load)
     int32_t *status;
@@ -207,8 +210,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
             const double k00 = sc * (E0x * E0x + E0y * E0y);
             const double k01 = sc * (E0x * E1x + E0y * E1y);
             const double k02 = sc * (E0x * E2x + E0y * E2y);
-            const int o1 = (meta >> Meta<3>::OFF) & 0xff;
-            const int o2 = (meta >> (Meta<3>::OFF + 8)) & 0xff;
+            const int o1 = (meta >> Meta<3>::OFF) & Meta<3>::OMASK;
+            const int o2 = (meta >> (Meta<3>::OFF + Meta<3>::OB)) & Meta<3>::OMASK;
             acc[diag * BLOCK + tid] += k00;
             acc[o1 * BLOCK + tid] += k01;
             acc[o2 * BLOCK + tid] += k02;
@@ -249,8 +252,43 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                     bsum += L * g / 2.0;
                 }
             }
-            // Dirichlet columns: lift b by K[0][c] u_D(c)
             const uint32_t db = (meta >> Meta<3>::DBIT) & 3u;
+            // Robin sides through the row's vertex: side mass alpha |F| (1 + delta) / 6
+            // (lifted like the stiffness when the other end is a Dirichlet node) and
+            // g_R by the midpoint rule
+            const uint32_t rb = (meta >> Meta<3>::RBIT) & 3u;
+            if (rb) {
+                for (int jj = 0; jj < 2; ++jj) {
+                    if (!((rb >> jj) & 1u)) continue;
+                    const double2 Xo = jj == 0 ? X2[u] : X1[u];         // other end of the side
+                    const double ex = jj == 0 ? E1x : E2x, ey = jj == 0 ? E1y : E2y;
+                    const double L = sqrt(ex * ex + ey * ey);
+                    const double m1 = A.ralpha * L / 6.0;
+                    acc[diag * BLOCK + tid] += A.ralpha * L / 3.0;
+                    acc[(jj == 0 ? o2 : o1) * BLOCK + tid] += m1;
+                    const uint32_t other_d = jj == 0 ? (db >> 1) & 1u : db & 1u;
+                    if (other_d && A.gd.kind != FE_FN_ZERO) {
+                        const double xo[2] = {Xo.x, Xo.y};
+                        lift += m1 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[jj == 0 ? p2[u] : p1[u]] : 0,
+                                                        xo);
+                    }
+                    if (A.gr.kind != FE_FN_ZERO) {
+                        const double mid[2] = {0.5 * (X0.x + Xo.x), 0.5 * (X0.y + Xo.y)};
+                        double g;
+                        if (A.gr.kind == FE_FN_DUDN_SINPROD) {
+                            const double nrm[2] = {ey / L, -ex / L};
+                            g = fn_dudn<2>(A.gr, mid, nrm);
+                        } else if (A.gr.kind == FE_FN_NODAL) {
+                            const int32_t vo = A.pi[jj == 0 ? p2[u] : p1[u]];
+                            g = 0.5 * (A.gr.nodal[A.pi[k]] + A.gr.nodal[vo]);
+                        } else {
+                            g = fn_point<2>(A.gr, mid);
+                        }
+                        bsum += L * g / 2.0;
+                    }
+                }
+            }
+            // Dirichlet columns: lift b by K[0][c] u_D(c)
             if (db && A.gd.kind != FE_FN_ZERO) {
                 if (db & 1u) {
                     const double x1[2] = {X1[u].x, X1[u].y};
@@ -369,7 +407,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
             int off[3];
 #pragma unroll
             for (int jj = 0; jj < 3; ++jj) {
-                off[jj] = (meta >> (Meta<4>::OFF + 8 * jj)) & 0xff;
+                off[jj] = (meta >> (Meta<4>::OFF + Meta<4>::OB * jj)) & Meta<4>::OMASK;
                 acc[off[jj] * BLOCK + tid] += kr[jj];
             }
             const double vol = vol6 / 6.0;
@@ -419,6 +457,45 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                 }
             }
             const uint32_t db = (meta >> Meta<4>::DBIT) & 7u;
+            // Robin faces containing Y0 (opposite Y1, Y2, Y3): face mass alpha |F| (1 +
+            // delta) / 12, lifted at Dirichlet face vertices, and g_R at the centroid
+            const uint32_t rb = (meta >> Meta<4>::RBIT) & 7u;
+            if (rb) {
+                const double *nq[3] = {n1, n2, n3};
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    if (!((rb >> jj) & 1u)) continue;
+                    const double *nf = nq[jj];
+                    const double nn = sqrt(dot3(nf, nf));
+                    const double area = 0.5 * nn;
+                    const double m1 = A.ralpha * area / 12.0;
+                    acc[diag * BLOCK + tid] += A.ralpha * area / 6.0;
+                    for (int r = 0; r < 3; ++r) {
+                        if (r == jj) continue;
+                        acc[off[r] * BLOCK + tid] += m1;
+                        if (((db >> r) & 1u) && A.gd.kind != FE_FN_ZERO)
+                            lift += m1 * dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[pq[u][r]] : 0,
+                                                            Y[u][r]);
+                    }
+                    if (A.gr.kind != FE_FN_ZERO) {
+                        double cen[3];
+                        for (int c = 0; c < 3; ++c) cen[c] = (Y0[c] + Y1[c] + Y2[c] + Y3[c] - Y[u][jj][c]) / 3.0;
+                        double g;
+                        if (A.gr.kind == FE_FN_DUDN_SINPROD) {
+                            const double nrm[3] = {-nf[0] / nn, -nf[1] / nn, -nf[2] / nn};
+                            g = fn_dudn<3>(A.gr, cen, nrm);
+                        } else if (A.gr.kind == FE_FN_NODAL) {
+                            double sg = A.gr.nodal[A.pi[k]];
+                            for (int c = 0; c < 3; ++c)
+                                if (c != jj) sg += A.gr.nodal[A.pi[pq[u][c]]];
+                            g = sg / 3.0;
+                        } else {
+                            g = fn_point<3>(A.gr, cen);
+                        }
+                        bsum += area * g / 3.0;
+                    }
+                }
+            }
             if (db && A.gd.kind != FE_FN_ZERO) {
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj) {
@@ -447,13 +524,16 @@ template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream
 
 }  // namespace
 
-extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
-                           const fe_fn *g_d, const fe_fn *g_n, double *val, double *val_bc, double *b,
-                           double *b_load, uint8_t *is_dirichlet, void *stream)
+extern "C" int fe_assemble_robin(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                                 const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
+                                 double *val, double *val_bc, double *b, double *b_load, uint8_t *is_dirichlet,
+                                 void *stream)
 {
     if (!plan || !node || !val || !b) return FE_EINVAL;
     if (!plan->pattern_done) return FE_EINVAL;
-    if (!devfn_valid(f, false) || !devfn_valid(g_d, false) || !devfn_valid(g_n, true)) return FE_EINVAL;
+    if (!devfn_valid(f, false) || !devfn_valid(g_d, false) || !devfn_valid(g_n, true) || !devfn_valid(g_r, true))
+        return FE_EINVAL;
+    if (!(robin_alpha >= 0.0) || !std::isfinite(robin_alpha)) return FE_EINVAL;
     AsmArgs A{};
     A.N = (int32_t)plan->N;
     A.NT = (int32_t)plan->NT;
@@ -469,6 +549,8 @@ extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kapp
     A.f = make_devfn(f);
     A.gd = make_devfn(g_d);
     A.gn = make_devfn(g_n);
+    A.gr = make_devfn(g_r);
+    A.ralpha = robin_alpha;
     A.valp = plan->valp;
     A.status = plan->status;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -494,4 +576,12 @@ extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kapp
                            (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,
                            (const double *)plan->valp, val, val_bc, b, b_load, is_dirichlet));
     return fe_launch_check();
+}
+
+extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                           const fe_fn *g_d, const fe_fn *g_n, double *val, double *val_bc, double *b,
+                           double *b_load, uint8_t *is_dirichlet, void *stream)
+{
+    return fe_assemble_robin(plan, node, kappa, f, g_d, g_n, nullptr, 0.0, val, val_bc, b, b_load, is_dirichlet,
+                             stream);
 }

@@ -34,18 +34,24 @@ template <> struct RowCaps<3> { static constexpr int COL = 32, BLOCK = 128; };
 template <> struct RowCaps<4> { static constexpr int COL = 64, BLOCK = 64; };
 
 // Incidence metadata word (one per vertex-element incidence, in row order):
-//   bits 0-1                 local index a of the row's vertex in the element
-//   bits 2+8j .. 9+8j        offset within the row of the column of local vertex
-//                            fe_other<NV>(a, j), j = 0..NV-2
-//   bit  2+8(NV-1)+j         that vertex is a Dirichlet node
-//   bit  2+9(NV-1)+j         the side opposite that vertex is a Neumann side
-//                            (the sides opposite the other vertices are the sides
-//                            that contain vertex a)
+//   bits 0-1                  local index a of the row's vertex in the element
+//   bits OFF+OB*j .. +OB-1    offset within the row of the column of local vertex
+//                             fe_other<NV>(a, j), j = 0..NV-2 (OB = 5 bits in 2-D,
+//                             6 in 3-D: rows hold at most 32 / 64 columns)
+//   bit  DBIT+j               that vertex is a Dirichlet node
+//   bit  NBIT+j               the side opposite that vertex is a Neumann side
+//   bit  RBIT+j               the side opposite that vertex is a Robin side
+//                             (the sides opposite the other vertices are the sides
+//                             that contain vertex a)
 template <int NV> struct Meta {
     static constexpr int OFF = 2;
-    static constexpr int DBIT = 2 + 8 * (NV - 1);
-    static constexpr int NBIT = 2 + 9 * (NV - 1);
+    static constexpr int OB = NV == 3 ? 5 : 6;
+    static constexpr uint32_t OMASK = (1u << OB) - 1;
+    static constexpr int DBIT = OFF + OB * (NV - 1);
+    static constexpr int NBIT = DBIT + (NV - 1);
+    static constexpr int RBIT = NBIT + (NV - 1);
 };
+static_assert(Meta<4>::RBIT + 3 <= 32, "metadata word overflow");
 
 // Local order used for the row of local vertex a: the element's vertices are
 // taken as (a, other(a,0), ..., other(a,NV-2)), an even permutation of the stored

@@ -65,7 +65,6 @@ FE_DEV int32_t check_element(const int32_t *__restrict__ elem, const int8_t *__r
     for (int f = 0; f < NV; ++f) {
         code[f] = bd ? bd[(int64_t)f * NT + t] : 0;
         if (code[f] < 0 || code[f] > 3) err |= ERR_BDCODE;
-        else if (code[f] == 3) err |= ERR_ROBIN;
     }
     return err;
 }
@@ -475,12 +474,13 @@ __global__ __launch_bounds__(RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     int m = 0;
                     while (cols[m * B + tid] != c[q][jj]) ++m;   // present by construction
-                    meta |= (uint32_t)m << (Meta<NV>::OFF + 8 * jj);
+                    meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
                     if (dz[q][jj]) {
                         meta |= 1u << (Meta<NV>::DBIT + jj);
                         dmask |= 1ull << m;
                     }
                     if (code[q][jj] == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
+                    if (code[q][jj] == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
                 }
                 R.pincm[s + j0 + q] = make_int2(key[q], (int32_t)meta);
             }

@@ -91,12 +91,13 @@ def fn_bound(spec, dim, xmax=1.5):
     return 0.0
 
 
-def data_scale(m, specs):
-    """Per-row size of the data: load of |f|max plus Neumann terms of |g_N|max (oracle,
-    constant data), and |g_D|max."""
+def data_scale(m, specs, gr=None):
+    """Per-row size of the data: load of |f|max plus Neumann (and Robin) side terms of
+    |g_N|max (|g_R|max) (oracle, constant data), and |g_D|max."""
     f, gd, gn = (list(specs) + [None] * 3)[:3]
-    fb, gb = fn_bound(f, m.dim), fn_bound(gn, m.dim)
-    a = oracle.assemble(m.node, m.elem, m.bdflag, None, f=oracle.Fn(1, (fb,)), gN=oracle.Fn(1, (gb,)))
+    fb, gb, rb = fn_bound(f, m.dim), fn_bound(gn, m.dim), fn_bound(gr, m.dim)
+    a = oracle.assemble(m.node, m.elem, m.bdflag, None, f=oracle.Fn(1, (fb,)), gN=oracle.Fn(1, (gb,)),
+                        gR=oracle.Fn(1, (rb,)))
     return np.abs(a.b_load), fn_bound(gd, m.dim)
 
 

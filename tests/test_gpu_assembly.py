@@ -169,11 +169,16 @@ def test_error_paths():
     with pytest.raises(femhip.FemhipError) as e:
         femhip.Plan(node, bad, bd)
     assert e.value.code == femhip.FE_EMESH
-    b3 = bd.clone()
-    b3[1, 0] = 3                              # Robin side
+    b4 = bd.clone()
+    b4[1, 0] = 4                              # no such boundary type
     with pytest.raises(femhip.FemhipError) as e:
-        femhip.Plan(node, elem, b3)
-    assert e.value.code == femhip.FE_EUNSUPPORTED
+        femhip.Plan(node, elem, b4)
+    assert e.value.code == femhip.FE_EINVAL
+    b3 = bd.clone()
+    b3[1, 0] = 3                              # Robin side: a negative coefficient is rejected
+    with pytest.raises(femhip.FemhipError) as e:
+        femhip.Plan(node, elem, b3).assemble(kap, robin_alpha=-1.0)
+    assert e.value.code == femhip.FE_EINVAL
     cw = elem.clone()
     cw[[0, 1], 4] = cw[[1, 0], 4]             # clockwise element: found by the numeric kernel
     plan = femhip.Plan(node, cw, bd)

@@ -1,6 +1,6 @@
 """Rows next to the core path: the pure Neumann problem (Section 3.3, equations
-(compatible) and (meanb)) and the L-shaped domain of Section 1.1, on the GPU
-against the oracle.
+(compatible) and (meanb)), Robin sides (boundary type 3 of Section 1.2) and the
+L-shaped domain of Section 1.1, on the GPU against the oracle.
 
 Pure Neumann: the oracle fixes vertex 0, solves directly and shifts u to zero
 mean; the GPU runs the same steps with PCG.  Both results are the unique zero-mean
@@ -21,7 +21,7 @@ from gpu_helpers import compare, data_scale, fns, host, log, run_gpu, to_dev
 
 pytestmark = pytest.mark.gpu
 
-FE_FN_CONST, FE_FN_LINEAR, FE_FN_NODAL = 1, 2, 5
+FE_FN_CONST, FE_FN_LINEAR, FE_FN_SINPROD, FE_FN_DUDN_SINPROD, FE_FN_NODAL = 1, 2, 3, 4, 5
 
 
 def _cos_nodal(m):
@@ -134,3 +134,71 @@ def test_lshape_linear_solution_reproduced():
     u, _, _ = plan.solve(asm, rtol=1e-14)
     exact = c[0] + c[1] * m.node[0] + c[2] * m.node[1]
     assert np.abs(u.cpu().numpy() - exact).max() < 1e-10
+
+
+def _robin_case(m, specs, gr_spec, alpha):
+    from paper_1804_05156_amd import femhip
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    (gr, gro), _, _ = fns(gr_spec)
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    asm = plan.assemble(kap, f, gd, gn, gR=gr, robin_alpha=alpha)
+    plan.check()
+    torch.cuda.synchronize()
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno, gR=gro, alpha=alpha)
+    return plan, asm, ora
+
+
+@pytest.mark.parametrize("seed,n", [(1, 6), (2, 17), (3, 33)])
+def test_robin_parity_2d(seed, n):
+    log(f"case: Robin 2d seed={seed} n={n}")
+    rng = np.random.default_rng(300 + seed)
+    sides = tuple(int(x) for x in rng.choice([1, 2, 3], size=4))
+    sides = (3,) + sides[1:] if 3 not in sides else sides
+    m = meshgen.square_mesh(n, jitter=0.2, permute=True, seed=seed, kappa="lognormal", sides=sides)
+    specs = [(FE_FN_SINPROD, (2 * math.pi ** 2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7)), (FE_FN_CONST, (0.9,))]
+    gr_spec = (FE_FN_DUDN_SINPROD, (1.3,)) if seed % 2 else (FE_FN_LINEAR, (0.2, -0.5, 0.4))
+    plan, asm, ora = _robin_case(m, specs, gr_spec, 1.7)
+    worst = compare(host(plan, asm), ora, data=data_scale(m, specs, gr_spec))
+    log(f"  sides {sides}, worst scaled value error {worst:.2e}")
+
+
+@pytest.mark.parametrize("seed,n", [(1, 4), (2, 7)])
+def test_robin_parity_3d(seed, n):
+    log(f"case: Robin 3d seed={seed} n={n}")
+    rng = np.random.default_rng(400 + seed)
+    faces = tuple(int(x) for x in rng.choice([1, 2, 3], size=6))
+    faces = (3,) + faces[1:] if 3 not in faces else faces
+    m = meshgen.kuhn_cube(n, jitter=0.15, permute=True, seed=seed, kappa="lognormal", faces=faces)
+    specs = [(FE_FN_SINPROD, (3 * math.pi ** 2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7, 0.4)), (FE_FN_CONST, (0.6,))]
+    gr_spec = (FE_FN_DUDN_SINPROD, (1.0,)) if seed % 2 else (FE_FN_LINEAR, (0.5, 0.2, 0.1, -0.3))
+    plan, asm, ora = _robin_case(m, specs, gr_spec, 0.8)
+    worst = compare(host(plan, asm), ora, data=data_scale(m, specs, gr_spec))
+    log(f"  faces {faces}, worst scaled value error {worst:.2e}")
+
+
+def test_robin_second_order_convergence_gpu():
+    """All sides Robin, u = cos(pi x) cos(pi y) (du/dn = 0, so g_R = alpha u), f = 2 pi^2 u
+    as nodal data: the GPU solution's L2 error decays like h^2."""
+    log("case: Robin convergence")
+    alpha = 1.5
+    errs = []
+    for n in (17, 33, 65, 129):
+        m = meshgen.square_mesh(n, sides=(3, 3, 3, 3))
+        exact, fv = _cos_nodal(m)
+        plan, asm, _ = _robin_case(m, [(FE_FN_NODAL, (0.0,), fv)], (FE_FN_NODAL, (0.0,), alpha * exact), alpha)
+        u, _, _ = plan.solve(asm, rtol=1e-12)
+        u = u.cpu().numpy()
+        x, y = m.node
+        X, Y = x[m.elem], y[m.elem]
+        area = 0.5 * np.abs((X[1] - X[0]) * (Y[2] - Y[0]) - (X[2] - X[0]) * (Y[1] - Y[0]))
+        U = u[m.elem]
+        s = 0.0
+        for k in range(3):
+            i, j = (k + 1) % 3, (k + 2) % 3
+            e = np.cos(math.pi * (X[i] + X[j]) / 2) * np.cos(math.pi * (Y[i] + Y[j]) / 2) - (U[i] + U[j]) / 2
+            s += float(np.sum(area / 3 * e * e))
+        errs.append(math.sqrt(s))
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    log(f"  L2 errors {errs} rates {rates}")
+    assert all(1.9 < r < 2.1 for r in rates)

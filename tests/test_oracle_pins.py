@@ -404,10 +404,14 @@ def test_neumann_constant_total(dim):
 def test_unsupported_and_invalid_inputs():
     m = meshgen.square_mesh(3)
     bd = m.bdflag.copy()
-    bd[1, 0] = 3
+    bd[1, 0] = 4                                          # no such boundary type
     with pytest.raises(oracle.OracleError) as e:
         oracle.assemble(m.node, m.elem, bd)
-    assert e.value.code == oracle.EUNSUPPORTED
+    assert e.value.code == oracle.EINVAL
+    bd[1, 0] = 3
+    with pytest.raises(oracle.OracleError) as e:          # Robin coefficient must be >= 0
+        oracle.assemble(m.node, m.elem, bd, alpha=-1.0)
+    assert e.value.code == oracle.EINVAL
     el = m.elem.copy()
     el[0, 0] = m.n_node
     with pytest.raises(oracle.OracleError) as e:
@@ -482,6 +486,62 @@ def test_second_order_convergence_3d_mixed():
         errs.append(math.sqrt(np.mean((u - exact) ** 2)))
     rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
     assert all(1.9 < r < 2.3 for r in rates), rates
+
+
+# --------------------------------------------------------------------------- Robin sides
+def test_robin_single_element_closed_form():
+    """Section 1.2, type 3: on the reference triangle with the side opposite vertex 0
+    (length sqrt 2) of Robin type, A = K + alpha sqrt(2)/6 [[2, 1], [1, 2]] on vertices
+    1, 2 and constant g_R puts |F| g_R / 2 on each side vertex; on the reference
+    tetrahedron with the face opposite vertex 0 (area sqrt(3)/2) the mass term is
+    alpha |F| (1 + delta_ij) / 12."""
+    alpha, g = 3.0, 2.0
+    for dim in (2, 3):
+        if dim == 2:
+            node = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+            K = np.array([[1.0, -0.5, -0.5], [-0.5, 0.5, 0.0], [-0.5, 0.0, 0.5]])
+            fm, den = math.sqrt(2.0), 6.0
+        else:
+            node = np.array([[0.0, 1.0, 0.0, 0.0], [0.0, 0.0, 1.0, 0.0], [0.0, 0.0, 0.0, 1.0]])
+            K = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]], float) / 6.0
+            fm, den = math.sqrt(3.0) / 2.0, 12.0
+        nv = dim + 1
+        elem = np.arange(nv, dtype=np.int32).reshape(nv, 1)
+        bd = np.zeros((nv, 1), np.int8)
+        bd[0, 0] = 3
+        a = oracle.assemble(node, elem, bd, gR=Fn(FN_CONST, (g,)), alpha=alpha)
+        M = np.zeros((nv, nv))
+        for i in range(1, nv):
+            for j in range(1, nv):
+                M[i, j] = alpha * fm * (2.0 if i == j else 1.0) / den
+        assert np.allclose(a.dense(), K + M, rtol=0, atol=1e-15)
+        expect_b = np.array([0.0] + [fm * g / dim] * dim)
+        assert np.allclose(a.b, expect_b, rtol=0, atol=1e-15)
+
+
+def test_robin_totals_on_jittered_square():
+    """All four sides Robin: the rows of K sum to zero, so 1^T A 1 = alpha |boundary| = 4
+    alpha, and constant g_R loads g_R |boundary| in total."""
+    m = meshgen.square_mesh(11, jitter=0.2, permute=True, seed=91, kappa="lognormal", sides=(3, 3, 3, 3))
+    a = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, gR=Fn(FN_CONST, (0.7,)), alpha=2.5)
+    assert abs(float(a.val.sum()) - 4 * 2.5) <= 1e-12
+    assert abs(float(a.b.sum()) - 4 * 0.7) <= 1e-12
+
+
+def test_robin_second_order_convergence():
+    """u = cos(pi x) cos(pi y): du/dn = 0 on the sides, so g_R = alpha u there; with
+    f = 2 pi^2 u the L2 error decays like h^2 (data as nodal interpolants)."""
+    errs = []
+    alpha = 1.5
+    for n in (9, 17, 33):
+        m = meshgen.square_mesh(n, sides=(3, 3, 3, 3))
+        exact = np.cos(math.pi * m.node[0]) * np.cos(math.pi * m.node[1])
+        a = oracle.assemble(m.node, m.elem, m.bdflag, None, f=Fn(FN_NODAL, (0.0,), 2 * math.pi ** 2 * exact),
+                            gR=Fn(FN_NODAL, (0.0,), alpha * exact), alpha=alpha)
+        u, _, _ = oracle.solve(a, method="direct")
+        errs.append(_l2_error_cos(m, u))
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    assert all(1.8 < r < 2.2 for r in rates), rates
 
 
 # --------------------------------------------------------------------------- pure Neumann problem
