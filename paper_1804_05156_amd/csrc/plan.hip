@@ -35,7 +35,8 @@ constexpr int NBMAX = 16384;    // buckets held in LDS by the level-1 kernels
 constexpr int VBMAX = 4096;     // vertices per bucket (2^bs) at most
 constexpr int BKB = 256;        // threads of the bucket kernel
 constexpr int BCAPMAX = 24576;  // incidences per bucket sorted in LDS at most (larger: global path)
-constexpr int FINE = 32;        // buckets per coarse bucket
+constexpr int FINE_SHIFT = 5;
+constexpr int FINE = 1 << FINE_SHIFT;   // buckets per coarse bucket
 constexpr int FB = 1024;        // threads of the coarse-to-fine kernel
 constexpr int RUNR = 4;         // incidences per batch in the row kernels
 
@@ -70,7 +71,7 @@ FE_DEV int32_t check_element(const int32_t *__restrict__ elem, const int8_t *__r
 }
 
 // Level 1a: validation, Dirichlet marks, histogram of incidences per coarse bucket
-// (FINE buckets, 2^(bs+5) vertices).  hist1 is coarse-bucket-major:
+// (FINE buckets, 2^(bs+FINE_SHIFT) vertices).  hist1 is coarse-bucket-major:
 // hist1[cb * nblk1 + chunk].  LDS: nb ints (dynamic), nb = number of coarse buckets.
 template <int NV>
 __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ elem, const int8_t *__restrict__ bd,
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
             err |= e;
             continue;
         }
-        for (int a = 0; a < NV; ++a) atomicAdd(h + (v[a] >> (bs + 5)), 1);
+        for (int a = 0; a < NV; ++a) atomicAdd(h + (v[a] >> (bs + FINE_SHIFT)), 1);
         for (int f = 0; f < NV; ++f)
             if (code[f] == FE_BD_DIRICHLET)
                 for (int q = 0; q < NV; ++q)
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
     for (int32_t t = t0 + threadIdx.x; t < t1; t += L1B) {
         for (int a = 0; a < NV; ++a) {
             const int32_t v = elem[(int64_t)a * NT + t];
-            const int32_t pos = atomicAdd(cur + (v >> (bs + 5)), 1);
+            const int32_t pos = atomicAdd(cur + (v >> (bs + FINE_SHIFT)), 1);
             pairs[pos] = make_int2(v, t * NV + a);
         }
     }
@@ -564,18 +565,18 @@ FE_DEV void block_reduce3(int64_t &mr, int64_t &md, int64_t &nd, int64_t *lds)
 }
 
 // Statistics over processing-order arrays: row lengths (prowptr after its scan),
-// incidences per vertex (pincptr), Dirichlet flags.
+// incidences per vertex (pincptr), Dirichlet flags; a grid-stride loop keeps the
+// number of block partials small for the one-block combine.
 __global__ __launch_bounds__(STB) void k_stats_partial(int32_t N, const int32_t *__restrict__ prowptr,
                                                        const int32_t *__restrict__ pincptr,
                                                        const uint8_t *__restrict__ isdp, int64_t *part)
 {
     __shared__ int64_t lds[3 * (STB / 64)];
-    const int32_t k = blockIdx.x * STB + threadIdx.x;
     int64_t mr = 0, md = 0, nd = 0;
-    if (k < N) {
-        mr = prowptr[k + 1] - prowptr[k];
-        md = pincptr[k + 1] - pincptr[k];
-        nd = isdp[k];
+    for (int32_t k = blockIdx.x * STB + threadIdx.x; k < N; k += gridDim.x * STB) {
+        mr = max(mr, (int64_t)(prowptr[k + 1] - prowptr[k]));
+        md = max(md, (int64_t)(pincptr[k + 1] - pincptr[k]));
+        nd += isdp[k];
     }
     block_reduce3(mr, md, nd, lds);
     if (threadIdx.x == 0) {
@@ -737,7 +738,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     if ((rc = fe_fill_i32(P->status, ST_COUNT, 0, s))) return rc;
     if ((rc = fe_fill_u8(P->isd, N, 0, s))) return rc;
     if ((rc = fe_fill_u8(P->ownf, P->ninc, 0, s))) return rc;
-    if ((rc = fe_fill_i32(reinterpret_cast<int32_t *>(P->vinfo), 2 * (int64_t)N, 0, s))) return rc;
+    // (vinfo needs no clearing: the bucket kernels write it for every vertex)
     if (NT > 0)
         FE_TIMED("k_l1_hist", s,
                  hipLaunchKernelGGL(k_l1_hist<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, P->bdflag, NT, N,
@@ -794,7 +795,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
              hipLaunchKernelGGL((k_rows<NV, false>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R));
     if ((rc = fe_launch_check())) return rc;
     if ((rc = fe_scan_exclusive(P->prowptr, P->prowptr, N, P->totals + 2, P->part, P->status, s))) return rc;
-    const unsigned sb = (unsigned)cdiv(N, STB);
+    const unsigned sb = (unsigned)(cdiv(N, STB) < 1024 ? cdiv(N, STB) : 1024);   // grid-stride beyond
     FE_TIMED("k_stats_partial", s,
              hipLaunchKernelGGL(k_stats_partial, dim3(sb), dim3(STB), 0, s, N, (const int32_t *)P->prowptr,
                            (const int32_t *)P->pincptr, (const uint8_t *)P->isdp, P->stat_part));

@@ -19,10 +19,10 @@ FE_DEV int64_t wave_inclusive(int64_t x)
 }
 
 // Exclusive block scan of one value per thread; *total receives the block sum.
-FE_DEV int64_t block_exclusive(int64_t v, int64_t *lds, int64_t *total)
+template <int BLOCK = SCAN_BLOCK> FE_DEV int64_t block_exclusive(int64_t v, int64_t *lds, int64_t *total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    constexpr int NW = SCAN_BLOCK / 64;
+    constexpr int NW = BLOCK / 64;
     int64_t inc = wave_inclusive(v);
     if (lane == 63) lds[wid] = inc;
     __syncthreads();
@@ -61,19 +61,26 @@ __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *in, i
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// One block: exclusive scan of part[0..nb), total to part[nb] and *total_dev.
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_partials(int64_t *part, int64_t nb, int64_t *total_dev,
-                                                              int32_t *out, int64_t n, int32_t *status)
+// One block: exclusive scan of part[0..nb), total to part[nb] and *total_dev.  Each
+// thread owns a contiguous run of partials: a serial sum, one block scan of the run
+// sums, then a serial pass writing the run's offsets.
+constexpr int SP_BLOCK = 1024;
+
+__global__ __launch_bounds__(SP_BLOCK) void k_scan_partials(int64_t *part, int64_t nb, int64_t *total_dev,
+                                                            int32_t *out, int64_t n, int32_t *status)
 {
-    __shared__ int64_t lds[2 * (SCAN_BLOCK / 64)];
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_BLOCK) {
-        int64_t idx = c0 + threadIdx.x;
-        int64_t v = (idx < nb) ? part[idx] : 0;
-        int64_t tot;
-        int64_t ex = block_exclusive(v, lds, &tot);
-        if (idx < nb) part[idx] = carry + ex;
-        carry += tot;
+    __shared__ int64_t lds[2 * (SP_BLOCK / 64)];
+    const int64_t per = (nb + SP_BLOCK - 1) / SP_BLOCK;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    const int64_t b1 = (b0 + per < nb) ? b0 + per : nb;
+    int64_t s = 0;
+    for (int64_t k = b0; k < b1; ++k) s += part[k];
+    int64_t carry;
+    int64_t ex = block_exclusive<SP_BLOCK>(s, lds, &carry);
+    for (int64_t k = b0; k < b1; ++k) {
+        const int64_t v = part[k];
+        part[k] = ex;
+        ex += v;
     }
     if (threadIdx.x == 0) {
         part[nb] = carry;
@@ -155,7 +162,7 @@ int fe_scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int64_t *total
     FE_TIMED("k_scan_reduce", s,
              hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part));
     FE_TIMED("k_scan_partials", s,
-             hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SCAN_BLOCK), 0, s, part, nb, total_dev, out, n, status));
+             hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SP_BLOCK), 0, s, part, nb, total_dev, out, n, status));
     FE_TIMED("k_scan_apply", s,
              hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part));
     return fe_launch_check();
