@@ -21,7 +21,8 @@ enum : int32_t {
     ERR_MEASURE = 16,   // element measure not positive / not finite
     ERR_KAPPA = 32,     // kappa not positive / not finite
     ERR_LIMIT = 64,     // a row exceeds the fixed per-row capacity
-    ERR_OVERFLOW = 128  // a prefix sum exceeds the int32 range
+    ERR_OVERFLOW = 128, // a prefix sum exceeds the int32 range
+    ERR_RETRY = 256     // internal: a row did not fit the register column set
 };
 
 // Slots of the device status array.
@@ -117,6 +118,7 @@ struct fe_plan {
     // host copies
     int64_t nnz, nused, ndir;
     int32_t max_row, max_deg;
+    int rows_reg;         // the row passes use the register column set
     int pattern_done;
 };
 

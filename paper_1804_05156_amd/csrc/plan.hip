@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "fe_internal.h"
 
@@ -344,18 +345,83 @@ struct RowArgs {
     int32_t *status;
 };
 
-// Insert c into the sorted set cols[0..*u) (stride B in LDS); false if full.
-template <int B, int COLCAP> FE_DEV bool set_insert(int32_t *cols, int tid, int *u, int32_t c)
-{
-    int m = 0;
-    while (m < *u && cols[m * B + tid] < c) ++m;
-    if (m < *u && cols[m * B + tid] == c) return true;
-    if (*u == COLCAP) return false;
-    for (int q = *u; q > m; --q) cols[q * B + tid] = cols[(q - 1) * B + tid];
-    cols[m * B + tid] = c;
-    ++*u;
-    return true;
-}
+// Sorted column set of one row, in LDS (one column of the block's array per
+// thread, capacity CAP): the general form, used when a row may be long.
+template <int B, int CAP> struct LdsSet {
+    int32_t *cols;
+    int tid, u;
+    FE_DEV void init(int32_t *lds, int t, int32_t i)
+    {
+        cols = lds;
+        tid = t;
+        u = 1;
+        cols[tid] = i;
+    }
+    // Insert c; false if the set is full.
+    FE_DEV bool insert(int32_t c)
+    {
+        int m = 0;
+        while (m < u && cols[m * B + tid] < c) ++m;
+        if (m < u && cols[m * B + tid] == c) return true;
+        if (u == CAP) return false;
+        for (int q = u; q > m; --q) cols[q * B + tid] = cols[(q - 1) * B + tid];
+        cols[m * B + tid] = c;
+        ++u;
+        return true;
+    }
+    FE_DEV int find(int32_t c) const   // position of a member
+    {
+        int m = 0;
+        while (cols[m * B + tid] != c) ++m;
+        return m;
+    }
+    FE_DEV int32_t at(int m) const { return cols[m * B + tid]; }
+};
+
+// The same set in CAP registers, sorted and padded with INT32_MAX.  Inserting c
+// into sorted a is new[m] = max(min(a[m], c), a[m-1]) for every m (a[-1] = -inf):
+// branch-free and with fixed register indices, so no LDS and no divergent loops.
+template <int CAP> struct RegSet {
+    int32_t a[CAP];
+    int u;
+    FE_DEV void init(int32_t *, int, int32_t i)
+    {
+        a[0] = i;
+#pragma unroll
+        for (int m = 1; m < CAP; ++m) a[m] = INT32_MAX;
+        u = 1;
+    }
+    FE_DEV bool insert(int32_t c)
+    {
+        bool dup = false;
+#pragma unroll
+        for (int m = 0; m < CAP; ++m) dup |= (a[m] == c);
+        if (dup) return true;
+        if (u == CAP) return false;
+#pragma unroll
+        for (int m = CAP - 1; m > 0; --m) a[m] = max(min(a[m], c), a[m - 1]);
+        a[0] = min(a[0], c);
+        ++u;
+        return true;
+    }
+    FE_DEV int find(int32_t c) const
+    {
+        int m = 0;
+#pragma unroll
+        for (int q = 0; q < CAP; ++q) m += (a[q] < c) ? 1 : 0;
+        return m;
+    }
+    FE_DEV int32_t at(int m) const   // (m is a compile-time index in the unrolled callers)
+    {
+        int32_t v = 0;
+#pragma unroll
+        for (int q = 0; q < CAP; ++q) v = (q == m) ? a[q] : v;
+        return v;
+    }
+};
+
+constexpr int REGCAP = 16;   // register set capacity; longer rows go to the LDS form
+constexpr int REGB = 256;    // threads per block of the register form
 
 // Per row (one thread, processing order): the sorted set of columns {i} u
 // {vertices of the incident elements}.  Incidences go in batches of RUNR whose
@@ -367,11 +433,15 @@ template <int B, int COLCAP> FE_DEV bool set_insert(int32_t *cols, int tid, int 
 //                  words in processing order and the row record; Dirichlet flags
 //                  of the columns are read in processing order through elemp, which
 //                  keeps those reads local.
-template <int NV, bool FINAL>
-__global__ __launch_bounds__(RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
+// REG selects the register set (capacity REGCAP): a row that does not fit sets
+// ERR_RETRY and the host reruns the pass with the LDS set.
+template <int NV, bool FINAL, bool REG>
+__global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
 {
-    constexpr int B = RowCaps<NV>::BLOCK, COLCAP = RowCaps<NV>::COL;
-    __shared__ int32_t cols[COLCAP * B];
+    constexpr int B = REG ? REGB : RowCaps<NV>::BLOCK, COLCAP = RowCaps<NV>::COL;
+    __shared__ int32_t cols[REG ? 1 : COLCAP * B];
+    using Set = typename std::conditional<REG, RegSet<REGCAP>, LdsSet<B, COLCAP>>::type;
+    constexpr int SETCAP = REG ? REGCAP : COLCAP;
     const int tid = threadIdx.x;
     const int32_t k = blockIdx.x * B + tid;
     if (k >= R.N) return;
@@ -389,8 +459,8 @@ __global__ __launch_bounds__(RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
     }
     const int32_t src = FINAL ? s : R.inclp[k];
     const int32_t *klist = FINAL ? R.pinc : R.sorted_l;
-    int u = 1;
-    cols[tid] = i;
+    Set set;
+    set.init(cols, tid, i);
     bool ok = true;
     for (int32_t j0 = 0; j0 < d && ok; j0 += RUNR) {
         int32_t key[RUNR];
@@ -414,21 +484,24 @@ __global__ __launch_bounds__(RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
         for (int q = 0; q < RUNR; ++q)
             if (j0 + q < d)
 #pragma unroll
-                for (int jj = 0; jj < NV - 1; ++jj) ok = ok && set_insert<B, COLCAP>(cols, tid, &u, c[q][jj]);
+                for (int jj = 0; jj < NV - 1; ++jj) ok = ok && set.insert(c[q][jj]);
     }
     if (!ok) {
-        atomicOr(R.status + ST_ERR, ERR_LIMIT);
+        atomicOr(R.status + ST_ERR, REG ? ERR_RETRY : ERR_LIMIT);
         if (!FINAL) R.prowptr[k] = 0;
         return;
     }
+    const int u = set.u;
     if (!FINAL) {
         R.prowptr[k] = u;
         return;
     }
     const int32_t ps = R.prowptr[k];
     int diag = 0;
-    for (int m = 0; m < u; ++m) {
-        const int32_t c = cols[m * B + tid];
+#pragma unroll
+    for (int m = 0; m < SETCAP; ++m) {
+        if (m >= u) break;
+        const int32_t c = set.at(m);
         R.colindp[ps + m] = c;
         if (c == i) diag = m;
     }
@@ -473,8 +546,7 @@ __global__ __launch_bounds__(RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
                 uint32_t meta = (uint32_t)(key[q] % NV);
 #pragma unroll
                 for (int jj = 0; jj < NV - 1; ++jj) {
-                    int m = 0;
-                    while (cols[m * B + tid] != c[q][jj]) ++m;   // present by construction
+                    const int m = set.find(c[q][jj]);   // present by construction
                     meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
                     if (dz[q][jj]) {
                         meta |= 1u << (Meta<NV>::DBIT + jj);
@@ -789,42 +861,64 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                            (const int64_t *)(P->totals + 0), P->pi, P->piinv, P->pincptr, P->inclp, P->isdp, P->status));
     if ((rc = fe_launch_check())) return rc;
     if ((rc = fe_scan_exclusive(P->pincptr, P->pincptr, N, P->totals + 1, P->part, P->status, s))) return rc;
-    constexpr int RB = RowCaps<NV>::BLOCK;
     const RowArgs R = row_args(P);
-    FE_TIMED("k_rows_count", s,
-             hipLaunchKernelGGL((k_rows<NV, false>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R));
-    if ((rc = fe_launch_check())) return rc;
-    if ((rc = fe_scan_exclusive(P->prowptr, P->prowptr, N, P->totals + 2, P->part, P->status, s))) return rc;
-    const unsigned sb = (unsigned)(cdiv(N, STB) < 1024 ? cdiv(N, STB) : 1024);   // grid-stride beyond
-    FE_TIMED("k_stats_partial", s,
-             hipLaunchKernelGGL(k_stats_partial, dim3(sb), dim3(STB), 0, s, N, (const int32_t *)P->prowptr,
-                           (const int32_t *)P->pincptr, (const uint8_t *)P->isdp, P->stat_part));
-    FE_TIMED("k_stats_final", s,
-             hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STB), 0, s, (int32_t)sb, (const int64_t *)P->stat_part, P->status));
-    if ((rc = fe_launch_check())) return rc;
-    int32_t st[ST_COUNT];
-    int64_t tot[8];
-    FE_HIP_CHECK(hipMemcpyAsync(st, P->status, sizeof(st), hipMemcpyDeviceToHost, s));
-    FE_HIP_CHECK(hipMemcpyAsync(tot, P->totals, sizeof(tot), hipMemcpyDeviceToHost, s));
-    FE_HIP_CHECK(hipStreamSynchronize(s));
-    if (st[ST_ERR]) return fe_status_from_bits(st[ST_ERR]);
-    P->nused = tot[0];
-    P->nnz = tot[2];
-    P->max_row = st[ST_MAXROW];
-    P->max_deg = st[ST_MAXDEG];
-    P->ndir = st[ST_NDIR];
-    if (tot[1] != P->ninc) return FE_EHIP;   // every incidence must be placed
-    if (P->nnz > P->nnz_max) return FE_EHIP;
-    return FE_OK;
+    // the row pass with the register column set; rows too long for it make the pass
+    // run again with the LDS set (both give the same sets)
+    P->rows_reg = 1;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (P->rows_reg)
+            FE_TIMED("k_rows_count", s,
+                     hipLaunchKernelGGL((k_rows<NV, false, true>), dim3((unsigned)cdiv(N, REGB)), dim3(REGB), 0, s,
+                                        R));
+        else
+            FE_TIMED("k_rows_count", s,
+                     hipLaunchKernelGGL((k_rows<NV, false, false>), dim3((unsigned)cdiv(N, RowCaps<NV>::BLOCK)),
+                                        dim3(RowCaps<NV>::BLOCK), 0, s, R));
+        if ((rc = fe_launch_check())) return rc;
+        if ((rc = fe_scan_exclusive(P->prowptr, P->prowptr, N, P->totals + 2, P->part, P->status, s))) return rc;
+        const unsigned sb = (unsigned)(cdiv(N, STB) < 1024 ? cdiv(N, STB) : 1024);   // grid-stride beyond
+        FE_TIMED("k_stats_partial", s,
+                 hipLaunchKernelGGL(k_stats_partial, dim3(sb), dim3(STB), 0, s, N, (const int32_t *)P->prowptr,
+                                    (const int32_t *)P->pincptr, (const uint8_t *)P->isdp, P->stat_part));
+        FE_TIMED("k_stats_final", s,
+                 hipLaunchKernelGGL(k_stats_final, dim3(1), dim3(STB), 0, s, (int32_t)sb,
+                                    (const int64_t *)P->stat_part, P->status));
+        if ((rc = fe_launch_check())) return rc;
+        int32_t st[ST_COUNT];
+        int64_t tot[8];
+        FE_HIP_CHECK(hipMemcpyAsync(st, P->status, sizeof(st), hipMemcpyDeviceToHost, s));
+        FE_HIP_CHECK(hipMemcpyAsync(tot, P->totals, sizeof(tot), hipMemcpyDeviceToHost, s));
+        FE_HIP_CHECK(hipStreamSynchronize(s));
+        if (st[ST_ERR] & ERR_RETRY) {
+            if (!P->rows_reg) return FE_EHIP;
+            P->rows_reg = 0;
+            if ((rc = fe_fill_i32(P->status + ST_ERR, 1, st[ST_ERR] & ~ERR_RETRY, s))) return rc;
+            continue;
+        }
+        if (st[ST_ERR]) return fe_status_from_bits(st[ST_ERR]);
+        P->nused = tot[0];
+        P->nnz = tot[2];
+        P->max_row = st[ST_MAXROW];
+        P->max_deg = st[ST_MAXDEG];
+        P->ndir = st[ST_NDIR];
+        if (tot[1] != P->ninc) return FE_EHIP;   // every incidence must be placed
+        if (P->nnz > P->nnz_max) return FE_EHIP;
+        return FE_OK;
+    }
+    return FE_EHIP;
 }
 
 template <int NV> int plan_pattern(fe_plan *P, int32_t *rowptr, int32_t *colind, hipStream_t s)
 {
     const int32_t N = (int32_t)P->N;
-    constexpr int RB = RowCaps<NV>::BLOCK;
     const RowArgs R = row_args(P);
-    FE_TIMED("k_rows_final", s,
-             hipLaunchKernelGGL((k_rows<NV, true>), dim3((unsigned)cdiv(N, RB)), dim3(RB), 0, s, R));
+    if (P->rows_reg)
+        FE_TIMED("k_rows_final", s,
+                 hipLaunchKernelGGL((k_rows<NV, true, true>), dim3((unsigned)cdiv(N, REGB)), dim3(REGB), 0, s, R));
+    else
+        FE_TIMED("k_rows_final", s,
+                 hipLaunchKernelGGL((k_rows<NV, true, false>), dim3((unsigned)cdiv(N, RowCaps<NV>::BLOCK)),
+                                    dim3(RowCaps<NV>::BLOCK), 0, s, R));
     FE_TIMED("k_label_rows", s,
              hipLaunchKernelGGL(k_label_rows, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, (const int32_t *)P->piinv,
                            (const int4 *)P->precp, P->rowrec, P->rowlen));
