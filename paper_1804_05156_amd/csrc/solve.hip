@@ -24,7 +24,17 @@ namespace {
 
 constexpr int SB = CG_UNIT;   // threads per block, one row per thread
 
-enum { S_RZ = 0, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_PQ, S_NSCAL = 8 };
+enum { S_RZ = 0, S_RR, S_BB, S_ALPHA, S_BETA, S_TOL2, S_PQ, S_RZ_ODD, S_NSCAL = 8 };
+
+// r.z of iteration j (fused form): even j in S_RZ, odd j in S_RZ_ODD, so a kernel
+// can read r.z of the previous iteration while its block 0 stores the current one.
+FE_DEV int rz_slot(int32_t j) { return (j & 1) ? S_RZ_ODD : S_RZ; }
+
+// Systems of at most FUSE_NB blocks use the fused form: each row kernel first adds
+// the partial sums of the previous row kernel itself (every block, the same fixed
+// order, so every block gets the same bits), which halves the launches per
+// iteration.  Larger systems run the separate one-block summing kernels.
+constexpr int32_t FUSE_NB = 1024;
 enum { F_DONE = 0, F_ITER, F_BAD, F_NFLAG = 8 };
 
 struct SolveWs {
@@ -203,6 +213,99 @@ __global__ __launch_bounds__(SB) void k_cg_b_sum(int32_t nb, const double *part,
     }
 }
 
+// Fused K_A of iteration it: r.z and r.r of the previous K_B from its partials,
+// beta and the stopping test (recorded by block 0), then p = z + beta p_old,
+// q = A p and the partial p.q.  check_only: record the stopping test and stop.
+__global__ __launch_bounds__(SB) void k_cg_a_fused(int32_t n, int32_t it, int32_t check_only,
+                                                   const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ colind, const double *__restrict__ val,
+                                                   const double *__restrict__ z, const double *__restrict__ pold,
+                                                   double *__restrict__ pnew, double *__restrict__ qv, double *part,
+                                                   double *scal, int32_t *flag)
+{
+    __shared__ double lds[SB / 64];
+    __shared__ double bc[2];
+    if (*(volatile const int32_t *)(flag + F_DONE)) return;
+    const int32_t nb = gridDim.x;
+    double beta = 0.0;
+    bool done = false;
+    if (it > 0) {
+        const double RZ = cg_sum_partials(part + nb, nb, lds);
+        const double RR = cg_sum_partials(part + 2 * nb, nb, lds);
+        if (threadIdx.x == 0) {
+            bc[0] = RZ;
+            bc[1] = RR;
+        }
+        __syncthreads();
+        const double rz = bc[0], rr = bc[1];
+        beta = rz / scal[rz_slot(it - 1)];
+        done = rr <= scal[S_TOL2];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[rz_slot(it)] = rz;
+            scal[S_RR] = rr;
+            scal[S_BETA] = beta;
+            if (done) {
+                flag[F_DONE] = 1;
+                flag[F_ITER] = it;
+            }
+        }
+    }
+    if (done || check_only) return;
+    const int32_t i = blockIdx.x * SB + threadIdx.x;
+    double pq = 0.0;
+    if (i < n) {
+        const bool ok = true;
+        double sv;
+        cg_apply_rows<1>(&i, &ok, rowptr, colind, val, z, pold, &beta, &sv);
+        const double pi = z[i] + beta * pold[i];
+        pnew[i] = pi;
+        qv[i] = sv;
+        pq = pi * sv;
+    }
+    const double bs = block_sum<SB>(pq, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// Fused K_B of iteration it: alpha = r.z / p.q from the partials of K_A, then
+// x += alpha p, r -= alpha q, z = r / diag and the partials r.z, r.r.
+__global__ __launch_bounds__(SB) void k_cg_b_fused(int32_t n, int32_t it, double *__restrict__ x,
+                                                   const double *__restrict__ p, const double *__restrict__ qv,
+                                                   double *__restrict__ r, double *__restrict__ z,
+                                                   const double *__restrict__ dinv, double *part, double *scal,
+                                                   int32_t *flag)
+{
+    __shared__ double lds[SB / 64];
+    __shared__ double bc;
+    if (*(volatile const int32_t *)(flag + F_DONE)) return;
+    const int32_t nb = gridDim.x;
+    const double PQ = cg_sum_partials(part, nb, lds);
+    if (threadIdx.x == 0) bc = PQ;
+    __syncthreads();
+    const double alpha = scal[rz_slot(it)] / bc;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[S_PQ] = bc;
+        scal[S_ALPHA] = alpha;
+        flag[F_ITER] = it + 1;
+    }
+    const int32_t i = blockIdx.x * SB + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (i < n) {
+        x[i] += alpha * p[i];
+        const double ri = r[i] - alpha * qv[i];
+        const double zi = ri * dinv[i];
+        r[i] = ri;
+        z[i] = zi;
+        rz = ri * zi;
+        rr = ri * ri;
+    }
+    const double s0 = block_sum<SB>(rz, lds);
+    const double s1 = block_sum<SB>(rr, lds);
+    if (threadIdx.x == 0) {
+        part[nb + blockIdx.x] = s0;
+        part[2 * nb + blockIdx.x] = s1;
+    }
+}
+
 }  // namespace
 
 extern "C" int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, const double *x,
@@ -251,6 +354,7 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
     int32_t launched = 0;
     int parity = 0;
     const int CHUNK = 32;
+    const bool fused = nb <= (unsigned)FUSE_NB;
     for (;;) {
         FE_HIP_CHECK(hipMemcpyAsync(fl, W.flag, sizeof(fl), hipMemcpyDeviceToHost, s));
         FE_HIP_CHECK(hipStreamSynchronize(s));
@@ -260,24 +364,44 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
         for (int32_t c = 0; c < chunk; ++c) {
             double *pold = parity ? W.p1 : W.p0;
             double *pnew = parity ? W.p0 : W.p1;
-            FE_TIMED("k_cg_a", s,
-                     hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, (const double *)W.z,
-                                        (const double *)pold, pnew, W.q, W.part, (const double *)W.scal,
-                                        (const int32_t *)W.flag));
-            FE_TIMED("k_cg_a_sum", s,
-                     hipLaunchKernelGGL(k_cg_a_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part,
-                                        W.scal, (const int32_t *)W.flag));
-            FE_TIMED("k_cg_b", s,
-                     hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(SB), 0, s, nn, u, (const double *)pnew,
-                                        (const double *)W.q, W.r, W.z, (const double *)W.dinv, W.part,
-                                        (const double *)W.scal, (const int32_t *)W.flag));
-            FE_TIMED("k_cg_b_sum", s,
-                     hipLaunchKernelGGL(k_cg_b_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part,
-                                        W.scal, W.flag));
+            if (fused) {
+                const int32_t it = launched + c;
+                FE_TIMED("k_cg_a_fused", s,
+                         hipLaunchKernelGGL(k_cg_a_fused, dim3(nb), dim3(SB), 0, s, nn, it, 0, rowptr, colind, val,
+                                            (const double *)W.z, (const double *)pold, pnew, W.q, W.part, W.scal,
+                                            W.flag));
+                FE_TIMED("k_cg_b_fused", s,
+                         hipLaunchKernelGGL(k_cg_b_fused, dim3(nb), dim3(SB), 0, s, nn, it, u, (const double *)pnew,
+                                            (const double *)W.q, W.r, W.z, (const double *)W.dinv, W.part, W.scal,
+                                            W.flag));
+            } else {
+                FE_TIMED("k_cg_a", s,
+                         hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val,
+                                            (const double *)W.z, (const double *)pold, pnew, W.q, W.part,
+                                            (const double *)W.scal, (const int32_t *)W.flag));
+                FE_TIMED("k_cg_a_sum", s,
+                         hipLaunchKernelGGL(k_cg_a_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part,
+                                            W.scal, (const int32_t *)W.flag));
+                FE_TIMED("k_cg_b", s,
+                         hipLaunchKernelGGL(k_cg_b, dim3(nb), dim3(SB), 0, s, nn, u, (const double *)pnew,
+                                            (const double *)W.q, W.r, W.z, (const double *)W.dinv, W.part,
+                                            (const double *)W.scal, (const int32_t *)W.flag));
+                FE_TIMED("k_cg_b_sum", s,
+                         hipLaunchKernelGGL(k_cg_b_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part,
+                                            W.scal, W.flag));
+            }
             parity ^= 1;
         }
         if ((rc = fe_launch_check())) return rc;
         launched += chunk;
+        if (fused && launched >= maxit) {
+            // the stopping test after the last iteration (no further work)
+            FE_TIMED("k_cg_a_fused", s,
+                     hipLaunchKernelGGL(k_cg_a_fused, dim3(nb), dim3(SB), 0, s, nn, launched, 1, rowptr, colind, val,
+                                        (const double *)W.z, (const double *)W.p0, W.p1, W.q, W.part, W.scal,
+                                        W.flag));
+            if ((rc = fe_launch_check())) return rc;
+        }
     }
     FE_HIP_CHECK(hipMemcpyAsync(sc, W.scal, sizeof(sc), hipMemcpyDeviceToHost, s));
     FE_HIP_CHECK(hipStreamSynchronize(s));

@@ -177,3 +177,19 @@ def test_full_size_batch_sampled():
     for k in sample:
         log(f"  instance {k}: side {sizes[k]}, iterations {it[k]}")
         _check_instance(B, k, ms[k], u, it, rel, f, None, 1e-10, fo, None, oracle_check=sizes[k] <= 128)
+
+
+def test_both_plain_solve_forms_match_batched():
+    """The plain solve fuses its reductions into the row kernels up to 1024 workgroups
+    (262144 rows) and runs separate summing kernels above; both give the bits of the
+    batched solve (a 513^2 instance: 263169 rows, separate form; a 300^2 instance:
+    fused form)."""
+    log("case: fused and separate plain solve forms vs batched")
+    ms = meshgen.batch_meshes([513, 300], seed_base=7400)
+    (f, fo), _, _ = fns(SPECS[0])
+    B, kap = _batch(ms)
+    u, it, rel = B.assemble_solve(kap, f, None, None, rtol=1e-10)
+    u = u.clone()
+    for k, m in enumerate(ms):
+        log(f"  instance {k}: {m.n_node} rows, iterations {it[k]}")
+        _check_instance(B, k, m, u, it, rel, f, None, 1e-10, fo, None, oracle_check=False)
