@@ -270,7 +270,9 @@ typedef struct fe_batch_info {
     int32_t n_inst, n_units;        /* instances; 256-row reduction units over all of them */
     int64_t n_rows;
     int32_t grid;                   /* workgroups of the persistent solve kernel */
-    int32_t blocks_per_cu, max_blocks_per_cu, units_per_step;
+    int32_t blocks_per_cu;
+    int32_t max_blocks_per_cu;      /* most workgroups per compute unit at this units_per_step */
+    int32_t units_per_step;
     int32_t cooperative;            /* 1 if the captured solve launch is a cooperative launch */
     int32_t captures;               /* graph captures so far */
 } fe_batch_info;

@@ -84,7 +84,7 @@ def _time_call(fn, reps: int) -> float:
 
 
 # (workgroups per compute unit, 256-row units per workgroup step) tried by autotune
-CANDIDATES = ((4, 1), (6, 1), (2, 2), (4, 2), (4, 4), (2, 4))
+CANDIDATES = ((4, 1), (5, 1), (2, 2), (4, 2), (2, 4))
 
 
 def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=100000, candidates=None,
@@ -104,10 +104,8 @@ def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=10
         if key in cache:
             batch.set_grid(*cache[key]["grid"])
             return dict(cache[key], cached=True)
-    hi = int(info["max_blocks_per_cu"])
-    cands = [c for c in (candidates or CANDIDATES) if c[0] <= hi]
     times = {}
-    for c in cands:
+    for c in (candidates or CANDIDATES):
         try:
             batch.set_grid(*c)
             batch.assemble_solve(kappa, f, gD, gN, rtol, maxit)          # capture + warm

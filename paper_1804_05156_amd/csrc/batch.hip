@@ -227,8 +227,9 @@ FE_DEV void record(const BatchArgs &A, int32_t k, bool done, int32_t iters, doub
 }
 
 // K units per step: every thread owns row t of each of the K units, so K independent
-// row walks overlap their loads; reductions stay per unit.
-template <int K>
+// row walks overlap their loads; reductions stay per unit.  CH: entries per chunk of
+// the row walk (fewer registers for smaller chunks, hence more workgroups per CU).
+template <int K, int CH>
 __global__ __launch_bounds__(BB) void k_batch_pcg(BatchArgs A)
 {
     extern __shared__ int4 dyn[];
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(BB) void k_batch_pcg(BatchArgs A)
                 if (c_done) t[j].count = 0;   // mark: no partial for this slot
             }
             double s[K];
-            cg_apply_rows<K>(rows, ok, A.rowptr, A.colind, A.val, A.z, pold, beta, s);
+            cg_apply_rows<K, CH>(rows, ok, A.rowptr, A.colind, A.val, A.z, pold, beta, s);
             double red[K];
 #pragma unroll
             for (int j = 0; j < K; ++j) {
@@ -483,13 +484,17 @@ size_t batch_layout(int64_t n, int32_t n_inst, BatchWs *w, char *base)
 
 size_t dyn_lds_bytes(int32_t n_inst) { return 16 * (size_t)n_inst + 4 * ((size_t)n_inst + 1); }
 
-const void *pcg_kernel(int K)
+// The instantiation for K units per step at `per_cu` workgroups per compute unit:
+// one unit per step takes 8-entry row chunks up to 4 workgroups per compute unit
+// and 4-entry chunks (fewer registers) for 5.
+const void *pcg_kernel(int K, int per_cu)
 {
-    switch (K) {
-    case 1: return reinterpret_cast<const void *>(&k_batch_pcg<1>);
-    case 2: return reinterpret_cast<const void *>(&k_batch_pcg<2>);
-    default: return reinterpret_cast<const void *>(&k_batch_pcg<4>);
+    if (K == 1) {
+        if (per_cu <= 4) return reinterpret_cast<const void *>(&k_batch_pcg<1, 8>);
+        return reinterpret_cast<const void *>(&k_batch_pcg<1, 4>);
     }
+    if (K == 2) return reinterpret_cast<const void *>(&k_batch_pcg<2, 2>);
+    return reinterpret_cast<const void *>(&k_batch_pcg<4, 2>);
 }
 
 }  // namespace
@@ -511,15 +516,18 @@ static int batch_set_grid(fe_batch_solver *S, int32_t blocks_per_cu, int32_t uni
     if (blocks_per_cu < 0) return FE_EINVAL;
     if (units_per_step == 0) units_per_step = 2;
     if (units_per_step != 1 && units_per_step != 2 && units_per_step != 4) return FE_EINVAL;
-    int dev = 0, cus = 0, per = 0;
+    int dev = 0, cus = 0, per = 0, per_small = 0;
     FE_HIP_CHECK(hipGetDevice(&dev));
     FE_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel(units_per_step), BB, S->lds));
-    if (per < 1) return FE_ELIMIT;
-    S->max_per_cu = per;
-    S->units_per_step = units_per_step;
-    int32_t want = blocks_per_cu ? blocks_per_cu : (per < 2 ? per : 2);
+    // the most workgroups per compute unit over the instantiations of this K
+    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_small, pcg_kernel(units_per_step, 1 << 20), BB,
+                                                              S->lds));
+    if (per_small < 1) return FE_ELIMIT;
+    int32_t want = blocks_per_cu ? blocks_per_cu : (per_small < 2 ? per_small : 2);
+    FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel(units_per_step, want), BB, S->lds));
     if (want > per) return FE_EINVAL;   // more workgroups per compute unit than fit
+    S->max_per_cu = per_small;
+    S->units_per_step = units_per_step;
     int64_t g = (int64_t)cus * want;
     if (g > S->n_units) g = S->n_units;
     S->grid = (int32_t)(g > 0 ? g : 1);
@@ -602,15 +610,15 @@ static int batch_enqueue(fe_batch_solver *S, const int32_t *rowptr, const int32_
         void *args[] = {&A};
         hipError_t e = hipSuccess;
         FE_TIMED("k_batch_pcg", s,
-                 e = hipLaunchCooperativeKernel(pcg_kernel(S->units_per_step), dim3((unsigned)S->grid), dim3(BB),
-                                                args, (unsigned)S->lds, s));
+                 e = hipLaunchCooperativeKernel(pcg_kernel(S->units_per_step, S->blocks_per_cu),
+                                                dim3((unsigned)S->grid), dim3(BB), args, (unsigned)S->lds, s));
         if (e != hipSuccess) return FE_EHIP;
     } else {
         void *args[] = {&A};
         hipError_t e = hipSuccess;
         FE_TIMED("k_batch_pcg", s,
-                 e = hipLaunchKernel(pcg_kernel(S->units_per_step), dim3((unsigned)S->grid), dim3(BB), args,
-                                     S->lds, s));
+                 e = hipLaunchKernel(pcg_kernel(S->units_per_step, S->blocks_per_cu), dim3((unsigned)S->grid),
+                                     dim3(BB), args, S->lds, s));
         if (e != hipSuccess) return FE_EHIP;
     }
     return FE_OK;

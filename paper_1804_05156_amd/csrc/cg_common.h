@@ -27,13 +27,13 @@ FE_DEV void cg_init_row(int32_t i, const int32_t *__restrict__ rowptr, const int
 // at once (rows with ok[j] false are skipped).  Each row is walked in chunks of CH
 // entries: all column indices and values of a chunk are loaded, then all gathers
 // of z and p_old, then the products are added in column order, so the loads of a
-// chunk overlap instead of forming one dependent chain per entry.
-template <int K>
+// chunk overlap instead of forming one dependent chain per entry.  The products are
+// added in column order whatever CH is, so CH never changes a result bit.
+template <int K, int CH = (K >= 4 ? 2 : (K == 2 ? 4 : 8))>
 FE_DEV void cg_apply_rows(const int32_t *i, const bool *ok, const int32_t *__restrict__ rowptr,
                           const int32_t *__restrict__ colind, const double *__restrict__ val,
                           const double *__restrict__ z, const double *__restrict__ pold, const double *beta, double *s)
 {
-    constexpr int CH = K >= 4 ? 2 : (K == 2 ? 4 : 8);
     int32_t q[K], e[K];
     int32_t len = 0;
 #pragma unroll

@@ -202,3 +202,23 @@ def test_robin_second_order_convergence_gpu():
     rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
     log(f"  L2 errors {errs} rates {rates}")
     assert all(1.9 < r < 2.1 for r in rates)
+
+
+def test_kernel_timing_api():
+    """fe_prof_enable / fe_prof_read: every kernel of one assembly is timed once, by
+    name, with positive durations; disabled timing records nothing."""
+    from paper_1804_05156_amd import femhip
+    log("case: kernel timing")
+    m = meshgen.square_mesh(65, jitter=0.2, permute=True, seed=77, kappa="lognormal")
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    asm = plan.assemble(kap)
+    torch.cuda.synchronize()
+    femhip.fe_prof_enable(True)
+    plan.assemble(kap, out=asm)
+    rec = femhip.fe_prof_read()
+    femhip.fe_prof_enable(False)
+    assert set(rec) == {"k_scatter_coords", "k_assemble_2d", "k_values_to_label"}
+    assert all(r["launches"] == 1 and r["total_ms"] > 0 for r in rec.values())
+    plan.assemble(kap, out=asm)
+    assert femhip.fe_prof_read() == {}
