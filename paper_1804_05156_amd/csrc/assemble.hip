@@ -170,6 +170,10 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
     int32_t err = 0;
     const bool nodal_f = A.f.kind == FE_FN_NODAL;
     const double fi = nodal_f ? A.fp[k] : 0.0;
+    // incidence bits that call for the boundary walk (lifting only with g_D != 0)
+    const uint32_t BND = (3u << Meta<3>::NBIT) | (3u << Meta<3>::RBIT) |
+                         (A.gd.kind != FE_FN_ZERO ? 3u << Meta<3>::DBIT : 0u);
+    uint32_t bmask = 0;
     for (int32_t p0 = s; p0 < e; p0 += UNR) {
         int2 km[UNR];
         int4 ep[UNR];
@@ -229,12 +233,40 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                 }
                 bsum += area2 * (f1 + f2) / 12.0;
             }
+            bmask |= meta;
+        }
+    }
+    // Boundary terms of the row: Neumann and Robin sides through its vertex and the
+    // lifting of Dirichlet neighbours.  Few rows have any, so they are added by a
+    // second walk over the incidences that carry such a bit, which keeps the
+    // registers of these rare paths out of the main loop.
+    if (bmask & BND) {
+        for (int32_t p = s; p < e; ++p) {
+            const int2 kmv = A.pincm[p];
+            const uint32_t meta = (uint32_t)kmv.y;
+            if (!(meta & BND)) continue;
+            const int32_t t = kmv.x / 3;
+            const int a = kmv.x - 3 * t;
+            const int4 epv = ep4[t];
+            const int q1 = sel3(epv, a == 2 ? 0 : a + 1);
+            const int q2 = sel3(epv, a == 0 ? 2 : a - 1);
+            const double2 X1 = xy[q1], X2 = xy[q2];
+            const double ktv = A.kappa ? A.kappa[t] : 1.0;
+            const double E0x = X2.x - X1.x, E0y = X2.y - X1.y;
+            const double E1x = X0.x - X2.x, E1y = X0.y - X2.y;
+            const double E2x = X1.x - X0.x, E2y = X1.y - X0.y;
+            const double area2 = E1x * E2y - E1y * E2x;
+            const double sc = ktv / (2.0 * area2);
+            const double k01 = sc * (E0x * E1x + E0y * E1y);
+            const double k02 = sc * (E0x * E2x + E0y * E2y);
+            const int o1 = (meta >> Meta<3>::OFF) & Meta<3>::OMASK;
+            const int o2 = (meta >> (Meta<3>::OFF + Meta<3>::OB)) & Meta<3>::OMASK;
             // Neumann sides through the row's vertex: opposite X1 (X2-X0) and opposite X2 (X0-X1)
             const uint32_t nb = (meta >> Meta<3>::NBIT) & 3u;
             if (nb) {
                 for (int jj = 0; jj < 2; ++jj) {
                     if (!((nb >> jj) & 1u)) continue;
-                    const double2 Xo = jj == 0 ? X2[u] : X1[u];         // other end of the side
+                    const double2 Xo = jj == 0 ? X2 : X1;         // other end of the side
                     const double ex = jj == 0 ? E1x : E2x, ey = jj == 0 ? E1y : E2y;
                     const double L = sqrt(ex * ex + ey * ey);
                     const double mid[2] = {0.5 * (X0.x + Xo.x), 0.5 * (X0.y + Xo.y)};
@@ -244,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                         const double nrm[2] = {ey / L, -ex / L};        // outward unit normal
                         g = fn_dudn<2>(A.gn, mid, nrm);
                     } else if (A.gn.kind == FE_FN_NODAL) {
-                        const int32_t vo = A.pi[jj == 0 ? p2[u] : p1[u]];
+                        const int32_t vo = A.pi[jj == 0 ? q2 : q1];
                         g = 0.5 * (A.gn.nodal[A.pi[k]] + A.gn.nodal[vo]);
                     } else {
                         g = fn_point<2>(A.gn, mid);
@@ -260,7 +292,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
             if (rb) {
                 for (int jj = 0; jj < 2; ++jj) {
                     if (!((rb >> jj) & 1u)) continue;
-                    const double2 Xo = jj == 0 ? X2[u] : X1[u];         // other end of the side
+                    const double2 Xo = jj == 0 ? X2 : X1;         // other end of the side
                     const double ex = jj == 0 ? E1x : E2x, ey = jj == 0 ? E1y : E2y;
                     const double L = sqrt(ex * ex + ey * ey);
                     const double m1 = A.ralpha * L / 6.0;
@@ -269,7 +301,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                     const uint32_t other_d = jj == 0 ? (db >> 1) & 1u : db & 1u;
                     if (other_d && A.gd.kind != FE_FN_ZERO) {
                         const double xo[2] = {Xo.x, Xo.y};
-                        lift += m1 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[jj == 0 ? p2[u] : p1[u]] : 0,
+                        lift += m1 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[jj == 0 ? q2 : q1] : 0,
                                                         xo);
                     }
                     if (A.gr.kind != FE_FN_ZERO) {
@@ -279,7 +311,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                             const double nrm[2] = {ey / L, -ex / L};
                             g = fn_dudn<2>(A.gr, mid, nrm);
                         } else if (A.gr.kind == FE_FN_NODAL) {
-                            const int32_t vo = A.pi[jj == 0 ? p2[u] : p1[u]];
+                            const int32_t vo = A.pi[jj == 0 ? q2 : q1];
                             g = 0.5 * (A.gr.nodal[A.pi[k]] + A.gr.nodal[vo]);
                         } else {
                             g = fn_point<2>(A.gr, mid);
@@ -291,12 +323,12 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
             // Dirichlet columns: lift b by K[0][c] u_D(c)
             if (db && A.gd.kind != FE_FN_ZERO) {
                 if (db & 1u) {
-                    const double x1[2] = {X1[u].x, X1[u].y};
-                    lift += k01 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[p1[u]] : 0, x1);
+                    const double x1[2] = {X1.x, X1.y};
+                    lift += k01 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[q1] : 0, x1);
                 }
                 if (db & 2u) {
-                    const double x2[2] = {X2[u].x, X2[u].y};
-                    lift += k02 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[p2[u]] : 0, x2);
+                    const double x2[2] = {X2.x, X2.y};
+                    lift += k02 * dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[q2] : 0, x2);
                 }
             }
         }
@@ -351,6 +383,9 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     const double beta = 0.13819660112501051518;    // (5 - sqrt 5) / 20
     const bool nodal_f = A.f.kind == FE_FN_NODAL;
     const double fi = nodal_f ? A.fp[k] : 0.0;
+    const uint32_t BND = (7u << Meta<4>::NBIT) | (7u << Meta<4>::RBIT) |
+                         (A.gd.kind != FE_FN_ZERO ? 7u << Meta<4>::DBIT : 0u);
+    uint32_t bmask = 0;
     for (int32_t p0 = s; p0 < e; p0 += UNR) {
         int2 km[UNR];
         int4 ep[UNR];
@@ -429,6 +464,47 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                 }
                 bsum += vol * q / 4.0;
             }
+            bmask |= meta;
+        }
+    }
+    // Boundary terms of the row (Neumann and Robin faces through its vertex, lifting
+    // of Dirichlet neighbours): a second walk over the incidences that carry such a
+    // bit, as in 2-D.
+    if (bmask & BND) {
+        for (int32_t p = s; p < e; ++p) {
+            const int2 kmv = A.pincm[p];
+            const uint32_t meta = (uint32_t)kmv.y;
+            if (!(meta & BND)) continue;
+            const int32_t t = kmv.x >> 2;
+            const int a = kmv.x & 3;
+            const int4 epv = ep4[t];
+            const double ktv = A.kappa ? A.kappa[t] : 1.0;
+            int pqv[3];
+            double Yv[3][3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                pqv[q] = sel4(epv, fe_other<4>(a, q));
+                const double2 c0 = xy[2 * (int64_t)pqv[q]], c1 = xy[2 * (int64_t)pqv[q] + 1];
+                Yv[q][0] = c0.x; Yv[q][1] = c0.y; Yv[q][2] = c1.x;
+            }
+            const double *Y1 = Yv[0], *Y2 = Yv[1], *Y3 = Yv[2];
+            double d10[3], d20[3], d30[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                d10[c] = Y1[c] - Y0[c];
+                d20[c] = Y2[c] - Y0[c];
+                d30[c] = Y3[c] - Y0[c];
+            }
+            double n1[3], n2[3], n3[3], n0[3];
+            cross3(d20, d30, n1);
+            cross3(d30, d10, n2);
+            cross3(d10, d20, n3);
+            for (int c = 0; c < 3; ++c) n0[c] = -(n1[c] + n2[c] + n3[c]);
+            const double sc = ktv / (6.0 * dot3(n3, d30));
+            const double kr[3] = {sc * dot3(n0, n1), sc * dot3(n0, n2), sc * dot3(n0, n3)};
+            int off[3];
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) off[jj] = (meta >> (Meta<4>::OFF + Meta<4>::OB * jj)) & Meta<4>::OMASK;
             // Neumann sides containing Y0: the sides opposite Y1, Y2, Y3
             const uint32_t nb = (meta >> Meta<4>::NBIT) & 7u;
             if (nb) {
@@ -440,7 +516,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                     const double nn = sqrt(dot3(nf, nf));
                     const double area = 0.5 * nn;
                     double cen[3];
-                    for (int c = 0; c < 3; ++c) cen[c] = (Y0[c] + Y1[c] + Y2[c] + Y3[c] - Y[u][jj][c]) / 3.0;
+                    for (int c = 0; c < 3; ++c) cen[c] = (Y0[c] + Y1[c] + Y2[c] + Y3[c] - Yv[jj][c]) / 3.0;
                     double g;
                     if (A.gn.kind == FE_FN_DUDN_SINPROD) {
                         const double nrm[3] = {-nf[0] / nn, -nf[1] / nn, -nf[2] / nn};
@@ -448,7 +524,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                     } else if (A.gn.kind == FE_FN_NODAL) {
                         double sg = A.gn.nodal[A.pi[k]];
                         for (int c = 0; c < 3; ++c)
-                            if (c != jj) sg += A.gn.nodal[A.pi[pq[u][c]]];
+                            if (c != jj) sg += A.gn.nodal[A.pi[pqv[c]]];
                         g = sg / 3.0;
                     } else {
                         g = fn_point<3>(A.gn, cen);
@@ -474,12 +550,12 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                         if (r == jj) continue;
                         acc[off[r] * BLOCK + tid] += m1;
                         if (((db >> r) & 1u) && A.gd.kind != FE_FN_ZERO)
-                            lift += m1 * dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[pq[u][r]] : 0,
-                                                            Y[u][r]);
+                            lift += m1 * dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[pqv[r]] : 0,
+                                                            Yv[r]);
                     }
                     if (A.gr.kind != FE_FN_ZERO) {
                         double cen[3];
-                        for (int c = 0; c < 3; ++c) cen[c] = (Y0[c] + Y1[c] + Y2[c] + Y3[c] - Y[u][jj][c]) / 3.0;
+                        for (int c = 0; c < 3; ++c) cen[c] = (Y0[c] + Y1[c] + Y2[c] + Y3[c] - Yv[jj][c]) / 3.0;
                         double g;
                         if (A.gr.kind == FE_FN_DUDN_SINPROD) {
                             const double nrm[3] = {-nf[0] / nn, -nf[1] / nn, -nf[2] / nn};
@@ -487,7 +563,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                         } else if (A.gr.kind == FE_FN_NODAL) {
                             double sg = A.gr.nodal[A.pi[k]];
                             for (int c = 0; c < 3; ++c)
-                                if (c != jj) sg += A.gr.nodal[A.pi[pq[u][c]]];
+                                if (c != jj) sg += A.gr.nodal[A.pi[pqv[c]]];
                             g = sg / 3.0;
                         } else {
                             g = fn_point<3>(A.gr, cen);
@@ -500,8 +576,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
 #pragma unroll
                 for (int jj = 0; jj < 3; ++jj) {
                     if (!((db >> jj) & 1u)) continue;
-                    lift += kr[jj] * dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[pq[u][jj]] : 0,
-                                                        Y[u][jj]);
+                    lift += kr[jj] * dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[pqv[jj]] : 0,
+                                                        Yv[jj]);
                 }
             }
         }
