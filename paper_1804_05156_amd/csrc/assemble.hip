@@ -10,8 +10,9 @@
 // recomputes the element geometry from the coordinates, and adds row a into an
 // LDS accumulator slot per stored column.  This is the `sparse` duplicate sum of
 // Section 2.2 done per row, in a fixed order, with no atomics and no triplet array.
-// The same walk adds the load term of Section 3.2, the Neumann side terms and the
-// Dirichlet lifting of Section 3.3, so A, A_bc and b come out of one kernel.
+// The same walk adds the load term of Section 3.2; a second walk, taken only by
+// rows with a boundary bit, adds the Neumann and Robin side terms and the Dirichlet
+// lifting of Section 3.3, so A, A_bc and b come out of one kernel.
 //
 // Memory layout.  Rows run in the plan's processing order (an order that follows
 // the element order), so neighbouring threads touch neighbouring elements.  A
