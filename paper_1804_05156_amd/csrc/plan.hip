@@ -39,6 +39,9 @@ constexpr int BCAPMAX = 24576;  // incidences per bucket sorted in LDS at most (
 constexpr int FINE_SHIFT = 5;
 constexpr int FINE = 1 << FINE_SHIFT;   // buckets per coarse bucket
 constexpr int FB = 1024;        // threads of the coarse-to-fine kernel
+constexpr int L1SUB = 2048;     // elements per LDS-staged sub-chunk of the level-1 scatter
+static_assert(NBMAX / FINE <= L1B, "one thread per coarse bucket in the level-1 scatter");
+static_assert(L1SUB % L1B == 0, "whole sub-chunks per thread");
 constexpr int RUNR = 4;         // incidences per batch in the row kernels
 
 // Level-1 chunk of block b.  Blocks are dealt to the 8 XCDs round-robin; this gives
@@ -105,26 +108,70 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
     for (int b = threadIdx.x; b < nb; b += L1B) hist1[(int64_t)b * nblk1 + ch] = h[b];
 }
 
-// Level 1b: scatter (vertex, key) pairs into their coarse bucket's range.  Every
-// chunk writes one run per coarse bucket (a few hundred pairs: long coalesced runs).
-// The order inside a bucket is arbitrary (LDS atomics); level 2 sorts it.
+// Level 1b: scatter (vertex, key) pairs into their coarse bucket's range.  The
+// chunk is taken L1SUB elements at a time: the sub-chunk's pairs are first grouped
+// by bucket in LDS (a counting sort), then stored run by run, so consecutive lanes
+// store consecutive pairs of one bucket (a per-pair scattered store would cost one
+// memory request per pair).  The order inside a bucket is arbitrary (LDS atomics);
+// level 2 sorts it.  LDS: 2 * nb ints (dynamic), nb = number of coarse buckets.
 template <int NV>
 __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ elem, int32_t NT, int32_t bs,
                                                     int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
                                                     int2 *pairs)
 {
-    extern __shared__ int32_t cur[];
+    extern __shared__ int32_t dyn[];
+    __shared__ int2 buf[L1SUB * NV];
+    __shared__ int32_t sl[2 * (L1B / 64)];
+    int32_t *cur = dyn;        // next global position of each bucket
+    int32_t *cnt = dyn + nb;   // sub-chunk pairs per bucket, then their LDS start
+    constexpr int PER = L1SUB / L1B;
     const int32_t ch = l1_chunk(blockIdx.x, nblk1);
-    for (int b = threadIdx.x; b < nb; b += L1B) cur[b] = offs[(int64_t)b * nblk1 + ch];
+    const int tid = threadIdx.x;
+    if (tid < nb) {
+        cur[tid] = offs[(int64_t)tid * nblk1 + ch];
+        cnt[tid] = 0;
+    }
     __syncthreads();
     const int32_t t0 = ch * L1CH;
     const int32_t t1 = min(NT, t0 + L1CH);
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += L1B) {
-        for (int a = 0; a < NV; ++a) {
-            const int32_t v = elem[(int64_t)a * NT + t];
-            const int32_t pos = atomicAdd(cur + (v >> (bs + FINE_SHIFT)), 1);
-            pairs[pos] = make_int2(v, t * NV + a);
+    const int sh = bs + FINE_SHIFT;
+    for (int32_t s0 = t0; s0 < t1; s0 += L1SUB) {
+        int32_t v[PER][NV], rk[PER][NV];
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int32_t t = s0 + e * L1B + tid;
+            if (t < t1)
+#pragma unroll
+                for (int a = 0; a < NV; ++a) {
+                    v[e][a] = elem[(int64_t)a * NT + t];
+                    rk[e][a] = atomicAdd(cnt + (v[e][a] >> sh), 1);
+                }
         }
+        __syncthreads();
+        const int32_t c = tid < nb ? cnt[tid] : 0;   // this thread's bucket count
+        int32_t tot;
+        const int32_t st = block_exclusive_i32<L1B>(c, sl, &tot);
+        if (tid < nb) cnt[tid] = st;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int32_t t = s0 + e * L1B + tid;
+            if (t < t1)
+#pragma unroll
+                for (int a = 0; a < NV; ++a) buf[cnt[v[e][a] >> sh] + rk[e][a]] = make_int2(v[e][a], t * NV + a);
+        }
+        __syncthreads();
+        for (int32_t j = tid; j < tot; j += L1B) {
+            const int2 pr = buf[j];
+            const int32_t b = pr.x >> sh;
+            pairs[cur[b] + (j - cnt[b])] = pr;
+        }
+        __syncthreads();
+        if (tid < nb) {
+            cur[tid] += c;
+            cnt[tid] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -824,9 +871,11 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     if (err) return fe_status_from_bits(err);
     if (NT > 0) {
         if ((rc = fe_scan_exclusive(P->hist1, P->hist1, nh, P->totals + 4, P->part, P->status, s))) return rc;
+        FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_l1_scatter<NV>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
         FE_TIMED("k_l1_scatter", s,
-                 hipLaunchKernelGGL(k_l1_scatter<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, NT, P->bs,
-                               P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
+                 hipLaunchKernelGGL(k_l1_scatter<NV>, dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s, P->elem, NT,
+                                    P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
         FE_TIMED("k_l1_fine", s,
                  hipLaunchKernelGGL(k_l1_fine, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
                                (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs, P->pairs2, P->fstart));
