@@ -70,6 +70,14 @@ enum {
     FE_FN_DUDN_SINPROD = 4,  /* c0 * grad(prod_c sin(pi x_c)) . n, n the outward unit normal (g_N only) */
     FE_FN_NODAL = 5          /* piecewise-linear interpolant of nodal[0..N-1] (device array) */
 };
+
+/* Quadrature of the load integrals int_t f phi_i (Section 4). */
+enum {
+    FE_LOAD_DEFAULT = 0,    /* 2-D three edge midpoints, 3-D symmetric four-point rule (degree 2) */
+    FE_LOAD_CENTROID = 1,   /* one-point rule: |t| f(c_t) / (d+1) to every vertex of t (degree 1) */
+    FE_LOAD_TRAPEZOID = 2   /* vertex (trapezoidal) rule: |t| f(x_i) / (d+1) to vertex i (degree 1) */
+};
+
 typedef struct fe_fn {
     int32_t kind;
     double c[4];
@@ -166,6 +174,14 @@ int fe_assemble_robin(fe_plan *plan, const double *node, const double *kappa, co
                       const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
                       double *val, double *val_bc, double *b, double *b_load,
                       uint8_t *is_dirichlet, void *stream);
+
+/* As fe_assemble_robin, with the load integrals int_t f phi_i taken by load_rule
+ * (FE_LOAD_*, Section 4; any other value: FE_EINVAL).  The side terms of g_n and g_r
+ * keep their rules.  fe_assemble_robin is this call with FE_LOAD_DEFAULT. */
+int fe_assemble_quad(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                     const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
+                     int32_t load_rule, double *val, double *val_bc, double *b, double *b_load,
+                     uint8_t *is_dirichlet, void *stream);
 
 /* y = A x for a CSR matrix (device arrays; n rows). */
 int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,

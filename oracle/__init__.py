@@ -80,11 +80,13 @@ def lib():
                                          P, P, P, P, P, P, P, P, P]
         _lib.oracle_assemble_robin.argtypes = [C.c_int, I64, I64, P, P, P, P, P, P, P, P, C.c_double, I64,
                                                P, P, P, P, P, P, P, P, P]
+        _lib.oracle_assemble_rule.argtypes = [C.c_int, I64, I64, P, P, P, P, P, P, P, P, C.c_double, C.c_int,
+                                              I64, P, P, P, P, P, P, P, P, P]
         _lib.oracle_solve.argtypes = [I64, P, P, P, P, P, P, C.c_double, I64, C.c_int, P, P]
         _lib.oracle_grad.argtypes = [C.c_int, I64, I64, P, P, P, P, P]
         _lib.oracle_spmv.argtypes = [I64, P, P, P, P, P]
         for name in ("oracle_coo_to_csr", "oracle_local_stiffness", "oracle_assemble",
-                     "oracle_assemble_robin", "oracle_solve", "oracle_grad", "oracle_spmv"):
+                     "oracle_assemble_robin", "oracle_assemble_rule", "oracle_solve", "oracle_grad", "oracle_spmv"):
             getattr(_lib, name).restype = C.c_int
     return _lib
 
@@ -164,10 +166,18 @@ class Assembled:
         return d
 
 
+# quadrature of the load integrals int_t f phi_a (Section 4)
+LOAD_DEFAULT = 0     # three edge midpoints (2-D), symmetric four-point rule (3-D)
+LOAD_CENTROID = 1    # one-point rule at the barycentre
+LOAD_TRAPEZOID = 2   # vertex (trapezoidal) rule
+
+
 def assemble(node, elem, bdflag=None, kappa=None, f: Fn | None = None, gD: Fn | None = None,
-             gN: Fn | None = None, gR: Fn | None = None, alpha: float = 0.0) -> Assembled:
+             gN: Fn | None = None, gR: Fn | None = None, alpha: float = 0.0,
+             rule: int = LOAD_DEFAULT) -> Assembled:
     """Assemble A (CSR), the lifted right-hand side b and the boundary data.  Robin
-    sides (bdflag 3) use kappa grad(u).n + alpha u = g_R."""
+    sides (bdflag 3) use kappa grad(u).n + alpha u = g_R; ``rule`` picks the load
+    quadrature (LOAD_*)."""
     node = np.ascontiguousarray(node, np.float64)
     elem = np.ascontiguousarray(elem, np.int32)
     dim = node.shape[0]
@@ -187,9 +197,9 @@ def assemble(node, elem, bdflag=None, kappa=None, f: Fn | None = None, gD: Fn | 
     nnz = np.zeros(1, np.int64)
     fs = [x._c() if x is not None else None for x in (f, gD, gN, gR)]
     refs = [C.byref(x) if x is not None else None for x in fs]
-    st = lib().oracle_assemble_robin(dim, N, NT, _p(node), _p(elem), _p(bd), _p(kp), refs[0], refs[1],
-                                     refs[2], refs[3], C.c_double(alpha), cap, _p(rowptr), _p(colind), _p(val),
-                                     _p(val_bc), _p(b), _p(b_load), _p(is_d), _p(b_scale), _p(nnz))
+    st = lib().oracle_assemble_rule(dim, N, NT, _p(node), _p(elem), _p(bd), _p(kp), refs[0], refs[1],
+                                    refs[2], refs[3], C.c_double(alpha), int(rule), cap, _p(rowptr), _p(colind),
+                                    _p(val), _p(val_bc), _p(b), _p(b_load), _p(is_d), _p(b_scale), _p(nnz))
     if st:
         raise OracleError(st, "assemble")
     k = int(nnz[0])

@@ -17,7 +17,8 @@
  *     (row, column) and adds duplicates left to right (Section 2.2);
  *   - load vector: 2-D three edge-midpoint rule (Section 3.2 and Section 4); 3-D
  *     symmetric four-point rule of degree two (the paper names a 4-point rule but
- *     lists none; the reading used here is recorded in the design notes);
+ *     lists none; the reading used here is recorded in the design notes); on
+ *     request the one-point (centroid) or the trapezoidal (vertex) rule of Section 4;
  *   - Dirichlet lifting b <- b - A u_D and Neumann side integrals by the midpoint
  *     (2-D) / centroid (3-D) rule (Section 3.3);
  *   - solve on the free nodes (equation (directsolve)): dense Cholesky when small,
@@ -280,13 +281,30 @@ static void gather_coords(int dim, int64_t N, int64_t NT, const double *node, co
  *   *nnz        number of stored entries
  */
 /* Robin sides (bdflag 3) carry kappa grad(u).n + alpha u = g_R: the side mass term
- * alpha int_F u v joins A and int_F g_R v joins b.  oracle_assemble is the case
- * alpha = 0, g_R = 0. */
+ * alpha int_F u v joins A and int_F g_R v joins b.  load_rule selects the quadrature
+ * of int_t f phi_a (Section 4): OR_LOAD_DEFAULT the rules above, OR_LOAD_CENTROID
+ * the one-point rule f(c_t) phi_a(c_t) |t| = f(c_t) |t| / (d+1), OR_LOAD_TRAPEZOID
+ * the vertex rule sum_e f(x_e) phi_a(x_e) |t| / (d+1) = f(x_a) |t| / (d+1).
+ * oracle_assemble_robin is the default rule; oracle_assemble is also alpha = 0,
+ * g_R = 0. */
+#define OR_LOAD_DEFAULT 0
+#define OR_LOAD_CENTROID 1
+#define OR_LOAD_TRAPEZOID 2
+int oracle_assemble_rule(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
+                         const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
+                         const or_fn *gN, const or_fn *gR, double alpha_r, int load_rule, int64_t nnz_cap,
+                         int64_t *rowptr, int64_t *colind, double *val, double *val_bc, double *b,
+                         double *b_load, uint8_t *is_d, double *b_scale, int64_t *nnz);
+
 int oracle_assemble_robin(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
                           const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
                           const or_fn *gN, const or_fn *gR, double alpha_r, int64_t nnz_cap,
                           int64_t *rowptr, int64_t *colind, double *val, double *val_bc, double *b,
-                          double *b_load, uint8_t *is_d, double *b_scale, int64_t *nnz);
+                          double *b_load, uint8_t *is_d, double *b_scale, int64_t *nnz)
+{
+    return oracle_assemble_rule(dim, N, NT, node, elem, bdflag, kappa, f, gD, gN, gR, alpha_r, OR_LOAD_DEFAULT,
+                                nnz_cap, rowptr, colind, val, val_bc, b, b_load, is_d, b_scale, nnz);
+}
 
 int oracle_assemble(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
                     const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
@@ -309,15 +327,17 @@ static double side_measure(int dim, double meas, const double *G, int a, double 
     return dim * meas * gn;
 }
 
-int oracle_assemble_robin(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
-                          const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
-                          const or_fn *gN, const or_fn *gR, double alpha_r, int64_t nnz_cap,
-                          int64_t *rowptr, int64_t *colind, double *val, double *val_bc, double *b,
-                          double *b_load, uint8_t *is_d, double *b_scale, int64_t *nnz)
+int oracle_assemble_rule(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
+                         const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
+                         const or_fn *gN, const or_fn *gR, double alpha_r, int load_rule, int64_t nnz_cap,
+                         int64_t *rowptr, int64_t *colind, double *val, double *val_bc, double *b,
+                         double *b_load, uint8_t *is_d, double *b_scale, int64_t *nnz)
 {
     if (dim != 2 && dim != 3) return OR_EUNSUPPORTED;
     const int nv = dim + 1;
     if (N <= 0 || NT < 0 || nnz_cap < (int64_t)nv * nv * NT) return OR_EINVAL;
+    if (load_rule != OR_LOAD_DEFAULT && load_rule != OR_LOAD_CENTROID && load_rule != OR_LOAD_TRAPEZOID)
+        return OR_EINVAL;
     if (!(alpha_r >= 0.0) || !isfinite(alpha_r)) return OR_EINVAL;
     for (int64_t k = 0; k < (int64_t)nv * NT; ++k)
         if (elem[k] < 0 || elem[k] >= N) return OR_EINVAL;
@@ -390,7 +410,24 @@ int oracle_assemble_robin(int dim, int64_t N, int64_t NT, const double *node, co
     /* Load vector (Section 3.2): per-element contributions bt[a*NT + t]. */
     for (int64_t t = 0; t < NT; ++t) {
         gather_coords(dim, N, NT, node, elem, t, p, verts);
-        if (dim == 2) {
+        if (load_rule == OR_LOAD_CENTROID) {
+            /* one-point rule at the barycentre c_t, where every phi_a is 1/(d+1) */
+            double x[3] = {0, 0, 0}, bary[4];
+            for (int e = 0; e < nv; ++e) {
+                bary[e] = 1.0 / nv;
+                for (int c = 0; c < dim; ++c) x[c] += p[e * dim + c] / nv;
+            }
+            const double fc = fn_eval(f, dim, x, nv, bary, verts, NULL);
+            for (int a = 0; a < nv; ++a) bt[a * NT + t] = area[t] * fc / nv;
+        } else if (load_rule == OR_LOAD_TRAPEZOID) {
+            /* vertex rule: at x_e only phi_e is non-zero (and equal to 1) */
+            for (int a = 0; a < nv; ++a) {
+                double bary[4];
+                for (int e = 0; e < nv; ++e) bary[e] = (e == a) ? 1.0 : 0.0;
+                const double fa = fn_eval(f, dim, p + a * dim, nv, bary, verts, NULL);
+                bt[a * NT + t] = area[t] * fa / nv;
+            }
+        } else if (dim == 2) {
             /* mid_a = midpoint of the edge opposite vertex a; three-midpoint rule */
             double mid[3][2], fm[3], bary[3];
             for (int a = 0; a < 3; ++a) {

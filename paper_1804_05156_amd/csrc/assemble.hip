@@ -36,6 +36,7 @@ struct AsmArgs {
     const double *xyp, *fp;
     DevFn f, gd, gn, gr;
     double ralpha;         // Robin coefficient alpha (kappa grad(u).n + alpha u = g_R)
+    int32_t load_rule;     // FE_LOAD_*: quadrature of the load integrals
     double *valp;          // rows in processing order: row k at prowptr[k] + 2k, its values
                            // followed by (b, b_load)
     int32_t *status;
@@ -171,6 +172,11 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
     int32_t err = 0;
     const bool nodal_f = A.f.kind == FE_FN_NODAL;
     const double fi = nodal_f ? A.fp[k] : 0.0;
+    double fvert = 0.0;   // f at the row's vertex (vertex rule)
+    if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) {
+        const double x0[2] = {X0.x, X0.y};
+        fvert = nodal_f ? fi : fn_point<2>(A.f, x0);
+    }
     // incidence bits that call for the boundary walk (lifting only with g_D != 0)
     const uint32_t BND = (3u << Meta<3>::NBIT) | (3u << Meta<3>::RBIT) |
                          (A.gd.kind != FE_FN_ZERO ? 3u << Meta<3>::DBIT : 0u);
@@ -220,19 +226,34 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
             acc[diag * BLOCK + tid] += k00;
             acc[o1 * BLOCK + tid] += k01;
             acc[o2 * BLOCK + tid] += k02;
-            // load: |t| (f(m1) + f(m2)) / 6, m1 = (X2+X0)/2, m2 = (X0+X1)/2 (Section 3.2)
+            // load: |t| (f(m1) + f(m2)) / 6, m1 = (X2+X0)/2, m2 = (X0+X1)/2 (Section 3.2),
+            // or the one-point rule |t| f(c_t) / 3, or the vertex rule |t| f(x_i) / 3
+            // (Section 4)
             if (A.f.kind != FE_FN_ZERO) {
-                double f1, f2;
-                if (nodal_f) {
-                    f1 = 0.5 * (A.fp[p2[u]] + fi);
-                    f2 = 0.5 * (fi + A.fp[p1[u]]);
+                if (A.load_rule == FE_LOAD_DEFAULT) {
+                    double f1, f2;
+                    if (nodal_f) {
+                        f1 = 0.5 * (A.fp[p2[u]] + fi);
+                        f2 = 0.5 * (fi + A.fp[p1[u]]);
+                    } else {
+                        const double m1[2] = {0.5 * (X2[u].x + X0.x), 0.5 * (X2[u].y + X0.y)};
+                        const double m2[2] = {0.5 * (X0.x + X1[u].x), 0.5 * (X0.y + X1[u].y)};
+                        f1 = fn_point<2>(A.f, m1);
+                        f2 = fn_point<2>(A.f, m2);
+                    }
+                    bsum += area2 * (f1 + f2) / 12.0;
+                } else if (A.load_rule == FE_LOAD_CENTROID) {
+                    double fc;
+                    if (nodal_f) {
+                        fc = (fi + A.fp[p1[u]] + A.fp[p2[u]]) / 3.0;
+                    } else {
+                        const double c[2] = {(X0.x + X1[u].x + X2[u].x) / 3.0, (X0.y + X1[u].y + X2[u].y) / 3.0};
+                        fc = fn_point<2>(A.f, c);
+                    }
+                    bsum += area2 * fc / 6.0;
                 } else {
-                    const double m1[2] = {0.5 * (X2[u].x + X0.x), 0.5 * (X2[u].y + X0.y)};
-                    const double m2[2] = {0.5 * (X0.x + X1[u].x), 0.5 * (X0.y + X1[u].y)};
-                    f1 = fn_point<2>(A.f, m1);
-                    f2 = fn_point<2>(A.f, m2);
+                    bsum += area2 * fvert / 6.0;
                 }
-                bsum += area2 * (f1 + f2) / 12.0;
             }
             bmask |= meta;
         }
@@ -384,6 +405,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     const double beta = 0.13819660112501051518;    // (5 - sqrt 5) / 20
     const bool nodal_f = A.f.kind == FE_FN_NODAL;
     const double fi = nodal_f ? A.fp[k] : 0.0;
+    double fvert = 0.0;   // f at the row's vertex (vertex rule)
+    if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) fvert = nodal_f ? fi : fn_point<3>(A.f, Y0);
     const uint32_t BND = (7u << Meta<4>::NBIT) | (7u << Meta<4>::RBIT) |
                          (A.gd.kind != FE_FN_ZERO ? 7u << Meta<4>::DBIT : 0u);
     uint32_t bmask = 0;
@@ -447,8 +470,21 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                 acc[off[jj] * BLOCK + tid] += kr[jj];
             }
             const double vol = vol6 / 6.0;
-            // load (Section 3.2): symmetric 4-point rule; exact closed form for nodal f
-            if (nodal_f) {
+            // load (Section 3.2): symmetric 4-point rule; exact closed form for nodal f.
+            // Section 4's one-point rule |t| f(c_t) / 4 and vertex rule |t| f(x_i) / 4 on request.
+            if (A.load_rule == FE_LOAD_CENTROID && A.f.kind != FE_FN_ZERO) {
+                double fc;
+                if (nodal_f) {
+                    fc = (fi + A.fp[pq[u][0]] + A.fp[pq[u][1]] + A.fp[pq[u][2]]) / 4.0;
+                } else {
+                    double c[3];
+                    for (int q = 0; q < 3; ++q) c[q] = (Y0[q] + Y1[q] + Y2[q] + Y3[q]) / 4.0;
+                    fc = fn_point<3>(A.f, c);
+                }
+                bsum += vol * fc / 4.0;
+            } else if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) {
+                bsum += vol * fvert / 4.0;
+            } else if (nodal_f) {
                 const double sf = fi + A.fp[pq[u][0]] + A.fp[pq[u][1]] + A.fp[pq[u][2]];
                 bsum += vol * (fi + sf) / 20.0;
             } else if (A.f.kind != FE_FN_ZERO) {
@@ -601,12 +637,14 @@ template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream
 
 }  // namespace
 
-extern "C" int fe_assemble_robin(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
-                                 const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
-                                 double *val, double *val_bc, double *b, double *b_load, uint8_t *is_dirichlet,
-                                 void *stream)
+extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                                const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
+                                int32_t load_rule, double *val, double *val_bc, double *b, double *b_load,
+                                uint8_t *is_dirichlet, void *stream)
 {
     if (!plan || !node || !val || !b) return FE_EINVAL;
+    if (load_rule != FE_LOAD_DEFAULT && load_rule != FE_LOAD_CENTROID && load_rule != FE_LOAD_TRAPEZOID)
+        return FE_EINVAL;
     if (!plan->pattern_done) return FE_EINVAL;
     if (!devfn_valid(f, false) || !devfn_valid(g_d, false) || !devfn_valid(g_n, true) || !devfn_valid(g_r, true))
         return FE_EINVAL;
@@ -628,6 +666,7 @@ extern "C" int fe_assemble_robin(fe_plan *plan, const double *node, const double
     A.gn = make_devfn(g_n);
     A.gr = make_devfn(g_r);
     A.ralpha = robin_alpha;
+    A.load_rule = load_rule;
     A.valp = plan->valp;
     A.status = plan->status;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -653,6 +692,15 @@ extern "C" int fe_assemble_robin(fe_plan *plan, const double *node, const double
                            (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,
                            (const double *)plan->valp, val, val_bc, b, b_load, is_dirichlet));
     return fe_launch_check();
+}
+
+extern "C" int fe_assemble_robin(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                                 const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
+                                 double *val, double *val_bc, double *b, double *b_load, uint8_t *is_dirichlet,
+                                 void *stream)
+{
+    return fe_assemble_quad(plan, node, kappa, f, g_d, g_n, g_r, robin_alpha, FE_LOAD_DEFAULT, val, val_bc, b, b_load,
+                            is_dirichlet, stream);
 }
 
 extern "C" int fe_assemble(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,

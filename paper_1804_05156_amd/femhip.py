@@ -20,11 +20,13 @@ LIB_PATH = os.path.join(_HERE, "libfemhip.so")
 FE_OK, FE_EINVAL, FE_EMESH, FE_EUNSUPPORTED, FE_EOVERFLOW = 0, -1, -2, -3, -4
 FE_ESIZE, FE_EHIP, FE_ENOCONV, FE_ELIMIT = -5, -6, -7, -8
 FE_FN_ZERO, FE_FN_CONST, FE_FN_LINEAR, FE_FN_SINPROD, FE_FN_DUDN_SINPROD, FE_FN_NODAL = range(6)
+FE_LOAD_DEFAULT, FE_LOAD_CENTROID, FE_LOAD_TRAPEZOID = range(3)
 
 # Entry points declared in include/femhip.h.
 ENTRY_POINTS = (
     "fe_version", "fe_status_string", "fe_plan_workspace_bytes", "fe_plan_create", "fe_plan_pattern",
-    "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_assemble_robin", "fe_spmv",
+    "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_assemble_robin",
+    "fe_assemble_quad", "fe_spmv",
     "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_neumann_workspace_bytes", "fe_neumann_solve",
     "fe_grad", "fe_batch_solve_workspace_bytes",
     "fe_batch_solve", "fe_batch_create", "fe_batch_set_grid", "fe_batch_get_info", "fe_batch_assemble_solve",
@@ -84,6 +86,8 @@ def _load():
                         C.c_int),
         "fe_assemble_robin": ([P, P, P, C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), D,
                                P, P, P, P, P, P], C.c_int),
+        "fe_assemble_quad": ([P, P, P, C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), D,
+                              I32, P, P, P, P, P, P], C.c_int),
         "fe_spmv": ([I64, P, P, P, P, P, P], C.c_int),
         "fe_solve_workspace_bytes": ([I64, C.POINTER(SZ)], C.c_int),
         "fe_solve": ([I64, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), P], C.c_int),
@@ -226,6 +230,15 @@ def fe_assemble_robin(plan, node, kappa, f: Fn | None, gD: Fn | None, gN: Fn | N
                                   _ptr(val, torch.float64, "val"), _ptr(val_bc, torch.float64, "val_bc"),
                                   _ptr(b, torch.float64, "b"), _ptr(b_load, torch.float64, "b_load"),
                                   _ptr(is_d, torch.uint8, "is_dirichlet"), _stream(stream)), "fe_assemble_robin")
+
+
+def fe_assemble_quad(plan, node, kappa, f: Fn | None, gD: Fn | None, gN: Fn | None, gR: Fn | None,
+                     robin_alpha: float, load_rule: int, val, val_bc, b, b_load, is_d, stream=None):
+    _check(_lib.fe_assemble_quad(plan, _ptr(node, torch.float64, "node"), _ptr(kappa, torch.float64, "kappa"),
+                                 _fnref(f), _fnref(gD), _fnref(gN), _fnref(gR), float(robin_alpha), int(load_rule),
+                                 _ptr(val, torch.float64, "val"), _ptr(val_bc, torch.float64, "val_bc"),
+                                 _ptr(b, torch.float64, "b"), _ptr(b_load, torch.float64, "b_load"),
+                                 _ptr(is_d, torch.uint8, "is_dirichlet"), _stream(stream)), "fe_assemble_quad")
 
 
 def fe_spmv(rowptr, colind, val, x, y, stream=None):
@@ -400,9 +413,10 @@ class Plan:
 
     def assemble(self, kappa=None, f: Fn | None = None, gD: Fn | None = None, gN: Fn | None = None, node=None,
                  outputs: str = "all", stream=None, out: Assembly | None = None, gR: Fn | None = None,
-                 robin_alpha: float = 0.0) -> Assembly:
+                 robin_alpha: float = 0.0, load_rule: int = FE_LOAD_DEFAULT) -> Assembly:
         """outputs: "all" (val, val_bc, b, b_load, is_dirichlet) or "min" (val, b).  gR and
-        robin_alpha are the Robin data (kappa grad(u).n + robin_alpha u = gR on bdflag-3 sides)."""
+        robin_alpha are the Robin data (kappa grad(u).n + robin_alpha u = gR on bdflag-3 sides);
+        load_rule is the quadrature of the load integrals (FE_LOAD_*)."""
         node = self.node if node is None else node
         dev = node.device
         if out is None:
@@ -413,7 +427,10 @@ class Plan:
                 torch.empty(self.N, dtype=torch.float64, device=dev),
                 torch.empty(self.N, dtype=torch.float64, device=dev) if full else None,
                 torch.empty(self.N, dtype=torch.uint8, device=dev) if full else None)
-        if gR is None and robin_alpha == 0.0:
+        if load_rule != FE_LOAD_DEFAULT:
+            fe_assemble_quad(self.handle, node, kappa, f, gD, gN, gR, robin_alpha, load_rule, out.val, out.val_bc,
+                             out.b, out.b_load, out.is_dirichlet, stream)
+        elif gR is None and robin_alpha == 0.0:
             fe_assemble(self.handle, node, kappa, f, gD, gN, out.val, out.val_bc, out.b, out.b_load,
                         out.is_dirichlet, stream)
         else:

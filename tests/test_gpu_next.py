@@ -177,6 +177,48 @@ def test_robin_parity_3d(seed, n):
     log(f"  faces {faces}, worst scaled value error {worst:.2e}")
 
 
+@pytest.mark.parametrize("rule", [1, 2])
+@pytest.mark.parametrize("dim,n", [(2, 17), (3, 6)])
+def test_load_rules_parity(rule, dim, n):
+    """Section 4's one-point (centroid) and trapezoidal (vertex) load rules on the GPU
+    against the oracle's, with analytic and nodal f, Neumann, Robin and Dirichlet
+    sides: pattern bit-exact, values and right-hand sides to the parity tolerance."""
+    from paper_1804_05156_amd import femhip
+    log(f"case: load rule {rule}, dim {dim}, n {n}")
+    if dim == 2:
+        m = meshgen.square_mesh(n, jitter=0.2, permute=True, seed=40 + rule, kappa="lognormal", sides=(1, 2, 3, 2))
+        fa = (FE_FN_SINPROD, (2 * math.pi ** 2,))
+        gd, gn, gr = (FE_FN_LINEAR, (0.3, 1.1, -0.7)), (FE_FN_DUDN_SINPROD, (1.0,)), (FE_FN_LINEAR, (0.2, -0.5, 0.4))
+    else:
+        m = meshgen.kuhn_cube(n, jitter=0.15, permute=True, seed=50 + rule, kappa="lognormal", faces=(1, 1, 2, 3, 2, 2))
+        fa = (FE_FN_SINPROD, (3 * math.pi ** 2,))
+        gd, gn, gr = ((FE_FN_LINEAR, (0.3, 1.1, -0.7, 0.4)), (FE_FN_DUDN_SINPROD, (1.0,)),
+                      (FE_FN_LINEAR, (0.5, 0.2, 0.1, -0.3)))
+    fnod = (FE_FN_NODAL, (0.0,), np.cos(math.pi * m.node).prod(axis=0) + 0.5)
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    for fspec in (fa, fnod):
+        specs = [fspec, gd, gn]
+        (f, fo), (gdf, gdo), (gnf, gno) = fns(*specs)
+        (grf, gro), _, _ = fns(gr)
+        asm = plan.assemble(kap, f, gdf, gnf, gR=grf, robin_alpha=1.2, load_rule=rule)
+        plan.check()
+        torch.cuda.synchronize()
+        ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno, gR=gro, alpha=1.2, rule=rule)
+        worst = compare(host(plan, asm), ora, data=data_scale(m, specs, gr))
+        log(f"  f kind {fspec[0]}: worst scaled value error {worst:.2e}")
+
+
+def test_load_rule_rejected():
+    from paper_1804_05156_amd import femhip
+    log("case: unknown load rule")
+    m = meshgen.square_mesh(5)
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    with pytest.raises(femhip.FemhipError):
+        plan.assemble(kap, None, load_rule=3)
+
+
 def test_robin_second_order_convergence_gpu():
     """All sides Robin, u = cos(pi x) cos(pi y) (du/dn = 0, so g_R = alpha u), f = 2 pi^2 u
     as nodal data: the GPU solution's L2 error decays like h^2."""

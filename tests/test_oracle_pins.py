@@ -370,6 +370,89 @@ def test_quadratic_exactness_of_sin_rule_limit():
     assert r1 > 1.9 and r2 > 1.9          # at least second order (fourth on uniform grids)
 
 
+# --------------------------------------------------------------------------- load rules of Section 4
+def _rule_mesh(dim, seed):
+    return meshgen.square_mesh(7, jitter=0.2, seed=seed) if dim == 2 else meshgen.kuhn_cube(4, jitter=0.2, seed=seed)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("rule", [oracle.LOAD_CENTROID, oracle.LOAD_TRAPEZOID])
+def test_first_order_rules_exact_for_constant_f(dim, rule):
+    """Section 4: the one-point and the trapezoidal rules are exact for linear
+    integrands, so for constant f (integrand f phi_i, linear) they give the exact
+    load, which the default rule (exact for quadratics) also gives."""
+    m = _rule_mesh(dim, 11)
+    fn = Fn(FN_CONST, (1.7,))
+    ref = oracle.assemble(m.node, m.elem, m.bdflag, None, f=fn).b_load
+    got = oracle.assemble(m.node, m.elem, m.bdflag, None, f=fn, rule=rule).b_load
+    assert np.allclose(got, ref, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_first_order_rules_error_identity_for_linear_f(dim):
+    """For linear f on a simplex, int_t f phi_a = |t| (sum_e f_e + f_a) / ((d+1)(d+2))
+    while the one-point rule gives |t| sum_e f_e / (d+1)^2 and the trapezoidal rule
+    |t| f_a / (d+1).  Their errors satisfy trap - exact = (d+1) (exact - centroid)
+    element by element, hence b_trap + (d+1) b_centroid = (d+2) b_exact for the
+    assembled vectors (the default rule is exact here, test above).  A wrong point,
+    weight or vertex in either first-order rule breaks the identity."""
+    m = _rule_mesh(dim, 12)
+    fn = Fn(FN_LINEAR, (0.4, -1.3, 0.9, 1.6))
+    ex = oracle.assemble(m.node, m.elem, m.bdflag, None, f=fn).b_load
+    ce = oracle.assemble(m.node, m.elem, m.bdflag, None, f=fn, rule=oracle.LOAD_CENTROID).b_load
+    tr = oracle.assemble(m.node, m.elem, m.bdflag, None, f=fn, rule=oracle.LOAD_TRAPEZOID).b_load
+    scale = np.abs(ex).max()
+    assert np.allclose(tr + (dim + 1) * ce, (dim + 2) * ex, rtol=0, atol=1e-13 * scale)
+    # the three vectors differ (the identity is not trivially met)
+    assert np.abs(ce - ex).max() > 1e-6 * scale and np.abs(tr - ex).max() > 1e-6 * scale
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("rule", [oracle.LOAD_CENTROID, oracle.LOAD_TRAPEZOID])
+def test_first_order_rules_integrate_linear_f(dim, rule):
+    """The hat functions sum to one, so sum_i b_i is the rule applied to f itself,
+    exact for linear f: on the unit square / cube, int (c0 + c . x) = c0 + sum(c)/2."""
+    m = _rule_mesh(dim, 13)
+    c = (0.4, -1.3, 0.9, 1.6)
+    b = oracle.assemble(m.node, m.elem, m.bdflag, None, f=Fn(FN_LINEAR, c), rule=rule).b_load
+    assert abs(b.sum() - (c[0] + sum(c[1:1 + dim]) / 2)) < 1e-13
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_trapezoidal_rule_is_nodal_scaling(dim):
+    """The trapezoidal rule samples f at the vertices only, where phi_i is 1 at x_i and
+    0 at the others: b_i = f(x_i) sum_{t containing i} |t|/(d+1), i.e. f(x_i) times
+    the load of f = 1 (the lumped mass)."""
+    m = _rule_mesh(dim, 14)
+    one = oracle.assemble(m.node, m.elem, m.bdflag, None, f=Fn(FN_CONST, (1.0,)),
+                          rule=oracle.LOAD_TRAPEZOID).b_load
+    b = oracle.assemble(m.node, m.elem, m.bdflag, None, f=Fn(FN_SINPROD, (2.5,)),
+                        rule=oracle.LOAD_TRAPEZOID).b_load
+    fx = 2.5 * np.prod(np.sin(math.pi * m.node), axis=0)
+    assert np.allclose(b, fx * one, rtol=1e-13, atol=1e-16)
+
+
+@pytest.mark.parametrize("rule", [oracle.LOAD_CENTROID, oracle.LOAD_TRAPEZOID])
+def test_first_order_rules_keep_second_order_convergence(rule):
+    """Section 3.2: a one-point rule is adequate for the linear element on
+    quasi-uniform meshes; the L2 error of u = sin(pi x) sin(pi y) still decays like
+    h^2 with either first-order rule."""
+    errs = []
+    for n in (9, 17, 33):
+        m = meshgen.square_mesh(n)
+        a = oracle.assemble(m.node, m.elem, m.bdflag, None, f=Fn(FN_SINPROD, (2 * math.pi ** 2,)), rule=rule)
+        u, _, _ = oracle.solve(a, rtol=1e-13, method="direct")
+        errs.append(_l2_error_2d(m, u))
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    assert all(1.85 < r < 2.15 for r in rates), rates
+
+
+def test_unknown_load_rule_rejected():
+    m = _rule_mesh(2, 15)
+    with pytest.raises(oracle.OracleError):
+        oracle.assemble(m.node, m.elem, m.bdflag, None, f=Fn(FN_CONST, (1.0,)), rule=3)
+
+
 # --------------------------------------------------------------------------- boundary conditions
 def test_boundary_flag_example():
     """Section 1.2 example bdFlag = [1 0 2]: the side opposite vertex 1 is Dirichlet,
