@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-next", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 3-D (129^3 Kuhn cube) assembly section")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (for counter calibration)")
     args = ap.parse_args()
@@ -250,6 +251,7 @@ def main():
     cold_bytes = in_bytes + (N + 1) * 4 + nnz * 4 + 2 * nnz * 8 + 2 * N * 8 + N
     warm_bytes = in_bytes - (dim + 1) * NT + 2 * nnz * 8 + 2 * N * 8 + N
 
+    c3 = None if (args.no_c3 or args.workload == "kuhn129") else bench_c3(args)
     nxt = None if args.no_next else bench_next(args)
     batched = None if args.no_batch else bench_batched(args)
     adjoint = None if args.no_adjoint else bench_adjoint(args)
@@ -278,6 +280,7 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
                      "avg_us": dom_us},
+        "c3": c3,
         "batched": batched,
         "next": nxt,
         "adjoint": adjoint,
@@ -342,6 +345,80 @@ def bench_batched(args):
             "blocks_per_cu": info["blocks_per_cu"], "units_per_step": info["units_per_step"],
             "cooperative_in_graph": bool(info["cooperative"]),
             "autotune_ms": tune.get("ms")}
+
+
+def bench_c3(args):
+    """The 3-D configuration: 129^3 Kuhn cube (12.6M tetrahedra), lognormal kappa, nodal
+    f, Dirichlet on x = 0, 1 and Neumann g_N = du/dn elsewhere.  Cold step (plan +
+    pattern + numeric assembly) and warm numeric assembly, event-timed, plus the 3-D
+    numeric kernel's algorithmic rate."""
+    import numpy as np
+    import torch
+    from paper_1804_05156_amd import femhip, meshgen
+    dev = torch.device("cuda:0")
+    log("[bench] c3: 129^3 Kuhn cube")
+    m = meshgen.workload("kuhn129")
+    N, NT = m.n_node, m.n_elem
+    node = torch.from_numpy(m.node).to(dev)
+    elem = torch.from_numpy(m.elem).to(dev)
+    bd = torch.from_numpy(m.bdflag).to(dev)
+    kappa = torch.from_numpy(m.kappa).to(dev)
+    u = torch.prod(torch.sin(math.pi * node), dim=0)
+    f = femhip.Fn(femhip.FE_FN_NODAL, (0,), (3 * math.pi ** 2 * u).contiguous())
+    gn = femhip.Fn(femhip.FE_FN_DUDN_SINPROD, (1.0,))
+    mesh = femhip.make_mesh(node, elem, bd)
+    ws = torch.empty(femhip.fe_plan_workspace_bytes(mesh), dtype=torch.uint8, device=dev)
+    plan, nnz = femhip.fe_plan_create(mesh, ws)
+    femhip.fe_plan_destroy(plan)
+    rowptr = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    colind = torch.empty(nnz, dtype=torch.int32, device=dev)
+    val = torch.empty(nnz, dtype=torch.float64, device=dev)
+    val_bc = torch.empty_like(val)
+    b = torch.empty(N, dtype=torch.float64, device=dev)
+    b_load = torch.empty_like(b)
+    isd = torch.empty(N, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    reps = max(1, min(args.steps, 10))
+
+    def cold():
+        p, _ = femhip.fe_plan_create(mesh, ws)
+        femhip.fe_plan_pattern(p, rowptr, colind)
+        femhip.fe_assemble(p, node, kappa, f, None, gn, val, val_bc, b, b_load, isd)
+        return p
+
+    femhip.fe_plan_destroy(cold())
+    torch.cuda.synchronize()
+    plans = []
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plans.append(cold())
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - t0) / reps * 1e3
+    rc = femhip.fe_plan_status(plans[-1])
+    if rc != 0:
+        raise RuntimeError(f"kernel status {rc}")
+    for p in plans[:-1]:
+        femhip.fe_plan_destroy(p)
+    plan = plans[-1]
+    femhip.fe_prof_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        femhip.fe_assemble(plan, node, kappa, f, None, gn, val, val_bc, b, b_load, isd)
+    e1.record(stream)
+    e1.synchronize()
+    kern = femhip.fe_prof_read()
+    femhip.fe_prof_enable(False)
+    femhip.fe_plan_destroy(plan)
+    warm_ms = e0.elapsed_time(e1) / reps
+    k3 = kern.get("k_assemble_3d")
+    k3_us = k3["avg_ms"] * 1e3 if k3 else None
+    k3_bytes = kernel_bytes("k_assemble_3d", N, NT, nnz, 3, True)
+    return {"workload": "kuhn129: 129^3 Kuhn cube, lognormal kappa, nodal f, Dirichlet x = 0, 1, Neumann elsewhere",
+            "n_node": N, "n_elem": NT, "nnz": nnz, "cold_ms": cold_ms, "cold_elements_per_s": NT / (cold_ms * 1e-3),
+            "warm_ms": warm_ms, "warm_elements_per_s": NT / (warm_ms * 1e-3),
+            "k_assemble_3d_us": k3_us,
+            "k_assemble_3d_GBps": (k3_bytes / (k3_us * 1e-6) / 1e9) if k3_us else None}
 
 
 def bench_next(args):

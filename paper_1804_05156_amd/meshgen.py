@@ -161,8 +161,8 @@ def kuhn_cube(n: int, *, jitter: float = 0.0, permute: bool = False, seed: int |
         d = rng.uniform(-jitter, jitter, size=(int(interior.sum()), 3)) * h
         coords[:, interior] += d.T
     cl, cj, ci = np.meshgrid(np.arange(n - 1), np.arange(n - 1), np.arange(n - 1), indexing="ij")
-    base = np.stack([ci.ravel(), cj.ravel(), cl.ravel()])           # (3, ncell)
-    ncell = base.shape[1]
+    base = [ci.ravel(), cj.ravel(), cl.ravel()]                    # cell corner per axis
+    ncell = base[0].size
     eye = np.eye(3, dtype=np.int64)
     tets = []
     for s in itertools.permutations(range(3)):
@@ -170,21 +170,24 @@ def kuhn_cube(n: int, *, jitter: float = 0.0, permute: bool = False, seed: int |
         if _perm_sign(s) < 0:
             corners[1], corners[2] = corners[2], corners[1]
         tets.append(corners)
-    # element order: cell-major, then the 6 permutations
-    ivert = np.empty((4, 3, ncell, 6), dtype=np.int64)   # (local vertex, axis, cell, tet)
-    for k, corners in enumerate(tets):
-        for a in range(4):
-            ivert[a, :, :, k] = base + corners[a][:, None]
-    ivert = ivert.reshape(4, 3, ncell * 6)
-    elem = (ivert[:, 0] + n * (ivert[:, 1] + n * ivert[:, 2])).astype(np.int32)
-    bd = np.zeros((4, ncell * 6), dtype=np.int8)
+    # element order: cell-major, then the 6 permutations (element cell * 6 + k)
+    off = np.array(tets, dtype=np.int64)                          # (tet k, local vertex a, axis)
+
+    def coord(a, axis):
+        """Grid coordinate along `axis` of local vertex a of every element."""
+        return (base[axis][:, None] + off[None, :, a, axis]).ravel()
+
+    elem = np.empty((4, ncell * 6), dtype=np.int32)
     for a in range(4):
-        others = [b for b in range(4) if b != a]
-        fv = ivert[others]                                   # (3 vertices, 3 axes, NT)
-        for axis in range(3):
-            for side, val in ((0, 0), (1, n - 1)):
-                on = np.all(fv[:, axis, :] == val, axis=0)
-                code = faces[2 * axis + side]
+        elem[a] = coord(a, 0) + n * (coord(a, 1) + n * coord(a, 2))
+    bd = np.zeros((4, ncell * 6), dtype=np.int8)
+    for axis in range(3):
+        for side, val in ((0, 0), (1, n - 1)):
+            onv = [coord(b, axis) == val for b in range(4)]
+            code = faces[2 * axis + side]
+            for a in range(4):
+                others = [b for b in range(4) if b != a]
+                on = onv[others[0]] & onv[others[1]] & onv[others[2]]
                 bd[a, on] = code
     node = coords
     if permute:
