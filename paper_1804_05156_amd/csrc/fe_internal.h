@@ -26,7 +26,7 @@ enum : int32_t {
 };
 
 // Slots of the device status array.
-enum { ST_ERR = 0, ST_UNUSED = 1, ST_MAXROW = 2, ST_MAXDEG = 3, ST_NDIR = 4, ST_COUNT = 16 };
+enum { ST_ERR = 0, ST_UNUSED = 1, ST_MAXROW = 2, ST_MAXDEG = 3, ST_NDIR = 4, ST_RUNS = 5, ST_COUNT = 16 };
 
 // Fixed per-row capacity (stored columns, the vertex itself included) of the row
 // kernels, and their block sizes.
@@ -119,6 +119,7 @@ struct fe_plan {
     int64_t nnz, nused, ndir;
     int32_t max_row, max_deg;
     int rows_reg;         // the row passes use the register column set
+    int l1_agg;           // the level-1 kernels aggregate LDS counter updates per wavefront
     int pattern_done;
 };
 
@@ -200,6 +201,46 @@ template <int BLOCK> FE_DEV double block_sum(double v, double *lds)
         for (int w = 0; w < BLOCK / 64; ++w) s += lds[w];
     __syncthreads();
     return s;   // valid in thread 0
+}
+
+// LDS counter increments aggregated over a wavefront: lanes with equal keys in a
+// run of consecutive active lanes make one atomicAdd(cnt + key, run length) (issued
+// by the run's first lane), so a key shared by many lanes costs one atomic instead
+// of one per lane.  When fewer than 16 lanes repeat their neighbour's key (scattered
+// keys: aggregation would save little) every lane adds its own 1; *aggregated tells
+// which way was taken (the same in every lane).  Returns, for an active lane, a
+// distinct rank within its key: the counter's old value plus the lane's place in
+// its run (as a per-lane atomicAdd(cnt + key, 1) would, in another order).  Every
+// lane of the wavefront must call it, inactive ones with active = false (their
+// result is meaningless).
+FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *aggregated)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t act = __ballot(active);
+    const int32_t kprev = __shfl_up(key, 1, 64);
+    const bool cont = active && lane > 0 && ((act >> (lane - 1)) & 1ull) && kprev == key;
+    const uint64_t conts = __ballot(cont);
+    *aggregated = __popcll((long long)conts) >= 16;
+    if (!*aggregated) return active ? atomicAdd(cnt + key, 1) : 0;   // wavefront-uniform branch
+    const uint64_t heads = act & ~conts;
+    const bool head = active && !cont;
+    const uint64_t stops = heads | ~act;                        // lanes that do not continue a run
+    const uint64_t after = lane == 63 ? 0ull : stops >> (lane + 1);
+    const int32_t len = after ? __ffsll((long long)after) : 64 - lane;
+    int32_t base = 0;
+    if (head) base = atomicAdd(cnt + key, len);
+    const uint64_t upto = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+    const int hl = upto ? 63 - __clzll((long long)upto) : lane;  // this lane's run head
+    return __shfl(base, hl, 64) + (lane - hl);
+}
+
+// Per-lane LDS counter increment (AGG false) or the wavefront-aggregated one above
+// (AGG true; then every lane of the wavefront must call it).
+template <bool AGG> FE_DEV int32_t lds_rank_add(int32_t *cnt, int32_t key, bool active)
+{
+    if (!AGG) return active ? atomicAdd(cnt + key, 1) : 0;
+    bool agg;
+    return wave_rank_add(cnt, key, active, &agg);
 }
 
 // Exclusive scan of one int per thread over a block of BLOCK threads (BLOCK a

@@ -19,6 +19,7 @@
 // row kernels stay within a small window.  The matrix pattern is first built in
 // that order; a label-order pass then gathers whole rows into the output layout
 // with coalesced stores.
+#include <algorithm>
 #include <climits>
 #include <cstdlib>
 #include <cstring>
@@ -89,21 +90,31 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
     const int32_t t0 = ch * L1CH;
     const int32_t t1 = min(NT, t0 + L1CH);
     int32_t err = 0;
-    for (int32_t t = t0 + threadIdx.x; t < t1; t += L1B) {
+    int32_t runs = 0;   // wavefront calls that found runs of equal buckets (lane 0 counts)
+    // every lane runs every trip (the counts are aggregated across the wavefront)
+    for (int32_t tb = t0; tb < t1; tb += L1B) {
+        const int32_t t = tb + threadIdx.x;
         int32_t v[NV];
         int8_t code[NV];
-        const int32_t e = check_element<NV>(elem, bd, NT, N, t, v, code);
-        if (e) {
+        bool ok = t < t1;
+        if (ok) {
+            const int32_t e = check_element<NV>(elem, bd, NT, N, t, v, code);
             err |= e;
-            continue;
+            ok = !e;
         }
-        for (int a = 0; a < NV; ++a) atomicAdd(h + (v[a] >> (bs + FINE_SHIFT)), 1);
-        for (int f = 0; f < NV; ++f)
-            if (code[f] == FE_BD_DIRICHLET)
-                for (int q = 0; q < NV; ++q)
-                    if (q != f) isd[v[q]] = 1;
+        for (int a = 0; a < NV; ++a) {
+            bool agg;
+            wave_rank_add(h, ok ? v[a] >> (bs + FINE_SHIFT) : 0, ok, &agg);
+            runs += agg ? 1 : 0;
+        }
+        if (ok)
+            for (int f = 0; f < NV; ++f)
+                if (code[f] == FE_BD_DIRICHLET)
+                    for (int q = 0; q < NV; ++q)
+                        if (q != f) isd[v[q]] = 1;
     }
     if (err) atomicOr(status + ST_ERR, err);
+    if ((threadIdx.x & 63) == 0 && runs) atomicAdd(status + ST_RUNS, runs);
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += L1B) hist1[(int64_t)b * nblk1 + ch] = h[b];
 }
@@ -114,7 +125,7 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
 // store consecutive pairs of one bucket (a per-pair scattered store would cost one
 // memory request per pair).  The order inside a bucket is arbitrary (LDS atomics);
 // level 2 sorts it.  LDS: 2 * nb ints (dynamic), nb = number of coarse buckets.
-template <int NV>
+template <int NV, bool AGG>
 __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ elem, int32_t NT, int32_t bs,
                                                     int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
                                                     int2 *pairs)
@@ -140,12 +151,11 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int32_t t = s0 + e * L1B + tid;
-            if (t < t1)
 #pragma unroll
-                for (int a = 0; a < NV; ++a) {
-                    v[e][a] = elem[(int64_t)a * NT + t];
-                    rk[e][a] = atomicAdd(cnt + (v[e][a] >> sh), 1);
-                }
+            for (int a = 0; a < NV; ++a) {
+                v[e][a] = t < t1 ? elem[(int64_t)a * NT + t] : 0;
+                rk[e][a] = lds_rank_add<AGG>(cnt, v[e][a] >> sh, t < t1);
+            }
         }
         __syncthreads();
         const int32_t c = tid < nb ? cnt[tid] : 0;   // this thread's bucket count
@@ -177,6 +187,7 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
 
 // Level 1c: one block per coarse bucket splits it into its FINE buckets: counts
 // (LDS), bucket starts (fstart), then a scatter whose runs are long again.
+template <bool AGG>
 __global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t ncb, const int32_t *__restrict__ offs,
                                                 int32_t nblk1, int64_t ninc, const int2 *__restrict__ pairs,
                                                 int2 *pairs2, int32_t *fstart)
@@ -189,7 +200,10 @@ __global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t 
     if (threadIdx.x < FINE) cnt[threadIdx.x] = 0;
     __syncthreads();
     const int32_t fbase = cb * FINE;
-    for (int32_t j = s + threadIdx.x; j < e; j += FB) atomicAdd(cnt + ((pairs[j].x >> bs) - fbase), 1);
+    for (int32_t jb = s; jb < e; jb += FB) {   // uniform trips: the counts are wavefront-aggregated
+        const int32_t j = jb + threadIdx.x;
+        lds_rank_add<AGG>(cnt, j < e ? (pairs[j].x >> bs) - fbase : 0, j < e);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int32_t run = s;
@@ -201,9 +215,11 @@ __global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t 
         if (cb == ncb - 1) fstart[nb] = (int32_t)ninc;
     }
     __syncthreads();
-    for (int32_t j = s + threadIdx.x; j < e; j += FB) {
-        const int2 pr = pairs[j];
-        pairs2[atomicAdd(cur + ((pr.x >> bs) - fbase), 1)] = pr;
+    for (int32_t jb = s; jb < e; jb += FB) {
+        const int32_t j = jb + threadIdx.x;
+        const int2 pr = j < e ? pairs[j] : make_int2(fbase << bs, 0);
+        const int32_t pos = lds_rank_add<AGG>(cur, (pr.x >> bs) - fbase, j < e);
+        if (j < e) pairs2[pos] = pr;
     }
 }
 
@@ -865,20 +881,43 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     if ((rc = fe_launch_check())) return rc;
     // Vertex indices are validated by the histogram kernel only: stop here, before
     // any kernel uses elem entries as addresses, if one was out of range.
-    int32_t err = 0;
-    FE_HIP_CHECK(hipMemcpyAsync(&err, P->status + ST_ERR, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t st0[ST_RUNS + 1];
+    FE_HIP_CHECK(hipMemcpyAsync(st0, P->status, sizeof(st0), hipMemcpyDeviceToHost, s));
     FE_HIP_CHECK(hipStreamSynchronize(s));
-    if (err) return fe_status_from_bits(err);
+    if (st0[ST_ERR]) return fe_status_from_bits(st0[ST_ERR]);
     if (NT > 0) {
+        // Labels that follow the element order put runs of equal buckets in
+        // neighbouring lanes; then the level-1 kernels aggregate their LDS counter
+        // updates per wavefront.  The histogram kernel counted its wavefront calls
+        // that found such runs.
+        int64_t calls = 0;
+        for (int64_t ch = 0; ch < P->nblk1; ++ch) {
+            const int64_t len = std::min<int64_t>(L1CH, (int64_t)NT - ch * L1CH);
+            calls += cdiv(len, L1B) * NV * (L1B / 64);
+        }
+        P->l1_agg = 2 * (int64_t)st0[ST_RUNS] > calls;
         if ((rc = fe_scan_exclusive(P->hist1, P->hist1, nh, P->totals + 4, P->part, P->status, s))) return rc;
-        FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_l1_scatter<NV>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
-        FE_TIMED("k_l1_scatter", s,
-                 hipLaunchKernelGGL(k_l1_scatter<NV>, dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s, P->elem, NT,
-                                    P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
-        FE_TIMED("k_l1_fine", s,
-                 hipLaunchKernelGGL(k_l1_fine, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
-                               (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs, P->pairs2, P->fstart));
+        if (P->l1_agg) {
+            FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_l1_scatter<NV, true>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
+            FE_TIMED("k_l1_scatter", s,
+                     hipLaunchKernelGGL((k_l1_scatter<NV, true>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
+                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
+            FE_TIMED("k_l1_fine", s,
+                     hipLaunchKernelGGL(k_l1_fine<true>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
+                                        (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
+                                        P->pairs2, P->fstart));
+        } else {
+            FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_l1_scatter<NV, false>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
+            FE_TIMED("k_l1_scatter", s,
+                     hipLaunchKernelGGL((k_l1_scatter<NV, false>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
+                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
+            FE_TIMED("k_l1_fine", s,
+                     hipLaunchKernelGGL(k_l1_fine<false>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
+                                        (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
+                                        P->pairs2, P->fstart));
+        }
         // LDS capacity per bucket: twice the average bucket, at least 2048 keys
         int64_t cap = cdiv(2 * P->ninc, P->nb);
         cap = cdiv(cap, 1024) * 1024;
@@ -1078,6 +1117,7 @@ extern "C" int fe_plan_get_info(const fe_plan *plan, fe_plan_info *info)
     info->max_row = plan->max_row;
     info->max_deg = plan->max_deg;
     info->n_dirichlet = plan->ndir;
+    info->sort_runs = plan->l1_agg;
     return FE_OK;
 }
 

@@ -64,6 +64,52 @@ def test_parity_2d_jittered_permuted(seed, n):
     log(f"  worst scaled value error {worst:.2e}")
 
 
+@pytest.mark.parametrize("dim,n", [(2, 1025), (3, 65)])
+def test_both_sort_paths(dim, n):
+    """The incidence sort aggregates its LDS counter updates per wavefront when labels
+    follow the element order (runs of equal buckets in neighbouring lanes) and
+    updates per lane when they are scattered over many buckets; the plan reports
+    which it took.  The same mesh with coherent labels and with a random relabelling
+    takes one path each, and the two matrices and right-hand sides are the same bits
+    up to the relabelling (rows sum in ascending element order either way).  Oracle
+    parity of each path is covered at full size (2049^2 permuted: per lane; 129^3:
+    aggregated)."""
+    from paper_1804_05156_amd import femhip
+    log(f"case: both sort paths, dim {dim}, n {n}")
+    if dim == 2:
+        m = meshgen.square_mesh(n, jitter=0.2, seed=61, kappa="lognormal", sides=(1, 2, 1, 2))
+        specs = [(FE_FN_SINPROD, (TWO_PI2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7)), (FE_FN_CONST, (0.9,))]
+    else:
+        m = meshgen.kuhn_cube(n, jitter=0.15, seed=62, kappa="lognormal")
+        specs = [(FE_FN_SINPROD, (3 * math.pi ** 2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7, 0.4)),
+                 (FE_FN_DUDN_SINPROD, (1.0,))]
+    perm = np.random.default_rng(63).permutation(m.n_node)          # old label -> new label
+    node_p = np.empty_like(m.node)
+    node_p[:, perm] = m.node
+    elem_p = np.ascontiguousarray(perm[m.elem].astype(np.int32))
+    (f, _), (gd, _), (gn, _) = fns(*specs)
+    outs = []
+    for node, elem in ((m.node, m.elem), (node_p, elem_p)):
+        nd = torch.from_numpy(np.ascontiguousarray(node)).cuda()
+        plan = femhip.Plan(nd, torch.from_numpy(elem).cuda(), torch.from_numpy(m.bdflag).cuda())
+        asm = plan.assemble(torch.from_numpy(m.kappa).cuda(), f, gd, gn)
+        plan.check()
+        outs.append((plan.info["sort_runs"], host(plan, asm)))
+    assert [o[0] for o in outs] == [1, 0]
+    g, gp = outs[0][1], outs[1][1]
+    rows = np.repeat(np.arange(m.n_node), np.diff(g["rowptr"]))
+    rows_p = np.repeat(np.arange(m.n_node), np.diff(gp["rowptr"]))
+    key = perm[rows].astype(np.int64) * m.n_node + perm[g["colind"]]
+    key_p = rows_p.astype(np.int64) * m.n_node + gp["colind"]
+    o, op = np.argsort(key), np.argsort(key_p)
+    assert np.array_equal(key[o], key_p[op])
+    for name in ("val", "val_bc"):
+        assert np.array_equal(g[name][o], gp[name][op]), name
+    for name in ("b", "b_load", "is_d"):
+        assert np.array_equal(g[name], gp[name][perm]), name
+    log(f"  nnz {key.size}: paths {[o[0] for o in outs]}, identical up to relabelling")
+
+
 @pytest.mark.parametrize("seed,n", [(1, 3), (2, 4), (3, 6), (4, 9)])
 def test_parity_3d_jittered_permuted(seed, n):
     log(f"case: 3d kuhn jitter permute seed={seed} n={n}")
