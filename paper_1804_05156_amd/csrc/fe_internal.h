@@ -206,22 +206,22 @@ template <int BLOCK> FE_DEV double block_sum(double v, double *lds)
 // LDS counter increments aggregated over a wavefront: lanes with equal keys in a
 // run of consecutive active lanes make one atomicAdd(cnt + key, run length) (issued
 // by the run's first lane), so a key shared by many lanes costs one atomic instead
-// of one per lane.  When fewer than 16 lanes repeat their neighbour's key (scattered
-// keys: aggregation would save little) every lane adds its own 1; *aggregated tells
-// which way was taken (the same in every lane).  Returns, for an active lane, a
+// of one per lane.  When no lane repeats its neighbour's key every lane adds its own
+// 1.  *runs is set (the same in every lane) when at least 16 lanes continue a run:
+// the statistic by which the plan picks the aggregated kernels.  Returns, for an active lane, a
 // distinct rank within its key: the counter's old value plus the lane's place in
 // its run (as a per-lane atomicAdd(cnt + key, 1) would, in another order).  Every
 // lane of the wavefront must call it, inactive ones with active = false (their
 // result is meaningless).
-FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *aggregated)
+FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *runs)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t act = __ballot(active);
     const int32_t kprev = __shfl_up(key, 1, 64);
     const bool cont = active && lane > 0 && ((act >> (lane - 1)) & 1ull) && kprev == key;
     const uint64_t conts = __ballot(cont);
-    *aggregated = __popcll((long long)conts) >= 16;
-    if (!*aggregated) return active ? atomicAdd(cnt + key, 1) : 0;   // wavefront-uniform branch
+    *runs = __popcll((long long)conts) >= 16;
+    if (conts == 0) return active ? atomicAdd(cnt + key, 1) : 0;   // wavefront-uniform branch
     const uint64_t heads = act & ~conts;
     const bool head = active && !cont;
     const uint64_t stops = heads | ~act;                        // lanes that do not continue a run
@@ -239,8 +239,8 @@ FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *aggre
 template <bool AGG> FE_DEV int32_t lds_rank_add(int32_t *cnt, int32_t key, bool active)
 {
     if (!AGG) return active ? atomicAdd(cnt + key, 1) : 0;
-    bool agg;
-    return wave_rank_add(cnt, key, active, &agg);
+    bool runs;
+    return wave_rank_add(cnt, key, active, &runs);
 }
 
 // Exclusive scan of one int per thread over a block of BLOCK threads (BLOCK a

@@ -84,13 +84,15 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
                                                  int32_t *hist1, uint8_t *isd, int32_t *status)
 {
     extern __shared__ int32_t h[];
+    __shared__ int32_t block_runs;
     for (int b = threadIdx.x; b < nb; b += L1B) h[b] = 0;
+    if (threadIdx.x == 0) block_runs = 0;
     __syncthreads();
     const int32_t ch = l1_chunk(blockIdx.x, nblk1);
     const int32_t t0 = ch * L1CH;
     const int32_t t1 = min(NT, t0 + L1CH);
     int32_t err = 0;
-    int32_t runs = 0;   // wavefront calls that found runs of equal buckets (lane 0 counts)
+    int32_t runs = 0;   // wavefront calls with 16 or more lanes in runs of equal buckets (lane 0 counts)
     // every lane runs every trip (the counts are aggregated across the wavefront)
     for (int32_t tb = t0; tb < t1; tb += L1B) {
         const int32_t t = tb + threadIdx.x;
@@ -103,9 +105,9 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
             ok = !e;
         }
         for (int a = 0; a < NV; ++a) {
-            bool agg;
-            wave_rank_add(h, ok ? v[a] >> (bs + FINE_SHIFT) : 0, ok, &agg);
-            runs += agg ? 1 : 0;
+            bool r;
+            wave_rank_add(h, ok ? v[a] >> (bs + FINE_SHIFT) : 0, ok, &r);
+            runs += r ? 1 : 0;
         }
         if (ok)
             for (int f = 0; f < NV; ++f)
@@ -114,8 +116,9 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
                         if (q != f) isd[v[q]] = 1;
     }
     if (err) atomicOr(status + ST_ERR, err);
-    if ((threadIdx.x & 63) == 0 && runs) atomicAdd(status + ST_RUNS, runs);
+    if ((threadIdx.x & 63) == 0 && runs) atomicAdd(&block_runs, runs);
     __syncthreads();
+    if (threadIdx.x == 0 && block_runs) atomicAdd(status + ST_RUNS, block_runs);   // one per block
     for (int b = threadIdx.x; b < nb; b += L1B) hist1[(int64_t)b * nblk1 + ch] = h[b];
 }
 
