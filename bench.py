@@ -524,7 +524,15 @@ def bench_adjoint(args):
     e1.synchronize()
     g_ms = e0.elapsed_time(e1) / 10
     NT = m.n_elem
+    # PCG iterations of the forward solve and its time per iteration
+    asm = plan.assemble(kap, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, iters, _ = plan.solve(asm, rtol=rtol)
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
     return {"workload": "1025^2 jittered mesh, lognormal kappa, u_obs from a second kappa, rtol 1e-10",
+            "forward_pcg_iterations": int(iters), "us_per_pcg_iteration": t_s / max(int(iters), 1) * 1e6,
             "ms_forward": t_f * 1e3, "ms_forward_adjoint_grad": t_fb * 1e3, "ratio": t_fb / t_f,
             "ms_grad_kernel": g_ms, "grad_elements_per_s": NT / (g_ms * 1e-3),
             "fd_equivalent_ms": 2 * NT * t_f * 1e3}
