@@ -401,7 +401,7 @@ struct RowArgs {
     const int8_t *bd;
     const int32_t *pi, *pincptr, *inclp, *sorted_l;
     const uint8_t *isdp;
-    int32_t *pinc;        // count: written; final: read
+    int32_t *pinc;        // count: written; final: read (unless LBL)
     int32_t *prowptr;     // count: row lengths; final: row starts
     int32_t *elemp;       // count: written; final: read
     int32_t *colindp;     // final
@@ -492,16 +492,18 @@ constexpr int REGB = 256;    // threads per block of the register form
 // Per row (one thread, processing order): the sorted set of columns {i} u
 // {vertices of the incident elements}.  Incidences go in batches of RUNR whose
 // loads are issued together.
-//   FINAL = false: copy the row's sorted incidence keys into processing order,
-//                  record the row's position in each incident element (elemp) and
-//                  write the row length (processing order).
+//   FINAL = false: copy the row's sorted incidence keys into processing order
+//                  (unless LBL), record the row's position in each incident
+//                  element (elemp) and write the row length (processing order).
 //   FINAL = true:  write the row's columns and the per-incidence (key, metadata)
 //                  words in processing order and the row record; Dirichlet flags
 //                  of the columns are read in processing order through elemp, which
 //                  keeps those reads local.
 // REG selects the register set (capacity REGCAP): a row that does not fit sets
-// ERR_RETRY and the host reruns the pass with the LDS set.
-template <int NV, bool FINAL, bool REG>
+// ERR_RETRY and the host reruns the pass with the LDS set.  LBL: both passes read
+// the label-order lists (sorted_l) instead of a processing-order copy; the plan
+// picks it when labels follow the element order, where those reads are local.
+template <int NV, bool FINAL, bool REG, bool LBL>
 __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
 {
     constexpr int B = REG ? REGB : RowCaps<NV>::BLOCK, COLCAP = RowCaps<NV>::COL;
@@ -523,8 +525,9 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         }
         return;
     }
-    const int32_t src = FINAL ? s : R.inclp[k];
-    const int32_t *klist = FINAL ? R.pinc : R.sorted_l;
+    const bool from_pinc = FINAL && !LBL;
+    const int32_t src = from_pinc ? s : R.inclp[k];
+    const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
     set.init(cols, tid, i);
     bool ok = true;
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 const int32_t t = key[q] / NV;
                 const int a = key[q] - t * NV;
                 if (!FINAL) {
-                    R.pinc[s + j0 + q] = key[q];
+                    if (!LBL) R.pinc[s + j0 + q] = key[q];
                     R.elemp[(int64_t)t * 4 + a] = k;
                 }
 #pragma unroll
@@ -581,7 +584,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         int8_t code[RUNR][NV - 1];
 #pragma unroll
         for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d) key[q] = R.pinc[s + j0 + q];
+            if (j0 + q < d) key[q] = klist[src + j0 + q];
 #pragma unroll
         for (int q = 0; q < RUNR; ++q)
             if (j0 + q < d) {
@@ -865,6 +868,27 @@ RowArgs row_args(fe_plan *P)
     return R;
 }
 
+// Launch a row pass.  Labels that follow the element order (the sort found runs)
+// make the label-order lists local in processing order: both passes read them
+// directly (LBL).  Scattered labels make them random reads, and the count pass
+// copies them into processing order for the final pass.
+template <int NV, bool FINAL> void launch_rows(const fe_plan *P, const RowArgs &R, hipStream_t s)
+{
+    const int32_t N = (int32_t)P->N;
+    const char *name = FINAL ? "k_rows_final" : "k_rows_count";
+    const dim3 greg((unsigned)cdiv(N, REGB)), glds((unsigned)cdiv(N, RowCaps<NV>::BLOCK));
+    if (P->rows_reg && P->l1_agg)
+        FE_TIMED(name, s, hipLaunchKernelGGL((k_rows<NV, FINAL, true, true>), greg, dim3(REGB), 0, s, R));
+    else if (P->rows_reg)
+        FE_TIMED(name, s, hipLaunchKernelGGL((k_rows<NV, FINAL, true, false>), greg, dim3(REGB), 0, s, R));
+    else if (P->l1_agg)
+        FE_TIMED(name, s,
+                 hipLaunchKernelGGL((k_rows<NV, FINAL, false, true>), glds, dim3(RowCaps<NV>::BLOCK), 0, s, R));
+    else
+        FE_TIMED(name, s,
+                 hipLaunchKernelGGL((k_rows<NV, FINAL, false, false>), glds, dim3(RowCaps<NV>::BLOCK), 0, s, R));
+}
+
 template <int NV> int plan_build(fe_plan *P, hipStream_t s)
 {
     const int32_t N = (int32_t)P->N, NT = (int32_t)P->NT;
@@ -957,14 +981,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     // run again with the LDS set (both give the same sets)
     P->rows_reg = 1;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        if (P->rows_reg)
-            FE_TIMED("k_rows_count", s,
-                     hipLaunchKernelGGL((k_rows<NV, false, true>), dim3((unsigned)cdiv(N, REGB)), dim3(REGB), 0, s,
-                                        R));
-        else
-            FE_TIMED("k_rows_count", s,
-                     hipLaunchKernelGGL((k_rows<NV, false, false>), dim3((unsigned)cdiv(N, RowCaps<NV>::BLOCK)),
-                                        dim3(RowCaps<NV>::BLOCK), 0, s, R));
+        launch_rows<NV, false>(P, R, s);
         if ((rc = fe_launch_check())) return rc;
         if ((rc = fe_scan_exclusive(P->prowptr, P->prowptr, N, P->totals + 2, P->part, P->status, s))) return rc;
         const unsigned sb = (unsigned)(cdiv(N, STB) < 1024 ? cdiv(N, STB) : 1024);   // grid-stride beyond
@@ -1003,13 +1020,7 @@ template <int NV> int plan_pattern(fe_plan *P, int32_t *rowptr, int32_t *colind,
 {
     const int32_t N = (int32_t)P->N;
     const RowArgs R = row_args(P);
-    if (P->rows_reg)
-        FE_TIMED("k_rows_final", s,
-                 hipLaunchKernelGGL((k_rows<NV, true, true>), dim3((unsigned)cdiv(N, REGB)), dim3(REGB), 0, s, R));
-    else
-        FE_TIMED("k_rows_final", s,
-                 hipLaunchKernelGGL((k_rows<NV, true, false>), dim3((unsigned)cdiv(N, RowCaps<NV>::BLOCK)),
-                                    dim3(RowCaps<NV>::BLOCK), 0, s, R));
+    launch_rows<NV, true>(P, R, s);
     FE_TIMED("k_label_rows", s,
              hipLaunchKernelGGL(k_label_rows, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, (const int32_t *)P->piinv,
                            (const int4 *)P->precp, P->rowrec, P->rowlen));
