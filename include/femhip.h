@@ -94,9 +94,10 @@ typedef struct fe_plan_info {
     int32_t max_row;        /* longest row of A */
     int32_t max_deg;        /* most elements around one vertex */
     int64_t n_dirichlet;    /* Dirichlet nodes */
-    int32_t sort_runs;      /* 1 if the incidence sort found runs of equal buckets in neighbouring
-                               elements and aggregated its counter updates per wavefront, else 0
-                               (a choice of kernels; results do not depend on it) */
+    int32_t sort_runs;      /* 1 if the labels follow the element order (the incidence sort found
+                               runs of equal buckets in neighbouring elements): the sort aggregates
+                               its counter updates per wavefront and rows are processed in label
+                               order; else 0 (a choice of kernels; results do not depend on it) */
 } fe_plan_info;
 
 /* Library version string (host, static). */

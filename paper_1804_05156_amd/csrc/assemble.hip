@@ -39,6 +39,12 @@ struct AsmArgs {
     int32_t load_rule;     // FE_LOAD_*: quadrature of the load integrals
     double *valp;          // rows in processing order: row k at prowptr[k] + 2k, its values
                            // followed by (b, b_load)
+    // direct: the processing order is the label order, and the rows go straight to
+    // the outputs (row k of A at prowptr[k])
+    int32_t direct;
+    const int4 *precp;     // row records (.z, .w: Dirichlet-column mask), for val_bc
+    double *val, *val_bc, *b, *b_load;
+    uint8_t *isd;
     int32_t *status;
 };
 
@@ -84,6 +90,29 @@ template <int BLOCK>
 FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, int len, bool rowd, double bsum,
                       double lift, double gdi)
 {
+    if (A.direct) {
+        // label order: A_bc replaces a Dirichlet row by the identity row and zeroes
+        // Dirichlet columns (the row record holds the row's Dirichlet-column mask)
+        const int64_t start = A.prowptr[k];
+        double *v = A.val + start;
+        for (int c = 0; c < len; ++c) v[c] = acc[c * BLOCK + tid];
+        if (A.val_bc) {
+            const int4 r = A.precp[k];
+            const int diag = (r.y >> 8) & 0xff;
+            const uint64_t dm = (uint64_t)(uint32_t)r.z | ((uint64_t)(uint32_t)r.w << 32);
+            double *vb = A.val_bc + start;
+            for (int c = 0; c < len; ++c) {
+                double x = acc[c * BLOCK + tid];
+                if (rowd) x = (c == diag) ? 1.0 : 0.0;
+                else if ((dm >> c) & 1ull) x = 0.0;
+                vb[c] = x;
+            }
+        }
+        A.b[k] = rowd ? gdi : bsum - lift;
+        if (A.b_load) A.b_load[k] = bsum;
+        if (A.isd) A.isd[k] = (uint8_t)rowd;
+        return;
+    }
     double *row = A.valp + A.prowptr[k] + 2 * (int64_t)k;
     for (int c = 0; c < len; ++c) row[c] = acc[c * BLOCK + tid];
     row[len] = rowd ? gdi : bsum - lift;
@@ -668,6 +697,13 @@ extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double 
     A.ralpha = robin_alpha;
     A.load_rule = load_rule;
     A.valp = plan->valp;
+    A.direct = plan->l1_agg;
+    A.precp = plan->precp;
+    A.val = val;
+    A.val_bc = val_bc;
+    A.b = b;
+    A.b_load = b_load;
+    A.isd = is_dirichlet;
     A.status = plan->status;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const unsigned gg = (unsigned)cdiv(A.N, 256);
@@ -687,6 +723,7 @@ extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double 
     else if (mr <= 32) rc = launch<32, 128>(plan->dim, A, s);
     else rc = launch<64, 64>(plan->dim, A, s);
     if (rc) return rc;
+    if (A.direct) return FE_OK;   // rows already in label order
     FE_TIMED("k_values_to_label", s,
              hipLaunchKernelGGL(k_values_to_label, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,
                            (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,

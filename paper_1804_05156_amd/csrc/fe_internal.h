@@ -116,10 +116,12 @@ struct fe_plan {
     int64_t nnz_max;      // capacity of valp
     int64_t *stat_part;   // per-block partial statistics
     // host copies
-    int64_t nnz, nused, ndir;
+    int64_t nnz, ndir;
     int32_t max_row, max_deg;
     int rows_reg;         // the row passes use the register column set
-    int l1_agg;           // the level-1 kernels aggregate LDS counter updates per wavefront
+    int l1_agg;           // labels follow the element order: the level-1 kernels aggregate LDS
+                          // counter updates per wavefront, the row passes read the label-order
+                          // lists, and rows are processed in label order (identity pi)
     int pattern_done;
 };
 

@@ -395,6 +395,28 @@ __global__ __launch_bounds__(EBLOCK) void k_unused(int32_t N, const int2 *__rest
     }
 }
 
+// Processing order = label order, for labels that follow the element order: the
+// identity permutation, and each vertex's incidence range and Dirichlet flag taken
+// straight from its label-order list (the lists are contiguous in label order, so
+// their starts are the exclusive prefix sums of the degrees).
+__global__ __launch_bounds__(EBLOCK) void k_ident(int32_t N, int64_t ninc, const int2 *__restrict__ vinfo,
+                                                  int32_t *pi, int32_t *piinv, int32_t *pincptr, int32_t *inclp,
+                                                  uint8_t *isdp)
+{
+    const int32_t v = blockIdx.x * EBLOCK + threadIdx.x;
+    if (v > N) return;
+    if (v == N) {
+        pincptr[N] = (int32_t)ninc;
+        return;
+    }
+    const int2 vi = vinfo[v];
+    pi[v] = v;
+    piinv[v] = v;
+    pincptr[v] = vi.x;
+    inclp[v] = vi.x;
+    isdp[v] = (uint8_t)((vi.y >> 30) & 1);
+}
+
 struct RowArgs {
     int32_t NT, N;
     const int32_t *elem;
@@ -961,21 +983,33 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                  hipLaunchKernelGGL(k_l2_bucket_global, dim3((unsigned)P->nb), dim3(BKB), 0, s, N, P->bs, (int32_t)cap,
                                (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd,
                                P->sorted_l, P->vinfo, P->rowlen, P->prowptr, P->ownf));
-        FE_TIMED("k_own_count", s,
-                 hipLaunchKernelGGL(k_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, (const uint8_t *)P->ownf, P->owncnt));
+        if (!P->l1_agg)
+            FE_TIMED("k_own_count", s,
+                     hipLaunchKernelGGL(k_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, (const uint8_t *)P->ownf,
+                                        P->owncnt));
         if ((rc = fe_launch_check())) return rc;
     }
-    if ((rc = fe_scan_exclusive(P->owncnt, P->owncnt, NT, P->totals + 0, P->part, P->status, s))) return rc;
-    if (NT > 0)
-        FE_TIMED("k_pi", s,
-                 hipLaunchKernelGGL(k_pi<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, (const uint8_t *)P->ownf,
-                               (const int32_t *)P->owncnt, (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp,
-                               P->isdp));
-    FE_TIMED("k_unused", s,
-             hipLaunchKernelGGL(k_unused, dim3(ng), dim3(EBLOCK), 0, s, N, (const int2 *)P->vinfo,
-                           (const int64_t *)(P->totals + 0), P->pi, P->piinv, P->pincptr, P->inclp, P->isdp, P->status));
-    if ((rc = fe_launch_check())) return rc;
-    if ((rc = fe_scan_exclusive(P->pincptr, P->pincptr, N, P->totals + 1, P->part, P->status, s))) return rc;
+    if (P->l1_agg) {
+        // labels follow the element order: process rows in label order
+        FE_TIMED("k_ident", s,
+                 hipLaunchKernelGGL(k_ident, dim3((unsigned)cdiv(N + 1, EBLOCK)), dim3(EBLOCK), 0, s, N, P->ninc,
+                                    (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp, P->isdp));
+        if ((rc = fe_launch_check())) return rc;
+    } else {
+        // processing position = rank of the vertex's first incidence (element order)
+        if ((rc = fe_scan_exclusive(P->owncnt, P->owncnt, NT, P->totals + 0, P->part, P->status, s))) return rc;
+        if (NT > 0)
+            FE_TIMED("k_pi", s,
+                     hipLaunchKernelGGL(k_pi<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, (const uint8_t *)P->ownf,
+                                        (const int32_t *)P->owncnt, (const int2 *)P->vinfo, P->pi, P->piinv,
+                                        P->pincptr, P->inclp, P->isdp));
+        FE_TIMED("k_unused", s,
+                 hipLaunchKernelGGL(k_unused, dim3(ng), dim3(EBLOCK), 0, s, N, (const int2 *)P->vinfo,
+                                    (const int64_t *)(P->totals + 0), P->pi, P->piinv, P->pincptr, P->inclp, P->isdp,
+                                    P->status));
+        if ((rc = fe_launch_check())) return rc;
+        if ((rc = fe_scan_exclusive(P->pincptr, P->pincptr, N, P->totals + 1, P->part, P->status, s))) return rc;
+    }
     const RowArgs R = row_args(P);
     // the row pass with the register column set; rows too long for it make the pass
     // run again with the LDS set (both give the same sets)
@@ -1004,12 +1038,11 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
             continue;
         }
         if (st[ST_ERR]) return fe_status_from_bits(st[ST_ERR]);
-        P->nused = tot[0];
         P->nnz = tot[2];
         P->max_row = st[ST_MAXROW];
         P->max_deg = st[ST_MAXDEG];
         P->ndir = st[ST_NDIR];
-        if (tot[1] != P->ninc) return FE_EHIP;   // every incidence must be placed
+        if (!P->l1_agg && tot[1] != P->ninc) return FE_EHIP;   // every incidence must be placed
         if (P->nnz > P->nnz_max) return FE_EHIP;
         return FE_OK;
     }
@@ -1019,7 +1052,17 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
 template <int NV> int plan_pattern(fe_plan *P, int32_t *rowptr, int32_t *colind, hipStream_t s)
 {
     const int32_t N = (int32_t)P->N;
-    const RowArgs R = row_args(P);
+    RowArgs R = row_args(P);
+    if (P->l1_agg) {
+        // processing order = label order: the final pass writes the caller's column
+        // indices, and the row pointer is the processing-order one
+        R.colindp = colind;
+        launch_rows<NV, true>(P, R, s);
+        int rc;
+        if ((rc = fe_launch_check())) return rc;
+        FE_HIP_CHECK(hipMemcpyAsync(rowptr, P->prowptr, sizeof(int32_t) * (size_t)(N + 1), hipMemcpyDeviceToDevice, s));
+        return FE_OK;
+    }
     launch_rows<NV, true>(P, R, s);
     FE_TIMED("k_label_rows", s,
              hipLaunchKernelGGL(k_label_rows, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, (const int32_t *)P->piinv,
