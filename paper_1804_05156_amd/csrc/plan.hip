@@ -417,6 +417,20 @@ __global__ __launch_bounds__(EBLOCK) void k_ident(int32_t N, int64_t ninc, const
     isdp[v] = (uint8_t)((vi.y >> 30) & 1);
 }
 
+// Element vertex records for label-order processing: with the identity order the
+// processing positions of an element's vertices are its labels, so elemp is the
+// element array transposed to one int4 per element (coalesced on both sides).
+template <int NV>
+__global__ __launch_bounds__(EBLOCK) void k_elemp_labels(int32_t NT, const int32_t *__restrict__ elem, int4 *elemp)
+{
+    const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
+    if (t >= NT) return;
+    elemp[t] = make_int4(elem[t], elem[(int64_t)NT + t], elem[2 * (int64_t)NT + t],
+                         NV == 4 ? elem[3 * (int64_t)NT + t] : 0);
+}
+
+FE_DEV int32_t sel_i4(const int4 &q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
+
 struct RowArgs {
     int32_t NT, N;
     const int32_t *elem;
@@ -522,9 +536,12 @@ constexpr int REGB = 256;    // threads per block of the register form
 //                  of the columns are read in processing order through elemp, which
 //                  keeps those reads local.
 // REG selects the register set (capacity REGCAP): a row that does not fit sets
-// ERR_RETRY and the host reruns the pass with the LDS set.  LBL: both passes read
-// the label-order lists (sorted_l) instead of a processing-order copy; the plan
-// picks it when labels follow the element order, where those reads are local.
+// ERR_RETRY and the host reruns the pass with the LDS set.  LBL: label-order
+// processing (labels that follow the element order): both passes read the label-
+// order lists (sorted_l), which are then local, instead of a processing-order copy,
+// and take an element's vertices from its elemp record (labels, one 16-byte load)
+// instead of the element array (one load per vertex); the count pass then writes
+// no elemp (k_elemp_labels did).
 template <int NV, bool FINAL, bool REG, bool LBL>
 __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
 {
@@ -564,12 +581,19 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             if (j0 + q < d) {
                 const int32_t t = key[q] / NV;
                 const int a = key[q] - t * NV;
-                if (!FINAL) {
-                    if (!LBL) R.pinc[s + j0 + q] = key[q];
+                if (!FINAL && !LBL) {
+                    R.pinc[s + j0 + q] = key[q];
                     R.elemp[(int64_t)t * 4 + a] = k;
                 }
+                if (LBL) {
+                    const int4 e4 = reinterpret_cast<const int4 *>(R.elemp)[t];
 #pragma unroll
-                for (int jj = 0; jj < NV - 1; ++jj) c[q][jj] = R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
+                    for (int jj = 0; jj < NV - 1; ++jj) c[q][jj] = sel_i4(e4, fe_other<NV>(a, jj));
+                } else {
+#pragma unroll
+                    for (int jj = 0; jj < NV - 1; ++jj)
+                        c[q][jj] = R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
+                }
             }
 #pragma unroll
         for (int q = 0; q < RUNR; ++q)
@@ -616,7 +640,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
 #pragma unroll
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
-                    c[q][jj] = R.elem[(int64_t)b * R.NT + t];
+                    if (!LBL) c[q][jj] = R.elem[(int64_t)b * R.NT + t];   // LBL: from ep[q] below
                     code[q][jj] = R.bd ? R.bd[(int64_t)b * R.NT + t] : 0;
                 }
             }
@@ -627,7 +651,8 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
 #pragma unroll
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
-                    const int32_t pb = b == 0 ? ep[q].x : (b == 1 ? ep[q].y : (b == 2 ? ep[q].z : ep[q].w));
+                    const int32_t pb = sel_i4(ep[q], b);
+                    if (LBL) c[q][jj] = pb;   // processing position = label
                     dz[q][jj] = R.isdp[pb];
                 }
             }
@@ -994,6 +1019,9 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         FE_TIMED("k_ident", s,
                  hipLaunchKernelGGL(k_ident, dim3((unsigned)cdiv(N + 1, EBLOCK)), dim3(EBLOCK), 0, s, N, P->ninc,
                                     (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp, P->isdp));
+        FE_TIMED("k_elemp_labels", s,
+                 hipLaunchKernelGGL(k_elemp_labels<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, P->elem,
+                                    reinterpret_cast<int4 *>(P->elemp)));
         if ((rc = fe_launch_check())) return rc;
     } else {
         // processing position = rank of the vertex's first incidence (element order)
