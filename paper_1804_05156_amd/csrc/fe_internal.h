@@ -88,7 +88,9 @@ struct fe_plan {
     uint8_t *isd;         // N      Dirichlet flag (label order)
     uint8_t *isdp;        // N      Dirichlet flag (processing order)
     int4 *precp;          // N      row record (processing order), see rowrec
-    uint8_t *ownf;        // ninc   1 if incidence t*nv+a is the first one of its vertex
+    uint8_t *ownf;        // ninc   1 if incidence t*nv+a is the first one of its vertex; in
+                          //        label-order processing reused as uint16 per element
+                          //        (packed side codes and vertex Dirichlet flags)
     int32_t *hist1;       // nb*nblk1+1  level-1 bucket histogram (bucket-major) -> offsets
     int2 *pairs;          // ninc   (vertex, key) grouped by coarse bucket (shares memory with pincm)
     int2 *pairs2;         // ninc   (vertex, key) grouped by bucket

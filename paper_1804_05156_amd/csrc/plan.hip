@@ -417,16 +417,29 @@ __global__ __launch_bounds__(EBLOCK) void k_ident(int32_t N, int64_t ninc, const
     isdp[v] = (uint8_t)((vi.y >> 30) & 1);
 }
 
-// Element vertex records for label-order processing: with the identity order the
+// Element records for label-order processing.  With the identity order the
 // processing positions of an element's vertices are its labels, so elemp is the
 // element array transposed to one int4 per element (coalesced on both sides).
+// einfo packs the element's side codes (2 bits per side a, bits 2a..2a+1) and the
+// Dirichlet flags of its vertices (bit 8 + a), which the final row pass would
+// otherwise gather byte by byte.
 template <int NV>
-__global__ __launch_bounds__(EBLOCK) void k_elemp_labels(int32_t NT, const int32_t *__restrict__ elem, int4 *elemp)
+__global__ __launch_bounds__(EBLOCK) void k_elemp_labels(int32_t NT, const int32_t *__restrict__ elem,
+                                                         const int8_t *__restrict__ bd, const uint8_t *__restrict__ isd,
+                                                         int4 *elemp, uint16_t *einfo)
 {
     const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
     if (t >= NT) return;
-    elemp[t] = make_int4(elem[t], elem[(int64_t)NT + t], elem[2 * (int64_t)NT + t],
-                         NV == 4 ? elem[3 * (int64_t)NT + t] : 0);
+    int32_t v[4] = {0, 0, 0, 0};
+    uint32_t w = 0;
+    for (int a = 0; a < NV; ++a) {
+        v[a] = elem[(int64_t)a * NT + t];
+        const uint32_t code = bd ? (uint32_t)bd[(int64_t)a * NT + t] : 0u;
+        w |= (code & 3u) << (2 * a);
+        w |= (uint32_t)(isd[v[a]] & 1u) << (8 + a);
+    }
+    elemp[t] = make_int4(v[0], v[1], v[2], v[3]);
+    einfo[t] = (uint16_t)w;
 }
 
 FE_DEV int32_t sel_i4(const int4 &q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
@@ -438,6 +451,7 @@ struct RowArgs {
     const int32_t *pi, *pincptr, *inclp, *sorted_l;
     const uint8_t *isdp;
     int32_t *pinc;        // count: written; final: read (unless LBL)
+    const uint16_t *einfo; // LBL: packed side codes and vertex Dirichlet flags per element
     int32_t *prowptr;     // count: row lengths; final: row starts
     int32_t *elemp;       // count: written; final: read
     int32_t *colindp;     // final
@@ -628,6 +642,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         int32_t c[RUNR][NV - 1];
         uint8_t dz[RUNR][NV - 1];
         int8_t code[RUNR][NV - 1];
+        uint32_t ei[RUNR];
 #pragma unroll
         for (int q = 0; q < RUNR; ++q)
             if (j0 + q < d) key[q] = klist[src + j0 + q];
@@ -637,11 +652,14 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 const int32_t t = key[q] / NV;
                 const int a = key[q] - t * NV;
                 ep[q] = ep4[t];
+                if (LBL) ei[q] = R.einfo[t];
 #pragma unroll
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
-                    if (!LBL) c[q][jj] = R.elem[(int64_t)b * R.NT + t];   // LBL: from ep[q] below
-                    code[q][jj] = R.bd ? R.bd[(int64_t)b * R.NT + t] : 0;
+                    if (!LBL) {   // LBL: vertices from ep[q], codes from ei[q] below
+                        c[q][jj] = R.elem[(int64_t)b * R.NT + t];
+                        code[q][jj] = R.bd ? R.bd[(int64_t)b * R.NT + t] : 0;
+                    }
                 }
             }
 #pragma unroll
@@ -652,8 +670,13 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
                     const int32_t pb = sel_i4(ep[q], b);
-                    if (LBL) c[q][jj] = pb;   // processing position = label
-                    dz[q][jj] = R.isdp[pb];
+                    if (LBL) {   // processing position = label; packed codes and flags
+                        c[q][jj] = pb;
+                        code[q][jj] = (int8_t)((ei[q] >> (2 * b)) & 3u);
+                        dz[q][jj] = (uint8_t)((ei[q] >> (8 + b)) & 1u);
+                    } else {
+                        dz[q][jj] = R.isdp[pb];
+                    }
                 }
             }
 #pragma unroll
@@ -905,6 +928,7 @@ RowArgs row_args(fe_plan *P)
     R.sorted_l = P->sorted_l;
     R.isdp = P->isdp;
     R.pinc = P->pinc;
+    R.einfo = reinterpret_cast<const uint16_t *>(P->ownf);
     R.prowptr = P->prowptr;
     R.elemp = P->elemp;
     R.colindp = reinterpret_cast<int32_t *>(P->valp);
@@ -1020,8 +1044,9 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                  hipLaunchKernelGGL(k_ident, dim3((unsigned)cdiv(N + 1, EBLOCK)), dim3(EBLOCK), 0, s, N, P->ninc,
                                     (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp, P->isdp));
         FE_TIMED("k_elemp_labels", s,
-                 hipLaunchKernelGGL(k_elemp_labels<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, P->elem,
-                                    reinterpret_cast<int4 *>(P->elemp)));
+                 hipLaunchKernelGGL(k_elemp_labels<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, P->elem, P->bdflag,
+                                    (const uint8_t *)P->isd, reinterpret_cast<int4 *>(P->elemp),
+                                    reinterpret_cast<uint16_t *>(P->ownf)));   // ownf is free in this order
         if ((rc = fe_launch_check())) return rc;
     } else {
         // processing position = rank of the vertex's first incidence (element order)
