@@ -62,11 +62,12 @@ __global__ __launch_bounds__(256) void k_scatter_coords(int32_t N, const int32_t
     if (DIM == 2) {
         reinterpret_cast<double2 *>(xyp)[k] = make_double2(node[i], node[(int64_t)N + i]);
     } else {
+        // (x, y), (z, nodal f): the coordinate loads of the 3-D kernel bring f along
         double2 *o = reinterpret_cast<double2 *>(xyp) + 2 * (int64_t)k;
         o[0] = make_double2(node[i], node[(int64_t)N + i]);
-        o[1] = make_double2(node[2 * (int64_t)N + i], 0.0);
+        o[1] = make_double2(node[2 * (int64_t)N + i], fnodal ? fnodal[i] : 0.0);
     }
-    if (fnodal) fp[k] = fnodal[i];
+    if (DIM == 2 && fnodal) fp[k] = fnodal[i];
 }
 
 template <int DIM> FE_DEV void load_label_xy(const double *node, int32_t N, int32_t v, double *x)
@@ -423,17 +424,17 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
     const double2 *xy = reinterpret_cast<const double2 *>(A.xyp);
     const int4 *ep4 = reinterpret_cast<const int4 *>(A.elemp);
-    double Y0[3];
+    double Y0[3], fi;   // fi: nodal f at the row's vertex (the fourth word of its record)
     {
         const double2 q0 = xy[2 * (int64_t)k], q1 = xy[2 * (int64_t)k + 1];
         Y0[0] = q0.x; Y0[1] = q0.y; Y0[2] = q1.x;
+        fi = q1.y;
     }
     double bsum = 0.0, lift = 0.0;
     int32_t err = 0;
     const double alpha = 0.58541019662496845446;   // (5 + 3 sqrt 5) / 20
     const double beta = 0.13819660112501051518;    // (5 - sqrt 5) / 20
     const bool nodal_f = A.f.kind == FE_FN_NODAL;
-    const double fi = nodal_f ? A.fp[k] : 0.0;
     double fvert = 0.0;   // f at the row's vertex (vertex rule)
     if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) fvert = nodal_f ? fi : fn_point<3>(A.f, Y0);
     const uint32_t BND = (7u << Meta<4>::NBIT) | (7u << Meta<4>::RBIT) |
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
         int4 ep[UNR];
         double kt[UNR];
         int pq[UNR][3];
-        double Y[UNR][3][3];
+        double Y[UNR][3][3], F[UNR][3];   // F: nodal f at the other vertices
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
             if (p0 + u < e) km[u] = A.pincm[p0 + u];
@@ -464,6 +465,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                     pq[u][q] = sel4(ep[u], fe_other<4>(a, q));
                     const double2 c0 = xy[2 * (int64_t)pq[u][q]], c1 = xy[2 * (int64_t)pq[u][q] + 1];
                     Y[u][q][0] = c0.x; Y[u][q][1] = c0.y; Y[u][q][2] = c1.x;
+                    F[u][q] = c1.y;
                 }
             }
 #pragma unroll
@@ -504,7 +506,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
             if (A.load_rule == FE_LOAD_CENTROID && A.f.kind != FE_FN_ZERO) {
                 double fc;
                 if (nodal_f) {
-                    fc = (fi + A.fp[pq[u][0]] + A.fp[pq[u][1]] + A.fp[pq[u][2]]) / 4.0;
+                    fc = (fi + F[u][0] + F[u][1] + F[u][2]) / 4.0;
                 } else {
                     double c[3];
                     for (int q = 0; q < 3; ++q) c[q] = (Y0[q] + Y1[q] + Y2[q] + Y3[q]) / 4.0;
@@ -514,7 +516,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
             } else if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) {
                 bsum += vol * fvert / 4.0;
             } else if (nodal_f) {
-                const double sf = fi + A.fp[pq[u][0]] + A.fp[pq[u][1]] + A.fp[pq[u][2]];
+                const double sf = fi + F[u][0] + F[u][1] + F[u][2];
                 bsum += vol * (fi + sf) / 20.0;
             } else if (A.f.kind != FE_FN_ZERO) {
                 double S[3];
