@@ -227,6 +227,21 @@ def main():
     traffic = None
     if counters and dom in counters:
         traffic = counters[dom][0] + counters[dom][1]
+    # counter-measured bandwidth (FETCH_SIZE + WRITE_SIZE per dispatch, copy-calibrated:
+    # bytes between the L2s and the fabric, MALL hits included) over the kernel times
+    # of this run, for the numeric phase and for the whole cold step
+    rocprof = None
+    if counters and all(n in counters for n in kernels):
+        def rate(names):
+            by = sum((counters[n][0] + counters[n][1]) * kernels[n]["launches_per_step"] for n in names)
+            us = sum(kernels[n]["us_per_step"] for n in names)
+            return by / (us * 1e-6) / 1e9
+        numeric = [n for n in kernels if n in ("k_scatter_coords", "k_assemble_2d", "k_assemble_3d",
+                                               "k_values_to_label")]
+        rocprof = {"numeric_phase_GBps": rate(numeric), "cold_step_GBps": rate(list(kernels)),
+                   "peak_GBps": HBM_PEAK_GBS}
+        rocprof["numeric_phase_frac"] = rocprof["numeric_phase_GBps"] / HBM_PEAK_GBS
+        rocprof["cold_step_frac"] = rocprof["cold_step_GBps"] / HBM_PEAK_GBS
 
     # warm numeric phase: plan reused, a different kappa each call
     log("[bench] timing warm numeric phase")
@@ -280,6 +295,7 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
                      "avg_us": dom_us},
+        "rocprof_bandwidth": rocprof,
         "c3": c3,
         "batched": batched,
         "next": nxt,
