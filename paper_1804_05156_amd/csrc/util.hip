@@ -4,8 +4,13 @@
 namespace {
 
 constexpr int SCAN_BLOCK = 256;
-constexpr int SCAN_ITEMS = 4;                       // one int4 per thread
-constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;  // 1024 elements per block
+constexpr int SCAN_CHUNKS = 4;                        // one int4 per thread per chunk
+constexpr int SCAN_CHUNK = SCAN_BLOCK * 4;            // 1024 elements
+constexpr int SCAN_TILE = SCAN_CHUNKS * SCAN_CHUNK;   // 4096 elements per block
+// Up to this many tiles the apply kernel sums its predecessors' partials itself
+// (at most 32 KB of L2-resident reads per block); beyond it a one-block kernel
+// scans the partials first.
+constexpr int64_t SCAN_DIRECT_TILES = 4096;
 
 // Inclusive scan across the 64 lanes of a wavefront.
 FE_DEV int64_t wave_inclusive(int64_t x)
@@ -38,32 +43,49 @@ template <int BLOCK = SCAN_BLOCK> FE_DEV int64_t block_exclusive(int64_t v, int6
     return pre + inc - v;
 }
 
-FE_DEV void load_items(const int32_t *in, int64_t n, int64_t base, int32_t v[SCAN_ITEMS])
+// A tile is SCAN_CHUNKS chunks of 1024 elements; in each chunk thread t holds
+// elements 4t..4t+3, so every int4 load and store of a wavefront is contiguous.
+FE_DEV void load_tile(const int32_t *in, int64_t n, int64_t tile0, int4 q[SCAN_CHUNKS])
 {
-    if (base + SCAN_ITEMS <= n) {
-        int4 q = *reinterpret_cast<const int4 *>(in + base);
-        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-    } else {
-        for (int k = 0; k < SCAN_ITEMS; ++k) v[k] = (base + k < n) ? in[base + k] : 0;
+    for (int c = 0; c < SCAN_CHUNKS; ++c) {
+        const int64_t base = tile0 + (int64_t)c * SCAN_CHUNK + 4 * (int64_t)threadIdx.x;
+        if (base + 4 <= n) {
+            q[c] = *reinterpret_cast<const int4 *>(in + base);
+        } else {
+            q[c].x = (base + 0 < n) ? in[base + 0] : 0;
+            q[c].y = (base + 1 < n) ? in[base + 1] : 0;
+            q[c].z = (base + 2 < n) ? in[base + 2] : 0;
+            q[c].w = (base + 3 < n) ? in[base + 3] : 0;
+        }
     }
 }
+
+FE_DEV int64_t sum4(int4 q) { return (int64_t)q.x + q.y + q.z + q.w; }
 
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *in, int64_t n, int64_t *part)
 {
     __shared__ int64_t lds[2 * (SCAN_BLOCK / 64)];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int32_t v[SCAN_ITEMS];
-    load_items(in, n, base, v);
+    int4 q[SCAN_CHUNKS];
+    load_tile(in, n, (int64_t)blockIdx.x * SCAN_TILE, q);
     int64_t s = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
+    for (int c = 0; c < SCAN_CHUNKS; ++c) s += sum4(q[c]);
     int64_t tot;
     block_exclusive(s, lds, &tot);
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// One block: exclusive scan of part[0..nb), total to part[nb] and *total_dev.  Each
-// thread owns a contiguous run of partials: a serial sum, one block scan of the run
-// sums, then a serial pass writing the run's offsets.
+// The scan's total: to *total_dev and out[n], with the int32 overflow check.
+FE_DEV void scan_total(int64_t carry, int64_t *total_dev, int32_t *out, int64_t n, int32_t *status)
+{
+    *total_dev = carry;
+    if (carry > INT32_MAX) atomicOr(status + ST_ERR, ERR_OVERFLOW);
+    out[n] = (int32_t)carry;
+}
+
+// One block: exclusive scan of part[0..nb) in place (for more than
+// SCAN_DIRECT_TILES tiles).  Each thread owns a contiguous run of partials: a
+// serial sum, one block scan of the run sums, then a serial pass writing the
+// run's offsets.
 constexpr int SP_BLOCK = 1024;
 
 __global__ __launch_bounds__(SP_BLOCK) void k_scan_partials(int64_t *part, int64_t nb, int64_t *total_dev,
@@ -82,48 +104,71 @@ __global__ __launch_bounds__(SP_BLOCK) void k_scan_partials(int64_t *part, int64
         part[k] = ex;
         ex += v;
     }
-    if (threadIdx.x == 0) {
-        part[nb] = carry;
-        *total_dev = carry;
-        if (carry > INT32_MAX) atomicOr(status + ST_ERR, ERR_OVERFLOW);
-        out[n] = (int32_t)carry;
-    }
+    if (threadIdx.x == 0) scan_total(carry, total_dev, out, n, status);
 }
 
+// DIRECT: part[] holds the tile sums and block b adds part[0..b) itself; the
+// last block also writes the total.  Otherwise part[] already holds the tiles'
+// exclusive offsets.
+template <bool DIRECT>
 __global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int32_t *in, int32_t *out, int64_t n,
-                                                           const int64_t *part)
+                                                           const int64_t *part, int64_t *total_dev, int32_t *status)
 {
     __shared__ int64_t lds[2 * (SCAN_BLOCK / 64)];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    int32_t v[SCAN_ITEMS];
-    load_items(in, n, base, v);
-    int64_t s = 0;
-    for (int k = 0; k < SCAN_ITEMS; ++k) s += v[k];
-    int64_t tot;
-    int64_t ex = block_exclusive(s, lds, &tot) + part[blockIdx.x];
-    int32_t o[SCAN_ITEMS];
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        o[k] = (int32_t)ex;
-        ex += v[k];
-    }
-    if (base + SCAN_ITEMS <= n) {
-        *reinterpret_cast<int4 *>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+    const int64_t tile0 = (int64_t)blockIdx.x * SCAN_TILE;
+    int4 q[SCAN_CHUNKS];
+    load_tile(in, n, tile0, q);
+    int64_t carry;
+    if (DIRECT) {
+        int64_t s = 0;
+        for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += SCAN_BLOCK) s += part[j];
+        block_exclusive(s, lds, &carry);
     } else {
-        for (int k = 0; k < SCAN_ITEMS; ++k)
-            if (base + k < n) out[base + k] = o[k];
+        carry = part[blockIdx.x];
     }
+    for (int c = 0; c < SCAN_CHUNKS; ++c) {
+        const int64_t s = sum4(q[c]);
+        int64_t tot;
+        int64_t ex = carry + block_exclusive(s, lds, &tot);
+        carry += tot;
+        int32_t o[4];
+        o[0] = (int32_t)ex; ex += q[c].x;
+        o[1] = (int32_t)ex; ex += q[c].y;
+        o[2] = (int32_t)ex; ex += q[c].z;
+        o[3] = (int32_t)ex;
+        const int64_t base = tile0 + (int64_t)c * SCAN_CHUNK + 4 * (int64_t)threadIdx.x;
+        if (base + 4 <= n) {
+            *reinterpret_cast<int4 *>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+        } else {
+            for (int k = 0; k < 4; ++k)
+                if (base + k < n) out[base + k] = o[k];
+        }
+    }
+    if (DIRECT && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) scan_total(carry, total_dev, out, n, status);
 }
 
+// p[0..n) = v: 16-byte stores over the aligned middle, element stores at the ends.
 template <typename T> __global__ void k_fill(T *p, int64_t n, T v)
 {
+    constexpr int PER = 16 / sizeof(T);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t head = (int64_t)((16 - ((uintptr_t)p & 15)) & 15) / (int64_t)sizeof(T);
+    if ((uintptr_t)p % sizeof(T)) head = n;     // misaligned element type: element stores only
+    if (head > n) head = n;
+    const int64_t nv = (n - head) / PER;
+    for (int64_t i = tid; i < head; i += stride) p[i] = v;
+    for (int64_t k = (n - head) % PER, i = tid; i < k; i += stride) p[head + nv * PER + i] = v;
+    union { T e[PER]; uint4 q; } u;
+    for (int k = 0; k < PER; ++k) u.e[k] = v;
+    uint4 *pv = reinterpret_cast<uint4 *>(p + head);
+    for (int64_t i = tid; i < nv; i += stride) pv[i] = u.q;
 }
 
 template <typename T> int fill(T *p, int64_t n, T v, hipStream_t s)
 {
     if (n <= 0) return FE_OK;
-    int64_t blocks = cdiv(n, 256);
+    int64_t blocks = cdiv(cdiv(n, 16 / (int64_t)sizeof(T)), 256);
     if (blocks > 8192) blocks = 8192;
     FE_TIMED("k_fill", s,
              hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v));
@@ -161,10 +206,18 @@ int fe_scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int64_t *total
     const int64_t nb = cdiv(n > 0 ? n : 1, SCAN_TILE);
     FE_TIMED("k_scan_reduce", s,
              hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part));
-    FE_TIMED("k_scan_partials", s,
-             hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SP_BLOCK), 0, s, part, nb, total_dev, out, n, status));
-    FE_TIMED("k_scan_apply", s,
-             hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part));
+    if (nb <= SCAN_DIRECT_TILES) {
+        FE_TIMED("k_scan_apply", s,
+                 hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part,
+                                    total_dev, status));
+    } else {
+        FE_TIMED("k_scan_partials", s,
+                 hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SP_BLOCK), 0, s, part, nb, total_dev, out, n,
+                                    status));
+        FE_TIMED("k_scan_apply", s,
+                 hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part,
+                                    total_dev, status));
+    }
     return fe_launch_check();
 }
 
