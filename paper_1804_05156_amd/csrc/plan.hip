@@ -122,16 +122,39 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
     for (int b = threadIdx.x; b < nb; b += L1B) hist1[(int64_t)b * nblk1 + ch] = h[b];
 }
 
+// Element record for label-order processing.  With the identity order the
+// processing positions of an element's vertices are its labels, so elemp is the
+// element array transposed to one int4 per element.  einfo packs the element's
+// side codes (2 bits per side a, bits 2a..2a+1) and the Dirichlet flags of its
+// vertices (bit 8 + a), which the final row pass would otherwise gather byte by
+// byte.  The level-1 scatter writes both while it reads the element array.
+template <int NV>
+FE_DEV void elem_record(int32_t t, const int32_t *v, int32_t NT, const int8_t *__restrict__ bd,
+                        const uint8_t *__restrict__ isd, int4 *elemp, uint16_t *einfo)
+{
+    uint32_t w = 0;
+#pragma unroll
+    for (int a = 0; a < NV; ++a) {
+        const uint32_t code = bd ? (uint32_t)bd[(int64_t)a * NT + t] : 0u;
+        w |= (code & 3u) << (2 * a);
+        w |= (uint32_t)(isd[v[a]] & 1u) << (8 + a);
+    }
+    elemp[t] = make_int4(v[0], v[1], v[2], NV == 4 ? v[NV - 1] : 0);
+    einfo[t] = (uint16_t)w;
+}
+
 // Level 1b: scatter (vertex, key) pairs into their coarse bucket's range.  The
 // chunk is taken L1SUB elements at a time: the sub-chunk's pairs are first grouped
 // by bucket in LDS (a counting sort), then stored run by run, so consecutive lanes
 // store consecutive pairs of one bucket (a per-pair scattered store would cost one
 // memory request per pair).  The order inside a bucket is arbitrary (LDS atomics);
 // level 2 sorts it.  LDS: 2 * nb ints (dynamic), nb = number of coarse buckets.
+// AGG (labels that follow the element order) also writes the element records.
 template <int NV, bool AGG>
 __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ elem, int32_t NT, int32_t bs,
                                                     int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
-                                                    int2 *pairs)
+                                                    int2 *pairs, const int8_t *__restrict__ bd,
+                                                    const uint8_t *__restrict__ isd, int4 *elemp, uint16_t *einfo)
 {
     extern __shared__ int32_t dyn[];
     __shared__ int2 buf[L1SUB * NV];
@@ -159,6 +182,7 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
                 v[e][a] = t < t1 ? elem[(int64_t)a * NT + t] : 0;
                 rk[e][a] = lds_rank_add<AGG>(cnt, v[e][a] >> sh, t < t1);
             }
+            if (AGG && t < t1) elem_record<NV>(t, v[e], NT, bd, isd, elemp, einfo);
         }
         __syncthreads();
         const int32_t c = tid < nb ? cnt[tid] : 0;   // this thread's bucket count
@@ -292,7 +316,7 @@ __global__ __launch_bounds__(BKB) void k_l2_bucket(int32_t N, int32_t bs, int32_
         if (c == 0) continue;
         const int32_t lo = cur[q] - c;   // the cursor ended at the list's end
         isort(keys, lo, c);
-        ownf[keys[lo]] = 1;
+        if (ownf) ownf[keys[lo]] = 1;
     }
     __syncthreads();
     for (int32_t j = threadIdx.x; j < n; j += BKB) sorted_l[s + j] = keys[j];
@@ -339,7 +363,7 @@ __global__ __launch_bounds__(BKB) void k_l2_bucket_global(int32_t N, int32_t bs,
         if (c == 0) continue;
         const int32_t lo = cursor[v] - c;
         isort(sorted_l, lo, c);
-        ownf[sorted_l[lo]] = 1;
+        if (ownf) ownf[sorted_l[lo]] = 1;
     }
 }
 
@@ -415,31 +439,6 @@ __global__ __launch_bounds__(EBLOCK) void k_ident(int32_t N, int64_t ninc, const
     pincptr[v] = vi.x;
     inclp[v] = vi.x;
     isdp[v] = (uint8_t)((vi.y >> 30) & 1);
-}
-
-// Element records for label-order processing.  With the identity order the
-// processing positions of an element's vertices are its labels, so elemp is the
-// element array transposed to one int4 per element (coalesced on both sides).
-// einfo packs the element's side codes (2 bits per side a, bits 2a..2a+1) and the
-// Dirichlet flags of its vertices (bit 8 + a), which the final row pass would
-// otherwise gather byte by byte.
-template <int NV>
-__global__ __launch_bounds__(EBLOCK) void k_elemp_labels(int32_t NT, const int32_t *__restrict__ elem,
-                                                         const int8_t *__restrict__ bd, const uint8_t *__restrict__ isd,
-                                                         int4 *elemp, uint16_t *einfo)
-{
-    const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
-    if (t >= NT) return;
-    int32_t v[4] = {0, 0, 0, 0};
-    uint32_t w = 0;
-    for (int a = 0; a < NV; ++a) {
-        v[a] = elem[(int64_t)a * NT + t];
-        const uint32_t code = bd ? (uint32_t)bd[(int64_t)a * NT + t] : 0u;
-        w |= (code & 3u) << (2 * a);
-        w |= (uint32_t)(isd[v[a]] & 1u) << (8 + a);
-    }
-    elemp[t] = make_int4(v[0], v[1], v[2], v[3]);
-    einfo[t] = (uint16_t)w;
 }
 
 FE_DEV int32_t sel_i4(const int4 &q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
@@ -555,7 +554,7 @@ constexpr int REGB = 256;    // threads per block of the register form
 // order lists (sorted_l), which are then local, instead of a processing-order copy,
 // and take an element's vertices from its elemp record (labels, one 16-byte load)
 // instead of the element array (one load per vertex); the count pass then writes
-// no elemp (k_elemp_labels did).
+// no elemp (the level-1 scatter did).
 template <int NV, bool FINAL, bool REG, bool LBL>
 __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArgs R)
 {
@@ -970,7 +969,6 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     int rc;
     if ((rc = fe_fill_i32(P->status, ST_COUNT, 0, s))) return rc;
     if ((rc = fe_fill_u8(P->isd, N, 0, s))) return rc;
-    if ((rc = fe_fill_u8(P->ownf, P->ninc, 0, s))) return rc;
     // (vinfo needs no clearing: the bucket kernels write it for every vertex)
     if (NT > 0)
         FE_TIMED("k_l1_hist", s,
@@ -1000,7 +998,9 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, true>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
-                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
+                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
+                                        P->bdflag, (const uint8_t *)P->isd, reinterpret_cast<int4 *>(P->elemp),
+                                        reinterpret_cast<uint16_t *>(P->ownf)));   // einfo: ownf is free in this order
             FE_TIMED("k_l1_fine", s,
                      hipLaunchKernelGGL(k_l1_fine<true>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
                                         (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
@@ -1010,12 +1010,16 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, false>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
-                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs));
+                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
+                                        nullptr, nullptr, nullptr, nullptr));
             FE_TIMED("k_l1_fine", s,
                      hipLaunchKernelGGL(k_l1_fine<false>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
                                         (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
                                         P->pairs2, P->fstart));
         }
+        // first-incidence flags, for the processing order of the general path
+        uint8_t *ownf = P->l1_agg ? nullptr : P->ownf;
+        if (ownf && (rc = fe_fill_u8(ownf, P->ninc, 0, s))) return rc;
         // LDS capacity per bucket: twice the average bucket, at least 2048 keys
         int64_t cap = cdiv(2 * P->ninc, P->nb);
         cap = cdiv(cap, 1024) * 1024;
@@ -1027,11 +1031,11 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         FE_TIMED("k_l2_bucket", s,
                  hipLaunchKernelGGL(k_l2_bucket, dim3((unsigned)P->nb), dim3(BKB), lds, s, N, P->bs, (int32_t)cap,
                                (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd, P->sorted_l,
-                               P->vinfo, P->ownf));
+                               P->vinfo, ownf));
         FE_TIMED("k_l2_bucket_global", s,
                  hipLaunchKernelGGL(k_l2_bucket_global, dim3((unsigned)P->nb), dim3(BKB), 0, s, N, P->bs, (int32_t)cap,
                                (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd,
-                               P->sorted_l, P->vinfo, P->rowlen, P->prowptr, P->ownf));
+                               P->sorted_l, P->vinfo, P->rowlen, P->prowptr, ownf));
         if (!P->l1_agg)
             FE_TIMED("k_own_count", s,
                      hipLaunchKernelGGL(k_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, (const uint8_t *)P->ownf,
@@ -1043,10 +1047,6 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         FE_TIMED("k_ident", s,
                  hipLaunchKernelGGL(k_ident, dim3((unsigned)cdiv(N + 1, EBLOCK)), dim3(EBLOCK), 0, s, N, P->ninc,
                                     (const int2 *)P->vinfo, P->pi, P->piinv, P->pincptr, P->inclp, P->isdp));
-        FE_TIMED("k_elemp_labels", s,
-                 hipLaunchKernelGGL(k_elemp_labels<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, P->elem, P->bdflag,
-                                    (const uint8_t *)P->isd, reinterpret_cast<int4 *>(P->elemp),
-                                    reinterpret_cast<uint16_t *>(P->ownf)));   // ownf is free in this order
         if ((rc = fe_launch_check())) return rc;
     } else {
         // processing position = rank of the vertex's first incidence (element order)
