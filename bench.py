@@ -243,6 +243,14 @@ def main():
         rocprof["numeric_phase_frac"] = rocprof["numeric_phase_GBps"] / HBM_PEAK_GBS
         rocprof["cold_step_frac"] = rocprof["cold_step_GBps"] / HBM_PEAK_GBS
 
+    # what a plain device copy reaches on this GPU (read + write bytes over its time)
+    log("[bench] timing a plain device copy")
+    copy = copy_rate(torch, dev, 512)
+    if rocprof:
+        rocprof["copy_GBps"] = copy["GBps"]
+        rocprof["numeric_phase_frac_of_copy"] = rocprof["numeric_phase_GBps"] / copy["GBps"]
+        rocprof["cold_step_frac_of_copy"] = rocprof["cold_step_GBps"] / copy["GBps"]
+
     # warm numeric phase: plan reused, a different kappa each call
     log("[bench] timing warm numeric phase")
     plan, _ = femhip.fe_plan_create(mesh, ws)
@@ -296,6 +304,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
                      "avg_us": dom_us},
         "rocprof_bandwidth": rocprof,
+        "copy_kernel": copy,
         "c3": c3,
         "batched": batched,
         "next": nxt,
@@ -552,6 +561,26 @@ def bench_adjoint(args):
             "ms_forward": t_f * 1e3, "ms_forward_adjoint_grad": t_fb * 1e3, "ratio": t_fb / t_f,
             "ms_grad_kernel": g_ms, "grad_elements_per_s": NT / (g_ms * 1e-3),
             "fd_equivalent_ms": 2 * NT * t_f * 1e3}
+
+
+def copy_rate(torch, dev, mb, launches=10):
+    """A plain device copy of mb MiB: read + write bytes per launch over its mean time."""
+    n = mb * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(launches):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / launches
+    del src, dst
+    return {"bytes_per_launch": 2 * n * 8, "avg_us": us, "GBps": 2 * n * 8 / (us * 1e-6) / 1e9,
+            "kind": f"torch copy_ of a {mb} MiB float64 tensor"}
 
 
 def copy_calibration(mb):
