@@ -167,6 +167,34 @@ def test_unused_vertex_single_elements():
             data=data_scale(m, specs))
 
 
+SCAN_TILE_EDGE = 4096 * 4096   # prefix sums: up to 4096 tiles of 4096 entries in two launches
+
+
+@pytest.mark.parametrize("extra,labels", [(0, "leading"), (1, "scattered")])
+def test_prefix_sum_tile_limit(extra, labels):
+    """A 129x129 jittered mesh whose vertices sit among N = 4096^2 (+1) labels, the
+    rest unused (empty rows): the per-vertex prefix sums run at the largest size of
+    the two-launch form and one past it (a one-block scan of the tile sums in
+    between).  Labels either lead (0.., element order: label-order processing) or
+    are scattered over the whole range (the general path, which scans three
+    per-vertex arrays).  f = 1, so the oracle's own term sums set the b scale."""
+    N = SCAN_TILE_EDGE + extra
+    log(f"case: prefix-sum tile limit, N = {N}, labels {labels}")
+    small = meshgen.square_mesh(129, jitter=0.2, permute=False, seed=91, kappa="lognormal")
+    rng = np.random.default_rng(92)
+    emb = np.arange(small.n_node) if labels == "leading" else rng.choice(N, small.n_node, replace=False)
+    node = np.zeros((2, N))
+    node[:, emb] = small.node
+    m = meshgen.Mesh(node, emb[small.elem].astype(np.int32), small.bdflag, small.kappa)
+    (f, fo), _, _ = fns((FE_FN_CONST, (1.0,)))
+    plan, asm = run_gpu(m, None, f)
+    assert plan.info["sort_runs"] == (labels == "leading")
+    g = host(plan, asm)
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo)
+    compare(g, ora)
+    assert g["rowptr"][-1] == ora.rowptr[-1] == plan.nnz
+
+
 def _fan(k):
     """k triangles around the origin (a vertex with k neighbours), outer ring Dirichlet."""
     ang = 2 * math.pi * np.arange(k) / k
