@@ -415,7 +415,9 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
 {
     __shared__ double acc[ROWCAP * BLOCK];
     const int tid = threadIdx.x;
-    const int32_t k = blockIdx.x * BLOCK + tid;
+    // contiguous rows per XCD: neighbours lie about N^(2/3) positions apart, a window
+    // that interleaved blocks would need in every XCD's L2
+    const int32_t k = xcd_block(blockIdx.x, gridDim.x) * BLOCK + tid;
     if (k >= A.N) return;
     const int32_t s = A.pincptr[k], e = A.pincptr[k + 1];
     const uint32_t info = A.prow_info[k];

@@ -240,6 +240,16 @@ FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *runs)
 
 // Per-lane LDS counter increment (AGG false) or the wavefront-aggregated one above
 // (AGG true; then every lane of the wavefront must call it).
+// Logical block of hardware block b in a grid of nblk.  Blocks are dealt to the 8
+// XCDs round-robin (b, b + 8, ... share one XCD and its L2); this bijection gives
+// every XCD a contiguous range of logical blocks, so blocks that run together on
+// one XCD work on neighbouring data.
+FE_DEV int32_t xcd_block(int32_t b, int32_t nblk)
+{
+    const int32_t q = nblk / 8, r = nblk % 8, x = b % 8;
+    return x * q + min(x, r) + b / 8;
+}
+
 template <bool AGG> FE_DEV int32_t lds_rank_add(int32_t *cnt, int32_t key, bool active)
 {
     if (!AGG) return active ? atomicAdd(cnt + key, 1) : 0;

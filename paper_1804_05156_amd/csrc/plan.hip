@@ -45,14 +45,9 @@ static_assert(NBMAX / FINE <= L1B, "one thread per coarse bucket in the level-1 
 static_assert(L1SUB % L1B == 0, "whole sub-chunks per thread");
 constexpr int RUNR = 4;         // incidences per batch in the row kernels
 
-// Level-1 chunk of block b.  Blocks are dealt to the 8 XCDs round-robin; this gives
-// every XCD a contiguous range of chunks, so the runs that neighbouring chunks
-// write into one bucket are written through the same L2.
-FE_DEV int32_t l1_chunk(int32_t b, int32_t nblk)
-{
-    const int32_t q = nblk / 8, r = nblk % 8, x = b % 8;
-    return x * q + min(x, r) + b / 8;
-}
+// Level-1 chunk of block b: contiguous chunk ranges per XCD, so the runs that
+// neighbouring chunks write into one bucket are written through the same L2.
+FE_DEV int32_t l1_chunk(int32_t b, int32_t nblk) { return xcd_block(b, nblk); }
 
 // Validate one element: vertex range, repeated vertices, side codes.
 template <int NV>
@@ -264,6 +259,43 @@ FE_DEV void isort(int32_t *keys, int32_t lo, int32_t n)
     }
 }
 
+// Sort keys[lo..lo+n) (n <= M) in registers: a bitonic network over M slots, the
+// unused ones padded with INT32_MAX.  Every index is a compile-time constant once
+// unrolled, so the array stays in registers; no chain of dependent LDS accesses
+// as in the insertion sort.  Keys are distinct, so the result is the same.
+template <int M> FE_DEV void net_sort(int32_t *keys, int32_t lo, int32_t n)
+{
+    int32_t a[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) a[m] = m < n ? keys[lo + m] : INT32_MAX;
+#pragma unroll
+    for (int k = 2; k <= M; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const int32_t x = a[i], y = a[l];
+                    const bool up = (i & k) == 0;
+                    a[i] = up ? min(x, y) : max(x, y);
+                    a[l] = up ? max(x, y) : min(x, y);
+                }
+            }
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+        if (m < n) keys[lo + m] = a[m];
+}
+
+// One vertex list in LDS: the register network up to 32 keys, else insertion.
+FE_DEV void sort_list(int32_t *keys, int32_t lo, int32_t n)
+{
+    if (n <= 8) net_sort<8>(keys, lo, n);
+    else if (n <= 16) net_sort<16>(keys, lo, n);
+    else if (n <= 32) net_sort<32>(keys, lo, n);
+    else isort(keys, lo, n);
+}
+
 
 
 // Level 2: one block per bucket.  Count incidences per vertex, place them, sort
@@ -315,7 +347,7 @@ __global__ __launch_bounds__(BKB) void k_l2_bucket(int32_t N, int32_t bs, int32_
         const int32_t c = cnt[q];
         if (c == 0) continue;
         const int32_t lo = cur[q] - c;   // the cursor ended at the list's end
-        isort(keys, lo, c);
+        sort_list(keys, lo, c);
         if (ownf) ownf[keys[lo]] = 1;
     }
     __syncthreads();
@@ -563,7 +595,9 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     using Set = typename std::conditional<REG, RegSet<REGCAP>, LdsSet<B, COLCAP>>::type;
     constexpr int SETCAP = REG ? REGCAP : COLCAP;
     const int tid = threadIdx.x;
-    const int32_t k = blockIdx.x * B + tid;
+    // 3-D: contiguous rows per XCD (neighbours lie about N^(2/3) positions apart, a
+    // window that interleaved blocks would need in every XCD's L2)
+    const int32_t k = (NV == 4 && !FINAL ? xcd_block(blockIdx.x, gridDim.x) : (int32_t)blockIdx.x) * B + tid;
     if (k >= R.N) return;
     const int32_t i = R.pi[k];
     const int32_t s = R.pincptr[k];
