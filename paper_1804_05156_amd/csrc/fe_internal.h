@@ -95,7 +95,9 @@ struct fe_plan {
     int2 *pairs;          // ninc   (vertex, key) grouped by coarse bucket (shares memory with pincm)
     int2 *pairs2;         // ninc   (vertex, key) grouped by bucket
     int32_t *fstart;      // nb+1   first incidence of each bucket in pairs2
-    int32_t ncb;          // coarse buckets (FINE buckets each)
+    int32_t ncb;          // coarse buckets (fine buckets each, the last maybe fewer)
+    int32_t fine;         // buckets per coarse bucket (1..32)
+    uint64_t cmul;        // ceil(2^32 / fine): coarse bucket = ((v >> bs) * cmul) >> 32
     int32_t *sorted_l;    // ninc   keys grouped by vertex label, ascending
     int32_t *owncnt;      // NT+1   vertices whose first incidence is in element t -> offsets
     int32_t *pi;          // N      processing order -> vertex label

@@ -37,17 +37,25 @@ constexpr int NBMAX = 16384;    // buckets held in LDS by the level-1 kernels
 constexpr int VBMAX = 4096;     // vertices per bucket (2^bs) at most
 constexpr int BKB = 256;        // threads of the bucket kernel
 constexpr int BCAPMAX = 24576;  // incidences per bucket sorted in LDS at most (larger: global path)
-constexpr int FINE_SHIFT = 5;
-constexpr int FINE = 1 << FINE_SHIFT;   // buckets per coarse bucket
+constexpr int FINE = 32;        // buckets per coarse bucket at most
+constexpr int L1SLOTS = 512;    // coarse-to-fine blocks resident at once (2 of FB threads per CU)
 constexpr int FB = 1024;        // threads of the coarse-to-fine kernel
 constexpr int L1SUB = 2048;     // elements per LDS-staged sub-chunk of the level-1 scatter
-static_assert(NBMAX / FINE <= L1B, "one thread per coarse bucket in the level-1 scatter");
+static_assert(NBMAX / FINE <= L1SLOTS && L1SLOTS <= L1B, "one thread per coarse bucket in the level-1 scatter");
 static_assert(L1SUB % L1B == 0, "whole sub-chunks per thread");
 constexpr int RUNR = 4;         // incidences per batch in the row kernels
 
 // Level-1 chunk of block b: contiguous chunk ranges per XCD, so the runs that
 // neighbouring chunks write into one bucket are written through the same L2.
 FE_DEV int32_t l1_chunk(int32_t b, int32_t nblk) { return xcd_block(b, nblk); }
+
+// Coarse bucket of vertex v: its bucket v >> bs divided by the buckets per coarse
+// bucket, as a multiply by cmul = ceil(2^32 / fine), exact for bucket numbers
+// below 2^22 and fine <= 32 (vertex labels are below 2^26, bs >= 4).
+FE_DEV int32_t coarse_of(int32_t v, int32_t bs, uint64_t cmul)
+{
+    return (int32_t)(((uint64_t)(uint32_t)(v >> bs) * cmul) >> 32);
+}
 
 // Validate one element: vertex range, repeated vertices, side codes.
 template <int NV>
@@ -71,12 +79,12 @@ FE_DEV int32_t check_element(const int32_t *__restrict__ elem, const int8_t *__r
 }
 
 // Level 1a: validation, Dirichlet marks, histogram of incidences per coarse bucket
-// (FINE buckets, 2^(bs+FINE_SHIFT) vertices).  hist1 is coarse-bucket-major:
+// (fine buckets of 2^bs vertices each).  hist1 is coarse-bucket-major:
 // hist1[cb * nblk1 + chunk].  LDS: nb ints (dynamic), nb = number of coarse buckets.
 template <int NV>
 __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ elem, const int8_t *__restrict__ bd,
-                                                 int32_t NT, int32_t N, int32_t bs, int32_t nb, int32_t nblk1,
-                                                 int32_t *hist1, uint8_t *isd, int32_t *status)
+                                                 int32_t NT, int32_t N, int32_t bs, uint64_t cmul, int32_t nb,
+                                                 int32_t nblk1, int32_t *hist1, uint8_t *isd, int32_t *status)
 {
     extern __shared__ int32_t h[];
     __shared__ int32_t block_runs;
@@ -101,7 +109,7 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
         }
         for (int a = 0; a < NV; ++a) {
             bool r;
-            wave_rank_add(h, ok ? v[a] >> (bs + FINE_SHIFT) : 0, ok, &r);
+            wave_rank_add(h, ok ? coarse_of(v[a], bs, cmul) : 0, ok, &r);
             runs += r ? 1 : 0;
         }
         if (ok)
@@ -147,7 +155,7 @@ FE_DEV void elem_record(int32_t t, const int32_t *v, int32_t NT, const int8_t *_
 // AGG (labels that follow the element order) also writes the element records.
 template <int NV, bool AGG>
 __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ elem, int32_t NT, int32_t bs,
-                                                    int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
+                                                    uint64_t cmul, int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
                                                     int2 *pairs, const int8_t *__restrict__ bd,
                                                     const uint8_t *__restrict__ isd, int4 *elemp, uint16_t *einfo)
 {
@@ -166,7 +174,6 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
     __syncthreads();
     const int32_t t0 = ch * L1CH;
     const int32_t t1 = min(NT, t0 + L1CH);
-    const int sh = bs + FINE_SHIFT;
     for (int32_t s0 = t0; s0 < t1; s0 += L1SUB) {
         int32_t v[PER][NV], rk[PER][NV];
 #pragma unroll
@@ -175,7 +182,7 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
 #pragma unroll
             for (int a = 0; a < NV; ++a) {
                 v[e][a] = t < t1 ? elem[(int64_t)a * NT + t] : 0;
-                rk[e][a] = lds_rank_add<AGG>(cnt, v[e][a] >> sh, t < t1);
+                rk[e][a] = lds_rank_add<AGG>(cnt, coarse_of(v[e][a], bs, cmul), t < t1);
             }
             if (AGG && t < t1) elem_record<NV>(t, v[e], NT, bd, isd, elemp, einfo);
         }
@@ -190,12 +197,13 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
             const int32_t t = s0 + e * L1B + tid;
             if (t < t1)
 #pragma unroll
-                for (int a = 0; a < NV; ++a) buf[cnt[v[e][a] >> sh] + rk[e][a]] = make_int2(v[e][a], t * NV + a);
+                for (int a = 0; a < NV; ++a)
+                    buf[cnt[coarse_of(v[e][a], bs, cmul)] + rk[e][a]] = make_int2(v[e][a], t * NV + a);
         }
         __syncthreads();
         for (int32_t j = tid; j < tot; j += L1B) {
             const int2 pr = buf[j];
-            const int32_t b = pr.x >> sh;
+            const int32_t b = coarse_of(pr.x, bs, cmul);
             pairs[cur[b] + (j - cnt[b])] = pr;
         }
         __syncthreads();
@@ -207,10 +215,12 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
     }
 }
 
-// Level 1c: one block per coarse bucket splits it into its FINE buckets: counts
-// (LDS), bucket starts (fstart), then a scatter whose runs are long again.
+// Level 1c: one block per coarse bucket splits it into its fine buckets: counts
+// (LDS), bucket starts (fstart), then a scatter whose runs are long again.  The
+// ratio fine is chosen so that all blocks are resident in one round.
 template <bool AGG>
-__global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t ncb, const int32_t *__restrict__ offs,
+__global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t fine, int32_t ncb,
+                                                const int32_t *__restrict__ offs,
                                                 int32_t nblk1, int64_t ninc, const int2 *__restrict__ pairs,
                                                 int2 *pairs2, int32_t *fstart)
 {
@@ -221,7 +231,7 @@ __global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t 
     const int32_t e = (cb + 1 < ncb) ? offs[(int64_t)(cb + 1) * nblk1] : (int32_t)ninc;
     if (threadIdx.x < FINE) cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int32_t fbase = cb * FINE;
+    const int32_t fbase = cb * fine;
     for (int32_t jb = s; jb < e; jb += FB) {   // uniform trips: the counts are wavefront-aggregated
         const int32_t j = jb + threadIdx.x;
         lds_rank_add<AGG>(cnt, j < e ? (pairs[j].x >> bs) - fbase : 0, j < e);
@@ -229,7 +239,7 @@ __global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t 
     __syncthreads();
     if (threadIdx.x == 0) {
         int32_t run = s;
-        for (int f = 0; f < FINE; ++f) {
+        for (int f = 0; f < fine; ++f) {
             cur[f] = run;
             if (fbase + f < nb) fstart[fbase + f] = run;
             run += cnt[f];
@@ -849,7 +859,8 @@ __global__ __launch_bounds__(STB) void k_stats_final(int32_t nb, const int64_t *
 
 // Bucket size: about 4096 incidences per bucket on average, at most NBMAX buckets.
 struct Buckets {
-    int32_t bs, nb, ncb, nblk1;
+    int32_t bs, nb, fine, ncb, nblk1;
+    uint64_t cmul;   // ceil(2^32 / fine)
 };
 
 Buckets choose_buckets(int64_t N, int64_t NT, int nv)
@@ -862,7 +873,14 @@ Buckets choose_buckets(int64_t N, int64_t NT, int nv)
     while (bs < 12 && cdiv(N, (int64_t)1 << bs) > NBMAX) ++bs;
     B.bs = bs;
     B.nb = (int32_t)cdiv(N, (int64_t)1 << bs);
-    B.ncb = (int32_t)cdiv(B.nb, FINE);
+    // Buckets per coarse bucket.  3-D: as few as keep the coarse-to-fine kernel's
+    // blocks within one resident round, so that round is as full as it can be
+    // (129^3 Kuhn cube: 494 blocks instead of 263).  2-D: 32, since more coarse
+    // buckets shorten the runs the level-1 scatter stores when labels are
+    // scattered, which cost it as much as the fuller round saved (2049^2 grid).
+    B.fine = nv == 4 ? (int32_t)(B.nb > L1SLOTS ? cdiv(B.nb, L1SLOTS) : 1) : FINE;
+    B.ncb = (int32_t)cdiv(B.nb, B.fine);
+    B.cmul = ((uint64_t)1 << 32) / (uint64_t)B.fine + (((uint64_t)1 << 32) % (uint64_t)B.fine ? 1 : 0);
     B.nblk1 = (int32_t)cdiv(NT > 0 ? NT : 1, L1CH);
     return B;
 }
@@ -1007,7 +1025,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     if (NT > 0)
         FE_TIMED("k_l1_hist", s,
                  hipLaunchKernelGGL(k_l1_hist<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, P->bdflag, NT, N,
-                               P->bs, P->ncb, P->nblk1, P->hist1, P->isd, P->status));
+                               P->bs, P->cmul, P->ncb, P->nblk1, P->hist1, P->isd, P->status));
     if ((rc = fe_launch_check())) return rc;
     // Vertex indices are validated by the histogram kernel only: stop here, before
     // any kernel uses elem entries as addresses, if one was out of range.
@@ -1032,11 +1050,11 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, true>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
-                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
+                                        P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
                                         P->bdflag, (const uint8_t *)P->isd, reinterpret_cast<int4 *>(P->elemp),
                                         reinterpret_cast<uint16_t *>(P->ownf)));   // einfo: ownf is free in this order
             FE_TIMED("k_l1_fine", s,
-                     hipLaunchKernelGGL(k_l1_fine<true>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
+                     hipLaunchKernelGGL(k_l1_fine<true>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->fine, P->ncb,
                                         (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
                                         P->pairs2, P->fstart));
         } else {
@@ -1044,10 +1062,10 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, false>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
-                                        P->elem, NT, P->bs, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
+                                        P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
                                         nullptr, nullptr, nullptr, nullptr));
             FE_TIMED("k_l1_fine", s,
-                     hipLaunchKernelGGL(k_l1_fine<false>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->ncb,
+                     hipLaunchKernelGGL(k_l1_fine<false>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->fine, P->ncb,
                                         (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
                                         P->pairs2, P->fstart));
         }
@@ -1197,6 +1215,8 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     P->elem = mesh->elem;
     P->bdflag = mesh->bdflag;
     P->bs = Bk.bs;
+    P->fine = Bk.fine;
+    P->cmul = Bk.cmul;
     P->nb = Bk.nb;
     P->ncb = Bk.ncb;
     P->nblk1 = Bk.nblk1;
