@@ -88,6 +88,7 @@ struct fe_plan {
     uint8_t *isd;         // N      Dirichlet flag (label order)
     uint8_t *isdp;        // N      Dirichlet flag (processing order)
     int4 *precp;          // N      row record (processing order), see rowrec
+    int4 *rslot;          // 4*N    3-D: each row's column set (register form, padded), count -> final pass
     uint8_t *ownf;        // ninc   1 if incidence t*nv+a is the first one of its vertex; in
                           //        label-order processing reused as uint16 per element
                           //        (packed side codes and vertex Dirichlet flags)

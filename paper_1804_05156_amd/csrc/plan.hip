@@ -499,6 +499,7 @@ struct RowArgs {
     int2 *pincm;          // final
     uint32_t *prow_info;  // final
     int4 *precp;          // final
+    int4 *rslot;          // 3-D register form: count: each row's column set written; final: read
     int32_t *status;
 };
 
@@ -539,6 +540,7 @@ template <int B, int CAP> struct LdsSet {
 // into sorted a is new[m] = max(min(a[m], c), a[m-1]) for every m (a[-1] = -inf):
 // branch-free and with fixed register indices, so no LDS and no divergent loops.
 template <int CAP> struct RegSet {
+    static_assert(CAP % 4 == 0, "stored as int4");
     int32_t a[CAP];
     int u;
     FE_DEV void init(int32_t *, int, int32_t i)
@@ -547,6 +549,24 @@ template <int CAP> struct RegSet {
 #pragma unroll
         for (int m = 1; m < CAP; ++m) a[m] = INT32_MAX;
         u = 1;
+    }
+    // The whole array (padding included) to / from a row slot of CAP/4 int4.
+    FE_DEV void store(int4 *slot) const
+    {
+#pragma unroll
+        for (int q = 0; q < CAP / 4; ++q) slot[q] = make_int4(a[4 * q], a[4 * q + 1], a[4 * q + 2], a[4 * q + 3]);
+    }
+    FE_DEV void load(const int4 *slot, int n)
+    {
+#pragma unroll
+        for (int q = 0; q < CAP / 4; ++q) {
+            const int4 v = slot[q];
+            a[4 * q] = v.x;
+            a[4 * q + 1] = v.y;
+            a[4 * q + 2] = v.z;
+            a[4 * q + 3] = v.w;
+        }
+        u = n;
     }
     FE_DEV bool insert(int32_t c)
     {
@@ -625,38 +645,47 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     const int32_t src = from_pinc ? s : R.inclp[k];
     const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
-    set.init(cols, tid, i);
     bool ok = true;
-    for (int32_t j0 = 0; j0 < d && ok; j0 += RUNR) {
-        int32_t key[RUNR];
-        int32_t c[RUNR][NV - 1];
+    // 3-D rows (about 24 incidences, 15 columns): the count pass stores the register
+    // set and the final pass loads it instead of walking the incidences again.  In
+    // 2-D (6 incidences) the stores cost the count pass more than the walk costs.
+    constexpr bool SLOT = REG && NV == 4;
+    if constexpr (FINAL && SLOT) {
+        // the count pass left the row's column set in its slot
+        set.load(R.rslot + (int64_t)k * (REGCAP / 4), R.prowptr[k + 1] - R.prowptr[k]);
+    } else {
+        set.init(cols, tid, i);
+        for (int32_t j0 = 0; j0 < d && ok; j0 += RUNR) {
+            int32_t key[RUNR];
+            int32_t c[RUNR][NV - 1];
 #pragma unroll
-        for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d) key[q] = klist[src + j0 + q];
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) key[q] = klist[src + j0 + q];
 #pragma unroll
-        for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d) {
-                const int32_t t = key[q] / NV;
-                const int a = key[q] - t * NV;
-                if (!FINAL && !LBL) {
-                    R.pinc[s + j0 + q] = key[q];
-                    R.elemp[(int64_t)t * 4 + a] = k;
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) {
+                    const int32_t t = key[q] / NV;
+                    const int a = key[q] - t * NV;
+                    if (!FINAL && !LBL) {
+                        R.pinc[s + j0 + q] = key[q];
+                        R.elemp[(int64_t)t * 4 + a] = k;
+                    }
+                    if (LBL) {
+                        const int4 e4 = reinterpret_cast<const int4 *>(R.elemp)[t];
+#pragma unroll
+                        for (int jj = 0; jj < NV - 1; ++jj) c[q][jj] = sel_i4(e4, fe_other<NV>(a, jj));
+                    } else {
+#pragma unroll
+                        for (int jj = 0; jj < NV - 1; ++jj)
+                            c[q][jj] = R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
+                    }
                 }
-                if (LBL) {
-                    const int4 e4 = reinterpret_cast<const int4 *>(R.elemp)[t];
 #pragma unroll
-                    for (int jj = 0; jj < NV - 1; ++jj) c[q][jj] = sel_i4(e4, fe_other<NV>(a, jj));
-                } else {
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d)
 #pragma unroll
-                    for (int jj = 0; jj < NV - 1; ++jj)
-                        c[q][jj] = R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
-                }
-            }
-#pragma unroll
-        for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d)
-#pragma unroll
-                for (int jj = 0; jj < NV - 1; ++jj) ok = ok && set.insert(c[q][jj]);
+                    for (int jj = 0; jj < NV - 1; ++jj) ok = ok && set.insert(c[q][jj]);
+        }
     }
     if (!ok) {
         atomicOr(R.status + ST_ERR, REG ? ERR_RETRY : ERR_LIMIT);
@@ -665,6 +694,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     }
     const int u = set.u;
     if (!FINAL) {
+        if constexpr (SLOT) set.store(R.rslot + (int64_t)k * (REGCAP / 4));
         R.prowptr[k] = u;
         return;
     }
@@ -897,7 +927,7 @@ int64_t nnz_bound(int64_t N, int64_t NT, int nv)
 enum {
     W_STATUS, W_TOTALS, W_PART, W_VINFO, W_INCLP, W_ISD, W_ISDP, W_OWNF, W_HIST1, W_OWNCNT, W_PI, W_PIINV,
     W_PINCPTR, W_PINC, W_PINCM, W_ELEMP, W_ROWLEN, W_PROWPTR, W_PROWINFO, W_PRECP, W_ROWREC, W_XYP, W_FP,
-    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_COUNT
+    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_RSLOT, W_COUNT
 };
 
 struct Layout {
@@ -945,6 +975,7 @@ Layout plan_layout(int64_t N, int64_t NT, int nv)
     sz[W_SORTED] = sizeof(int32_t) * (size_t)ninc;
     sz[W_PAIRS2] = sizeof(int2) * (size_t)ninc;
     sz[W_FSTART] = sizeof(int32_t) * (size_t)(Bk.nb + 1);
+    sz[W_RSLOT] = nv == 4 ? sizeof(int32_t) * (size_t)REGCAP * (size_t)N : 0;   // 3-D row slots
     Layout L{};
     size_t o = 0;
     for (int k = 0; k < W_COUNT; ++k) {
@@ -986,6 +1017,7 @@ RowArgs row_args(fe_plan *P)
     R.pincm = P->pincm;
     R.prow_info = P->prow_info;
     R.precp = P->precp;
+    R.rslot = P->rslot;
     R.status = P->status;
     return R;
 }
@@ -1249,6 +1281,7 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     P->sorted_l = reinterpret_cast<int32_t *>(base + L.off[W_SORTED]);
     P->pairs2 = reinterpret_cast<int2 *>(base + L.off[W_PAIRS2]);
     P->fstart = reinterpret_cast<int32_t *>(base + L.off[W_FSTART]);
+    P->rslot = reinterpret_cast<int4 *>(base + L.off[W_RSLOT]);
     P->nnz_max = nnz_bound(mesh->n_node, mesh->n_elem, nv);
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = (nv == 3) ? plan_build<3>(P, s) : plan_build<4>(P, s);
