@@ -218,6 +218,33 @@ def test_high_degree_vertex(k):
             data=data_scale(m, specs))
 
 
+def _edge_fan(k):
+    """k tetrahedra around the axis edge (0, 1) (its two vertices have k + 1
+    neighbours); faces opposite vertex 0 Dirichlet, faces opposite vertex 1 Neumann."""
+    ang = 2 * math.pi * np.arange(k) / k
+    node = np.vstack([np.r_[0.0, 0.0, np.cos(ang)], np.r_[0.0, 0.0, np.sin(ang)], np.r_[0.0, 1.0, np.full(k, 0.5)]])
+    ring = np.arange(k)
+    elem = np.array([[0] * k, [1] * k, list(2 + ring), list(2 + (ring + 1) % k)], np.int32)
+    bd = np.zeros((4, k), np.int8)
+    bd[0] = 1
+    bd[1] = 2
+    return meshgen.Mesh(node, elem, bd, np.exp(np.cos(np.arange(k))))
+
+
+@pytest.mark.parametrize("k", [20, 40])
+def test_high_degree_vertex_3d(k):
+    """3-D rows longer than 16 entries: the row passes take the LDS column set
+    (no stored register sets) and the numeric kernel the wider accumulator."""
+    log(f"case: edge fan k={k}")
+    m = _edge_fan(k)
+    specs = [(FE_FN_SINPROD, (1.0,)), (FE_FN_LINEAR, (1.0, 0.5, 0.25, 0.125)), (FE_FN_CONST, (0.5,))]
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    plan, asm = run_gpu(m, None, f, gd, gn)
+    assert plan.info["max_row"] == k + 2
+    compare(host(plan, asm), oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno),
+            data=data_scale(m, specs))
+
+
 def test_row_capacity_limit_is_reported():
     from paper_1804_05156_amd import femhip
     log("case: fan beyond row capacity")
