@@ -43,6 +43,9 @@ struct AsmArgs {
     // the outputs (row k of A at prowptr[k])
     int32_t direct;
     const int4 *precp;     // row records (.z, .w: Dirichlet-column mask), for val_bc
+    // 3-D label-order processing with the register column set: each row's sorted
+    // columns (processing positions), 16 per row, padded (the row passes' slots)
+    const int32_t *rcols;
     double *val, *val_bc, *b, *b_load;
     uint8_t *isd;
     int32_t *status;
@@ -410,10 +413,14 @@ FE_DEV void cross3(const double *u, const double *v, double *w)
 
 FE_DEV double dot3(const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
 
-template <int ROWCAP, int BLOCK, int UNR>
+// COLS: the other vertices' positions come from the row's stored columns (LDS),
+// indexed by the column offsets in each incidence's metadata word, instead of
+// from a gather of the element's record: same vertices, same arithmetic.
+template <int ROWCAP, int BLOCK, int UNR, bool COLS>
 __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
 {
     __shared__ double acc[ROWCAP * BLOCK];
+    __shared__ int32_t cols[COLS ? ROWCAP * BLOCK : 1];
     const int tid = threadIdx.x;
     // contiguous rows per XCD: neighbours lie about N^(2/3) positions apart, a window
     // that interleaved blocks would need in every XCD's L2
@@ -424,6 +431,18 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     const int len = info & 0xff, diag = (info >> 8) & 0xff;
     const bool rowd = (info >> 16) & 1;
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
+    if (COLS) {
+        static_assert(!COLS || ROWCAP == 16, "stored columns: 16 per row");
+        const int4 *rc = reinterpret_cast<const int4 *>(A.rcols) + 4 * (int64_t)k;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int4 v = rc[q];
+            cols[(4 * q) * BLOCK + tid] = v.x;
+            cols[(4 * q + 1) * BLOCK + tid] = v.y;
+            cols[(4 * q + 2) * BLOCK + tid] = v.z;
+            cols[(4 * q + 3) * BLOCK + tid] = v.w;
+        }
+    }
     const double2 *xy = reinterpret_cast<const double2 *>(A.xyp);
     const int4 *ep4 = reinterpret_cast<const int4 *>(A.elemp);
     double Y0[3], fi;   // fi: nodal f at the row's vertex (the fourth word of its record)
@@ -455,16 +474,18 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
         for (int u = 0; u < UNR; ++u)
             if (p0 + u < e) {
                 const int32_t t = km[u].x >> 2;
-                ep[u] = ep4[t];
+                if (!COLS) ep[u] = ep4[t];
                 kt[u] = A.kappa ? A.kappa[t] : 1.0;
             }
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
             if (p0 + u < e) {
                 const int a = km[u].x & 3;
+                const uint32_t meta = (uint32_t)km[u].y;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
-                    pq[u][q] = sel4(ep[u], fe_other<4>(a, q));
+                    pq[u][q] = COLS ? cols[(int)((meta >> (Meta<4>::OFF + Meta<4>::OB * q)) & Meta<4>::OMASK) * BLOCK + tid]
+                                    : sel4(ep[u], fe_other<4>(a, q));
                     const double2 c0 = xy[2 * (int64_t)pq[u][q]], c1 = xy[2 * (int64_t)pq[u][q] + 1];
                     Y[u][q][0] = c0.x; Y[u][q][1] = c0.y; Y[u][q][2] = c1.x;
                     F[u][q] = c1.y;
@@ -663,8 +684,10 @@ template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream
     const unsigned g = (unsigned)cdiv(A.N, BLOCK);
     if (dim == 2) FE_TIMED("k_assemble_2d", s,
              hipLaunchKernelGGL((k_assemble_2d<ROWCAP, BLOCK, 4>), dim3(g), dim3(BLOCK), 0, s, A));
+    else if (ROWCAP == 16 && A.rcols) FE_TIMED("k_assemble_3d", s,
+             hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2, ROWCAP == 16>), dim3(g), dim3(BLOCK), 0, s, A));
     else FE_TIMED("k_assemble_3d", s,
-             hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2>), dim3(g), dim3(BLOCK), 0, s, A));
+             hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2, false>), dim3(g), dim3(BLOCK), 0, s, A));
     return fe_launch_check();
 }
 
@@ -703,6 +726,7 @@ extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double 
     A.valp = plan->valp;
     A.direct = plan->l1_agg;
     A.precp = plan->precp;
+    A.rcols = (plan->dim == 3 && plan->l1_agg && plan->rows_reg) ? reinterpret_cast<const int32_t *>(plan->rslot) : nullptr;
     A.val = val;
     A.val_bc = val_bc;
     A.b = b;
