@@ -85,8 +85,9 @@ template <int DIM> FE_DEV double dirichlet_value(const DevFn &g, int32_t v, cons
     return fn_point<DIM>(g, x);
 }
 
-FE_DEV int sel3(int4 q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : q.z); }
-FE_DEV int sel4(int4 q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
+// Processing position of local vertex c of an element record (see EREC_POS).
+FE_DEV int sel3(int4 q, int c) { return (c == 0 ? q.x : (c == 1 ? q.y : q.z)) & EREC_POS; }
+FE_DEV int sel4(int4 q, int c) { return (c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w))) & EREC_POS; }
 
 // Write the accumulated row and its right-hand side entries, in processing order
 // (consecutive threads write consecutive rows, so the stores are contiguous).

@@ -89,9 +89,7 @@ struct fe_plan {
     uint8_t *isdp;        // N      Dirichlet flag (processing order)
     int4 *precp;          // N      row record (processing order), see rowrec
     int4 *rslot;          // 4*N    3-D: each row's column set (register form, padded), count -> final pass
-    uint8_t *ownf;        // ninc   1 if incidence t*nv+a is the first one of its vertex; in
-                          //        label-order processing reused as uint16 per element
-                          //        (packed side codes and vertex Dirichlet flags)
+    uint8_t *ownf;        // ninc   1 if incidence t*nv+a is the first one of its vertex
     int32_t *hist1;       // nb*nblk1+1  level-1 bucket histogram (bucket-major) -> offsets
     int2 *pairs;          // ninc   (vertex, key) grouped by coarse bucket (shares memory with pincm)
     int2 *pairs2;         // ninc   (vertex, key) grouped by bucket
@@ -106,7 +104,8 @@ struct fe_plan {
     int32_t *pincptr;     // N+1    incidence ranges in processing order
     int32_t *pinc;        // ninc   incidence keys t*nv+a, ascending within a row
     int2 *pincm;          // ninc   (key, metadata word) per incidence, processing order
-    int32_t *elemp;       // 4*NT   processing positions of each element's vertices (AoS)
+    int32_t *elemp;       // 4*NT   processing positions of each element's vertices (AoS),
+                          //        see EREC_POS
     int32_t *rowlen;      // N+1    row lengths (label order) -> row pointer (label order)
     int32_t *prowptr;     // N+1    row lengths (processing order) -> row pointer of the
                           //        processing-order copy of the matrix
@@ -243,6 +242,13 @@ FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *runs)
 
 // Per-lane LDS counter increment (AGG false) or the wavefront-aggregated one above
 // (AGG true; then every lane of the wavefront must call it).
+// Element records (elemp, one int4 per element): word a holds the processing
+// position of vertex a in its low 26 bits (at most 2^26 vertices).  Under
+// label-order processing its top bits also carry the side code of the face
+// opposite vertex a (bits 26-27) and the Dirichlet flag of vertex a (bit 28).
+constexpr int32_t EREC_POS = (1 << 26) - 1;
+constexpr int EREC_CODE = 26, EREC_DIR = 28;
+
 // Logical block of hardware block b in a grid of nblk.  Blocks are dealt to the 8
 // XCDs round-robin (b, b + 8, ... share one XCD and its L2); this bijection gives
 // every XCD a contiguous range of logical blocks, so blocks that run together on

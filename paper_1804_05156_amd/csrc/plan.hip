@@ -127,23 +127,19 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
 
 // Element record for label-order processing.  With the identity order the
 // processing positions of an element's vertices are its labels, so elemp is the
-// element array transposed to one int4 per element.  einfo packs the element's
-// side codes (2 bits per side a, bits 2a..2a+1) and the Dirichlet flags of its
-// vertices (bit 8 + a), which the final row pass would otherwise gather byte by
-// byte.  The level-1 scatter writes both while it reads the element array.
+// element array transposed to one int4 per element; each word also packs the side
+// code opposite its vertex and the vertex's Dirichlet flag (EREC_CODE, EREC_DIR),
+// which the final row pass would otherwise gather byte by byte.  The level-1
+// scatter writes it while it reads the element array.
 template <int NV>
-FE_DEV void elem_record(int32_t t, const int32_t *v, int32_t NT, const int8_t *__restrict__ bd,
-                        const uint8_t *__restrict__ isd, int4 *elemp, uint16_t *einfo)
+FE_DEV void erec_words(int32_t t, const int32_t *v, int32_t NT, const int8_t *__restrict__ bd,
+                       const uint8_t *__restrict__ isd, int32_t *w)
 {
-    uint32_t w = 0;
 #pragma unroll
     for (int a = 0; a < NV; ++a) {
         const uint32_t code = bd ? (uint32_t)bd[(int64_t)a * NT + t] : 0u;
-        w |= (code & 3u) << (2 * a);
-        w |= (uint32_t)(isd[v[a]] & 1u) << (8 + a);
+        w[a] = v[a] | (int32_t)((code & 3u) << EREC_CODE) | (int32_t)((uint32_t)(isd[v[a]] & 1u) << EREC_DIR);
     }
-    elemp[t] = make_int4(v[0], v[1], v[2], NV == 4 ? v[NV - 1] : 0);
-    einfo[t] = (uint16_t)w;
 }
 
 // Level 1b: scatter (vertex, key) pairs into their coarse bucket's range.  The
@@ -157,7 +153,7 @@ template <int NV, bool AGG>
 __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ elem, int32_t NT, int32_t bs,
                                                     uint64_t cmul, int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
                                                     int2 *pairs, const int8_t *__restrict__ bd,
-                                                    const uint8_t *__restrict__ isd, int4 *elemp, uint16_t *einfo)
+                                                    const uint8_t *__restrict__ isd, int4 *elemp)
 {
     extern __shared__ int32_t dyn[];
     __shared__ int2 buf[L1SUB * NV];
@@ -175,17 +171,33 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
     const int32_t t0 = ch * L1CH;
     const int32_t t1 = min(NT, t0 + L1CH);
     for (int32_t s0 = t0; s0 < t1; s0 += L1SUB) {
-        int32_t v[PER][NV], rk[PER][NV];
+        int32_t v[PER][NV], rk[PER][NV], w[PER][NV];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
             const int32_t t = s0 + e * L1B + tid;
 #pragma unroll
-            for (int a = 0; a < NV; ++a) {
-                v[e][a] = t < t1 ? elem[(int64_t)a * NT + t] : 0;
-                rk[e][a] = lds_rank_add<AGG>(cnt, coarse_of(v[e][a], bs, cmul), t < t1);
-            }
-            if (AGG && t < t1) elem_record<NV>(t, v[e], NT, bd, isd, elemp, einfo);
+            for (int a = 0; a < NV; ++a) v[e][a] = t < t1 ? elem[(int64_t)a * NT + t] : 0;
         }
+        // element records: their loads go out before the ranking work, their
+        // stores after it
+        if (AGG)
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int32_t t = s0 + e * L1B + tid;
+                if (t < t1) erec_words<NV>(t, v[e], NT, bd, isd, w[e]);
+            }
+#pragma unroll
+        for (int e = 0; e < PER; ++e) {
+            const int32_t t = s0 + e * L1B + tid;
+#pragma unroll
+            for (int a = 0; a < NV; ++a) rk[e][a] = lds_rank_add<AGG>(cnt, coarse_of(v[e][a], bs, cmul), t < t1);
+        }
+        if (AGG)
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int32_t t = s0 + e * L1B + tid;
+                if (t < t1) elemp[t] = make_int4(w[e][0], w[e][1], w[e][2], NV == 4 ? w[e][NV - 1] : 0);
+            }
         __syncthreads();
         const int32_t c = tid < nb ? cnt[tid] : 0;   // this thread's bucket count
         int32_t tot;
@@ -483,7 +495,9 @@ __global__ __launch_bounds__(EBLOCK) void k_ident(int32_t N, int64_t ninc, const
     isdp[v] = (uint8_t)((vi.y >> 30) & 1);
 }
 
-FE_DEV int32_t sel_i4(const int4 &q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
+FE_DEV int32_t word_i4(const int4 &q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
+// Processing position of local vertex c of an element record.
+FE_DEV int32_t sel_i4(const int4 &q, int c) { return word_i4(q, c) & EREC_POS; }
 
 struct RowArgs {
     int32_t NT, N;
@@ -492,7 +506,6 @@ struct RowArgs {
     const int32_t *pi, *pincptr, *inclp, *sorted_l;
     const uint8_t *isdp;
     int32_t *pinc;        // count: written; final: read (unless LBL)
-    const uint16_t *einfo; // LBL: packed side codes and vertex Dirichlet flags per element
     int32_t *prowptr;     // count: row lengths; final: row starts
     int32_t *elemp;       // count: written; final: read
     int32_t *colindp;     // final
@@ -715,7 +728,6 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         int32_t c[RUNR][NV - 1];
         uint8_t dz[RUNR][NV - 1];
         int8_t code[RUNR][NV - 1];
-        uint32_t ei[RUNR];
 #pragma unroll
         for (int q = 0; q < RUNR; ++q)
             if (j0 + q < d) key[q] = klist[src + j0 + q];
@@ -725,11 +737,10 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 const int32_t t = key[q] / NV;
                 const int a = key[q] - t * NV;
                 ep[q] = ep4[t];
-                if (LBL) ei[q] = R.einfo[t];
 #pragma unroll
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
-                    if (!LBL) {   // LBL: vertices from ep[q], codes from ei[q] below
+                    if (!LBL) {   // LBL: vertices, codes and flags from ep[q] below
                         c[q][jj] = R.elem[(int64_t)b * R.NT + t];
                         code[q][jj] = R.bd ? R.bd[(int64_t)b * R.NT + t] : 0;
                     }
@@ -743,10 +754,11 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
                     const int32_t pb = sel_i4(ep[q], b);
-                    if (LBL) {   // processing position = label; packed codes and flags
+                    if (LBL) {   // processing position = label; packed code and flag
+                        const uint32_t wb = (uint32_t)word_i4(ep[q], b);
                         c[q][jj] = pb;
-                        code[q][jj] = (int8_t)((ei[q] >> (2 * b)) & 3u);
-                        dz[q][jj] = (uint8_t)((ei[q] >> (8 + b)) & 1u);
+                        code[q][jj] = (int8_t)((wb >> EREC_CODE) & 3u);
+                        dz[q][jj] = (uint8_t)((wb >> EREC_DIR) & 1u);
                     } else {
                         dz[q][jj] = R.isdp[pb];
                     }
@@ -1010,7 +1022,6 @@ RowArgs row_args(fe_plan *P)
     R.sorted_l = P->sorted_l;
     R.isdp = P->isdp;
     R.pinc = P->pinc;
-    R.einfo = reinterpret_cast<const uint16_t *>(P->ownf);
     R.prowptr = P->prowptr;
     R.elemp = P->elemp;
     R.colindp = reinterpret_cast<int32_t *>(P->valp);
@@ -1083,8 +1094,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, true>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
                                         P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
-                                        P->bdflag, (const uint8_t *)P->isd, reinterpret_cast<int4 *>(P->elemp),
-                                        reinterpret_cast<uint16_t *>(P->ownf)));   // einfo: ownf is free in this order
+                                        P->bdflag, (const uint8_t *)P->isd, reinterpret_cast<int4 *>(P->elemp)));
             FE_TIMED("k_l1_fine", s,
                      hipLaunchKernelGGL(k_l1_fine<true>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->fine, P->ncb,
                                         (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
@@ -1095,7 +1105,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, false>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
                                         P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
-                                        nullptr, nullptr, nullptr, nullptr));
+                                        nullptr, nullptr, nullptr));
             FE_TIMED("k_l1_fine", s,
                      hipLaunchKernelGGL(k_l1_fine<false>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->fine, P->ncb,
                                         (const int32_t *)P->hist1, P->nblk1, P->ninc, (const int2 *)P->pairs,
