@@ -243,9 +243,9 @@ FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *runs)
 // Per-lane LDS counter increment (AGG false) or the wavefront-aggregated one above
 // (AGG true; then every lane of the wavefront must call it).
 // Element records (elemp, one int4 per element): word a holds the processing
-// position of vertex a in its low 26 bits (at most 2^26 vertices).  Under
-// label-order processing its top bits also carry the side code of the face
-// opposite vertex a (bits 26-27) and the Dirichlet flag of vertex a (bit 28).
+// position of vertex a in its low 26 bits (at most 2^26 vertices), the side code
+// of the face opposite vertex a in bits 26-27 and the Dirichlet flag of vertex a
+// in bit 28.
 constexpr int32_t EREC_POS = (1 << 26) - 1;
 constexpr int EREC_CODE = 26, EREC_DIR = 28;
 

@@ -655,6 +655,9 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         return;
     }
     const bool from_pinc = FINAL && !LBL;
+    // general path: the count pass writes the element record words of this row's
+    // vertex (position, side code opposite it, its Dirichlet flag)
+    const int32_t rowdir = (!FINAL && !LBL && R.isdp[k]) ? (1 << EREC_DIR) : 0;
     const int32_t src = from_pinc ? s : R.inclp[k];
     const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
@@ -671,6 +674,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         for (int32_t j0 = 0; j0 < d && ok; j0 += RUNR) {
             int32_t key[RUNR];
             int32_t c[RUNR][NV - 1];
+            int32_t code[RUNR];
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
                 if (j0 + q < d) key[q] = klist[src + j0 + q];
@@ -679,10 +683,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 if (j0 + q < d) {
                     const int32_t t = key[q] / NV;
                     const int a = key[q] - t * NV;
-                    if (!FINAL && !LBL) {
-                        R.pinc[s + j0 + q] = key[q];
-                        R.elemp[(int64_t)t * 4 + a] = k;
-                    }
+                    if (!FINAL && !LBL) code[q] = R.bd ? (int32_t)(R.bd[(int64_t)a * R.NT + t] & 3) : 0;
                     if (LBL) {
                         const int4 e4 = reinterpret_cast<const int4 *>(R.elemp)[t];
 #pragma unroll
@@ -693,6 +694,15 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                             c[q][jj] = R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
                     }
                 }
+            if (!FINAL && !LBL)   // stores after all of the batch's loads
+#pragma unroll
+                for (int q = 0; q < RUNR; ++q)
+                    if (j0 + q < d) {
+                        const int32_t t = key[q] / NV;
+                        const int a = key[q] - t * NV;
+                        R.pinc[s + j0 + q] = key[q];
+                        R.elemp[(int64_t)t * 4 + a] = k | (code[q] << EREC_CODE) | rowdir;
+                    }
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
                 if (j0 + q < d)
@@ -740,10 +750,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
 #pragma unroll
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
-                    if (!LBL) {   // LBL: vertices, codes and flags from ep[q] below
-                        c[q][jj] = R.elem[(int64_t)b * R.NT + t];
-                        code[q][jj] = R.bd ? R.bd[(int64_t)b * R.NT + t] : 0;
-                    }
+                    if (!LBL) c[q][jj] = R.elem[(int64_t)b * R.NT + t];   // labels (LBL: from ep[q])
                 }
             }
 #pragma unroll
@@ -753,15 +760,10 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
 #pragma unroll
                 for (int jj = 0; jj < NV - 1; ++jj) {
                     const int b = fe_other<NV>(a, jj);
-                    const int32_t pb = sel_i4(ep[q], b);
-                    if (LBL) {   // processing position = label; packed code and flag
-                        const uint32_t wb = (uint32_t)word_i4(ep[q], b);
-                        c[q][jj] = pb;
-                        code[q][jj] = (int8_t)((wb >> EREC_CODE) & 3u);
-                        dz[q][jj] = (uint8_t)((wb >> EREC_DIR) & 1u);
-                    } else {
-                        dz[q][jj] = R.isdp[pb];
-                    }
+                    const uint32_t wb = (uint32_t)word_i4(ep[q], b);   // packed code and flag
+                    if (LBL) c[q][jj] = (int32_t)(wb & EREC_POS);      // processing position = label
+                    code[q][jj] = (int8_t)((wb >> EREC_CODE) & 3u);
+                    dz[q][jj] = (uint8_t)((wb >> EREC_DIR) & 1u);
                 }
             }
 #pragma unroll
