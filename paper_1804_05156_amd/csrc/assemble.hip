@@ -147,33 +147,51 @@ __global__ __launch_bounds__(256) void k_values_to_label(int32_t N, const int32_
         rec = rowrec[i];
         rec.x += 2 * piinv[i];                         // start of the row in valp
         const int len = rec.y & 0xff;
-        b[i] = valp[rec.x + len];
-        if (b_load) b_load[i] = valp[rec.x + len + 1];
+        const double bi = valp[rec.x + len], bl = b_load ? valp[rec.x + len + 1] : 0.0;
+        b[i] = bi;
+        if (b_load) b_load[i] = bl;
         if (isd) isd[i] = (uint8_t)((rec.y >> 16) & 1);
     }
     srec[w][lane] = rec;
     __syncthreads();
     const int32_t base = sdst[w][0];
     const int32_t total = sdst[w][64] - base;
-    for (int32_t e = lane; e < total; e += 64) {
-        const int32_t pos = base + e;
-        int lo = 0, hi = 63;   // last row r with sdst[r] <= pos
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sdst[w][mid] <= pos) lo = mid;
-            else hi = mid - 1;
+    // CU gathers per lane in flight, then their stores
+    constexpr int CU = 4;
+    for (int32_t e0 = lane; e0 < total; e0 += 64 * CU) {
+        double v[CU];
+        int row[CU], col[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int32_t e = e0 + 64 * u;
+            if (e >= total) break;
+            const int32_t pos = base + e;
+            int lo = 0, hi = 63;   // last row r with sdst[r] <= pos
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sdst[w][mid] <= pos) lo = mid;
+                else hi = mid - 1;
+            }
+            row[u] = lo;
+            col[u] = pos - sdst[w][lo];
+            v[u] = valp[srec[w][lo].x + col[u]];
         }
-        const int4 r = srec[w][lo];
-        const int c = pos - sdst[w][lo];
-        const double v = valp[r.x + c];
-        val[pos] = v;
-        if (val_bc) {
-            const uint32_t info = (uint32_t)r.y;
-            const uint64_t dm = (uint64_t)(uint32_t)r.z | ((uint64_t)(uint32_t)r.w << 32);
-            double vb = v;
-            if ((info >> 16) & 1u) vb = (c == (int)((info >> 8) & 0xffu)) ? 1.0 : 0.0;
-            else if ((dm >> c) & 1ull) vb = 0.0;
-            val_bc[pos] = vb;
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int32_t e = e0 + 64 * u;
+            if (e >= total) break;
+            const int32_t pos = base + e;
+            val[pos] = v[u];
+            if (val_bc) {
+                const int4 r = srec[w][row[u]];
+                const int c = col[u];
+                const uint32_t info = (uint32_t)r.y;
+                const uint64_t dm = (uint64_t)(uint32_t)r.z | ((uint64_t)(uint32_t)r.w << 32);
+                double vb = v[u];
+                if ((info >> 16) & 1u) vb = (c == (int)((info >> 8) & 0xffu)) ? 1.0 : 0.0;
+                else if ((dm >> c) & 1ull) vb = 0.0;
+                val_bc[pos] = vb;
+            }
         }
     }
 }

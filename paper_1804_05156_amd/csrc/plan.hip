@@ -820,15 +820,26 @@ __global__ __launch_bounds__(256) void k_pattern_to_label(int32_t N, const int32
     __syncthreads();
     const int32_t base = sdst[w][0];
     const int32_t total = sdst[w][64] - base;
-    for (int32_t e = lane; e < total; e += 64) {
-        const int32_t pos = base + e;
-        int lo = 0, hi = 63;   // last row r with sdst[r] <= pos
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (sdst[w][mid] <= pos) lo = mid;
-            else hi = mid - 1;
+    // CU gathers per lane in flight, then their stores
+    constexpr int CU = 4;
+    for (int32_t e0 = lane; e0 < total; e0 += 64 * CU) {
+        int32_t v[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u) {
+            const int32_t e = e0 + 64 * u;
+            if (e >= total) break;
+            const int32_t pos = base + e;
+            int lo = 0, hi = 63;   // last row r with sdst[r] <= pos
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sdst[w][mid] <= pos) lo = mid;
+                else hi = mid - 1;
+            }
+            v[u] = colindp[ssrc[w][lo] + (pos - sdst[w][lo])];
         }
-        colind[pos] = colindp[ssrc[w][lo] + (pos - sdst[w][lo])];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (e0 + 64 * u < total) colind[base + e0 + 64 * u] = v[u];
     }
 }
 
