@@ -928,12 +928,12 @@ Buckets choose_buckets(int64_t N, int64_t NT, int nv)
     while (bs < 12 && cdiv(N, (int64_t)1 << bs) > NBMAX) ++bs;
     B.bs = bs;
     B.nb = (int32_t)cdiv(N, (int64_t)1 << bs);
-    // Buckets per coarse bucket.  3-D: as few as keep the coarse-to-fine kernel's
-    // blocks within one resident round, so that round is as full as it can be
-    // (129^3 Kuhn cube: 494 blocks instead of 263).  2-D: 32, since more coarse
-    // buckets shorten the runs the level-1 scatter stores when labels are
-    // scattered, which cost it as much as the fuller round saved (2049^2 grid).
-    B.fine = nv == 4 ? (int32_t)(B.nb > L1SLOTS ? cdiv(B.nb, L1SLOTS) : 1) : FINE;
+    // Buckets per coarse bucket: as few as keep the coarse-to-fine kernel's blocks
+    // within one resident round, so that round is as full as it can be (129^3 Kuhn
+    // cube: 494 blocks instead of 263, 381 -> 263 us; 2049^2 grid: 483 instead of
+    // 257, 182 -> 169 us, for 7 us more in the level-1 scatter, whose runs get
+    // shorter with more coarse buckets).
+    B.fine = (int32_t)(B.nb > L1SLOTS ? cdiv(B.nb, L1SLOTS) : 1);
     B.ncb = (int32_t)cdiv(B.nb, B.fine);
     B.cmul = ((uint64_t)1 << 32) / (uint64_t)B.fine + (((uint64_t)1 << 32) % (uint64_t)B.fine ? 1 : 0);
     B.nblk1 = (int32_t)cdiv(NT > 0 ? NT : 1, L1CH);
