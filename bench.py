@@ -71,7 +71,6 @@ def kernel_bytes(name, N, NT, nnz, dim, nodal):
         "k_l1_scatter": 4 * ninc + 8 * ninc,
         "k_l1_fine": 8 * ninc + 8 * ninc,
         "k_l2_bucket": 8 * ninc + N + 4 * ninc + 8 * N + N,
-        "k_own_count": ninc + 4 * NT,
         "k_pi": ninc + 4 * NT + 4 * N + 8 * N + 17 * N,
         "k_unused": 8 * N,
         "k_rows_count": 12 * N + 4 * ninc + 4 * ninc + 4 * ninc + 16 * NT + 4 * N,

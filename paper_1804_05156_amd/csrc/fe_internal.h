@@ -327,6 +327,10 @@ static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // The 64-bit total is also stored at *total_dev; ERR_OVERFLOW is set in *status if
 // it does not fit int32.  `part` needs fe_scan_part_elems(n) int64 entries.
 int64_t fe_scan_part_elems(int64_t n);
+// The same scan over per-entry counts of flag bytes: entry i is the sum of the nv
+// (3 or 4) bytes flags[nv*i .. nv*i + nv); flags 4-byte aligned.
+int fe_scan_exclusive_flags(const uint8_t *flags, int nv, int32_t *out, int64_t n, int64_t *total_dev, int64_t *part,
+                            int32_t *status, hipStream_t s);
 int fe_scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int64_t *total_dev, int64_t *part,
                       int32_t *status, hipStream_t s);
 

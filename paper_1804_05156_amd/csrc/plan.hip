@@ -43,7 +43,7 @@ constexpr int FB = 1024;        // threads of the coarse-to-fine kernel
 constexpr int L1SUB = 2048;     // elements per LDS-staged sub-chunk of the level-1 scatter
 static_assert(NBMAX / FINE <= L1SLOTS && L1SLOTS <= L1B, "one thread per coarse bucket in the level-1 scatter");
 static_assert(L1SUB % L1B == 0, "whole sub-chunks per thread");
-constexpr int RUNR = 4;         // incidences per batch in the row kernels
+constexpr int RUNR = 8;         // incidences per batch in the row kernels
 
 // Level-1 chunk of block b: contiguous chunk ranges per XCD, so the runs that
 // neighbouring chunks write into one bucket are written through the same L2.
@@ -421,15 +421,6 @@ __global__ __launch_bounds__(BKB) void k_l2_bucket_global(int32_t N, int32_t bs,
     }
 }
 
-template <int NV>
-__global__ __launch_bounds__(EBLOCK) void k_own_count(int32_t NT, const uint8_t *__restrict__ ownf, int32_t *owncnt)
-{
-    const int32_t t = blockIdx.x * EBLOCK + threadIdx.x;
-    if (t >= NT) return;
-    int c = 0;
-    for (int a = 0; a < NV; ++a) c += ownf[(int64_t)t * NV + a];
-    owncnt[t] = c;
-}
 
 // Processing order: the vertex owned by incidence (t, a) goes to position
 // ownoff[t] + (rank of a among t's owned vertices).
@@ -1143,10 +1134,6 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                  hipLaunchKernelGGL(k_l2_bucket_global, dim3((unsigned)P->nb), dim3(BKB), 0, s, N, P->bs, (int32_t)cap,
                                (const int32_t *)P->fstart, (const int2 *)P->pairs2, (const uint8_t *)P->isd,
                                P->sorted_l, P->vinfo, P->rowlen, P->prowptr, ownf));
-        if (!P->l1_agg)
-            FE_TIMED("k_own_count", s,
-                     hipLaunchKernelGGL(k_own_count<NV>, dim3(eg), dim3(EBLOCK), 0, s, NT, (const uint8_t *)P->ownf,
-                                        P->owncnt));
         if ((rc = fe_launch_check())) return rc;
     }
     if (P->l1_agg) {
@@ -1157,7 +1144,8 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         if ((rc = fe_launch_check())) return rc;
     } else {
         // processing position = rank of the vertex's first incidence (element order)
-        if ((rc = fe_scan_exclusive(P->owncnt, P->owncnt, NT, P->totals + 0, P->part, P->status, s))) return rc;
+        // first incidences per element, scanned straight from the flags
+        if ((rc = fe_scan_exclusive_flags(P->ownf, NV, P->owncnt, NT, P->totals + 0, P->part, P->status, s))) return rc;
         if (NT > 0)
             FE_TIMED("k_pi", s,
                      hipLaunchKernelGGL(k_pi<NV>, dim3(eg), dim3(EBLOCK), 0, s, P->elem, NT, (const uint8_t *)P->ownf,

@@ -44,29 +44,64 @@ template <int BLOCK = SCAN_BLOCK> FE_DEV int64_t block_exclusive(int64_t v, int6
 }
 
 // A tile is SCAN_CHUNKS chunks of 1024 elements; in each chunk thread t holds
-// elements 4t..4t+3, so every int4 load and store of a wavefront is contiguous.
-FE_DEV void load_tile(const int32_t *in, int64_t n, int64_t tile0, int4 q[SCAN_CHUNKS])
+// elements 4t..4t+3, so every load and store of a wavefront is contiguous.
+// FL = 0: int32 input.  FL = 3 or 4: element i is the sum of the FL bytes
+// in[FL*i .. FL*i + FL) (per-element flag counts, read as 32-bit words).
+template <int FL> FE_DEV int32_t in_at(const void *in, int64_t i)
+{
+    if constexpr (FL == 0) {
+        return static_cast<const int32_t *>(in)[i];
+    } else {
+        const uint8_t *f = static_cast<const uint8_t *>(in) + (int64_t)FL * i;
+        int32_t s = 0;
+#pragma unroll
+        for (int a = 0; a < FL; ++a) s += f[a];
+        return s;
+    }
+}
+
+template <int FL> FE_DEV void load_tile(const void *in, int64_t n, int64_t tile0, int4 q[SCAN_CHUNKS])
 {
     for (int c = 0; c < SCAN_CHUNKS; ++c) {
         const int64_t base = tile0 + (int64_t)c * SCAN_CHUNK + 4 * (int64_t)threadIdx.x;
         if (base + 4 <= n) {
-            q[c] = *reinterpret_cast<const int4 *>(in + base);
+            if constexpr (FL == 0) {
+                q[c] = *reinterpret_cast<const int4 *>(static_cast<const int32_t *>(in) + base);
+            } else {
+                // 4 elements = FL aligned words (base is a multiple of 4)
+                const uint32_t *p = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(in) + FL * base);
+                uint32_t w[FL];
+#pragma unroll
+                for (int j = 0; j < FL; ++j) w[j] = p[j];
+                int32_t e[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    e[k] = 0;
+#pragma unroll
+                    for (int a = 0; a < FL; ++a) {
+                        const int j = k * FL + a;
+                        e[k] += (int32_t)((w[j >> 2] >> (8 * (j & 3))) & 0xffu);
+                    }
+                }
+                q[c] = make_int4(e[0], e[1], e[2], e[3]);
+            }
         } else {
-            q[c].x = (base + 0 < n) ? in[base + 0] : 0;
-            q[c].y = (base + 1 < n) ? in[base + 1] : 0;
-            q[c].z = (base + 2 < n) ? in[base + 2] : 0;
-            q[c].w = (base + 3 < n) ? in[base + 3] : 0;
+            q[c].x = (base + 0 < n) ? in_at<FL>(in, base + 0) : 0;
+            q[c].y = (base + 1 < n) ? in_at<FL>(in, base + 1) : 0;
+            q[c].z = (base + 2 < n) ? in_at<FL>(in, base + 2) : 0;
+            q[c].w = (base + 3 < n) ? in_at<FL>(in, base + 3) : 0;
         }
     }
 }
 
 FE_DEV int64_t sum4(int4 q) { return (int64_t)q.x + q.y + q.z + q.w; }
 
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const int32_t *in, int64_t n, int64_t *part)
+template <int FL>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_reduce(const void *in, int64_t n, int64_t *part)
 {
     __shared__ int64_t lds[2 * (SCAN_BLOCK / 64)];
     int4 q[SCAN_CHUNKS];
-    load_tile(in, n, (int64_t)blockIdx.x * SCAN_TILE, q);
+    load_tile<FL>(in, n, (int64_t)blockIdx.x * SCAN_TILE, q);
     int64_t s = 0;
     for (int c = 0; c < SCAN_CHUNKS; ++c) s += sum4(q[c]);
     int64_t tot;
@@ -110,14 +145,14 @@ __global__ __launch_bounds__(SP_BLOCK) void k_scan_partials(int64_t *part, int64
 // DIRECT: part[] holds the tile sums and block b adds part[0..b) itself; the
 // last block also writes the total.  Otherwise part[] already holds the tiles'
 // exclusive offsets.
-template <bool DIRECT>
-__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const int32_t *in, int32_t *out, int64_t n,
+template <bool DIRECT, int FL>
+__global__ __launch_bounds__(SCAN_BLOCK) void k_scan_apply(const void *in, int32_t *out, int64_t n,
                                                            const int64_t *part, int64_t *total_dev, int32_t *status)
 {
     __shared__ int64_t lds[2 * (SCAN_BLOCK / 64)];
     const int64_t tile0 = (int64_t)blockIdx.x * SCAN_TILE;
     int4 q[SCAN_CHUNKS];
-    load_tile(in, n, tile0, q);
+    load_tile<FL>(in, n, tile0, q);
     int64_t carry;
     if (DIRECT) {
         int64_t s = 0;
@@ -198,27 +233,46 @@ extern "C" int fe_select(int64_t n, const uint8_t *mask, const double *a, const 
 
 int64_t fe_scan_part_elems(int64_t n) { return cdiv(n > 0 ? n : 1, SCAN_TILE) + 1; }
 
-int fe_scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int64_t *total_dev, int64_t *part,
-                      int32_t *status, hipStream_t s)
+namespace {
+
+template <int FL>
+int scan_exclusive(const void *in, int32_t *out, int64_t n, int64_t *total_dev, int64_t *part, int32_t *status,
+                   hipStream_t s)
 {
-    // in/out must be 16-byte aligned (workspace arrays are 256-byte aligned).
-    if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return FE_EINVAL;
     const int64_t nb = cdiv(n > 0 ? n : 1, SCAN_TILE);
     FE_TIMED("k_scan_reduce", s,
-             hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part));
+             hipLaunchKernelGGL(k_scan_reduce<FL>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, n, part));
     if (nb <= SCAN_DIRECT_TILES) {
         FE_TIMED("k_scan_apply", s,
-                 hipLaunchKernelGGL(k_scan_apply<true>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part,
-                                    total_dev, status));
+                 hipLaunchKernelGGL((k_scan_apply<true, FL>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n,
+                                    part, total_dev, status));
     } else {
         FE_TIMED("k_scan_partials", s,
                  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(SP_BLOCK), 0, s, part, nb, total_dev, out, n,
                                     status));
         FE_TIMED("k_scan_apply", s,
-                 hipLaunchKernelGGL(k_scan_apply<false>, dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n, part,
-                                    total_dev, status));
+                 hipLaunchKernelGGL((k_scan_apply<false, FL>), dim3((unsigned)nb), dim3(SCAN_BLOCK), 0, s, in, out, n,
+                                    part, total_dev, status));
     }
     return fe_launch_check();
+}
+
+}  // namespace
+
+int fe_scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int64_t *total_dev, int64_t *part,
+                      int32_t *status, hipStream_t s)
+{
+    // in/out must be 16-byte aligned (workspace arrays are 256-byte aligned).
+    if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return FE_EINVAL;
+    return scan_exclusive<0>(in, out, n, total_dev, part, status, s);
+}
+
+int fe_scan_exclusive_flags(const uint8_t *flags, int nv, int32_t *out, int64_t n, int64_t *total_dev, int64_t *part,
+                            int32_t *status, hipStream_t s)
+{
+    if (((uintptr_t)flags & 3) || ((uintptr_t)out & 15) || (nv != 3 && nv != 4)) return FE_EINVAL;
+    return nv == 3 ? scan_exclusive<3>(flags, out, n, total_dev, part, status, s)
+                   : scan_exclusive<4>(flags, out, n, total_dev, part, status, s);
 }
 
 int fe_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) { return fill<int32_t>(p, n, v, s); }

@@ -7,7 +7,7 @@ import bench
 
 def test_byte_models_cover_the_assembly_kernels():
     N, NT, nnz = 4198401, 8388608, 29372417
-    names = ["k_l1_hist", "k_l1_scatter", "k_l1_fine", "k_l2_bucket", "k_own_count", "k_pi", "k_rows_count",
+    names = ["k_l1_hist", "k_l1_scatter", "k_l1_fine", "k_l2_bucket", "k_pi", "k_rows_count",
              "k_rows_final", "k_label_rows", "k_pattern_to_label", "k_scatter_coords", "k_assemble_2d",
              "k_values_to_label"]
     for n in names:
