@@ -73,9 +73,9 @@ def kernel_bytes(name, N, NT, nnz, dim, nodal):
         "k_l2_bucket": 8 * ninc + N + 4 * ninc + 8 * N + N,
         "k_pi": ninc + 4 * NT + 4 * N + 8 * N + 17 * N,
         "k_unused": 8 * N,
-        "k_rows_count": 12 * N + 4 * ninc + 4 * ninc + 4 * ninc + 16 * NT + 4 * N,
+        "k_rows_count": 12 * N + 4 * ninc + 4 * ninc + 4 * ninc + ninc + 16 * NT + 4 * N,
         "k_stats_partial": 9 * N,
-        "k_rows_final": 12 * N + 4 * ninc + 16 * NT + 4 * ninc + ninc + N + 4 * nnz + 8 * ninc + 20 * N,
+        "k_rows_final": 12 * N + 4 * ninc + 16 * NT + 4 * ninc + N + 4 * nnz + 8 * ninc + 20 * N,
         "k_label_rows": 40 * N,
         "k_pattern_to_label": 20 * N + 8 * nnz,
         "k_scatter_coords": 8 * dim * N + 4 * N + 32 * N + (16 * N if nodal else 0),
