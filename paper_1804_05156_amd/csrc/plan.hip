@@ -1118,8 +1118,8 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         // first-incidence flags, for the processing order of the general path
         uint8_t *ownf = P->l1_agg ? nullptr : P->ownf;
         if (ownf && (rc = fe_fill_u8(ownf, P->ninc, 0, s))) return rc;
-        // LDS capacity per bucket: twice the average bucket, at least 2048 keys
-        int64_t cap = cdiv(2 * P->ninc, P->nb);
+        // LDS capacity per bucket: 1.5 times the average bucket, at least 2048 keys
+        int64_t cap = cdiv(3 * P->ninc, 2 * (int64_t)P->nb);
         cap = cdiv(cap, 1024) * 1024;
         if (cap < 2048) cap = 2048;
         if (cap > BCAPMAX) cap = BCAPMAX;
