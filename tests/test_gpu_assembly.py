@@ -355,6 +355,30 @@ def test_full_size_jittered_2049_sampled():
     assert torch.all((val[order] - val).abs() <= 1e-13 * scale)
 
 
+def test_element_prefix_sum_beyond_tile_limit_sampled():
+    """A 2898^2 grid with scattered labels has 16,785,218 > 4096^2 triangles, so the
+    prefix sum of first incidences per element (general path) takes its three-launch
+    form.  Built directly (plain grid, two triangles a cell, random labels, no
+    boundary sides); sampled rows against the oracle, and the pattern size."""
+    n = 2898
+    log(f"case: {n}^2 grid, scattered labels, elements beyond the two-launch scan")
+    N = n * n
+    rng = np.random.default_rng(29)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="xy")
+    node = np.vstack([i.ravel() / (n - 1), j.ravel() / (n - 1)])
+    c = np.arange((n - 1) * (n - 1))
+    p1 = (c // (n - 1)) * n + c % (n - 1)
+    elem = np.hstack([np.vstack([p1, p1 + 1, p1 + n + 1]), np.vstack([p1, p1 + n + 1, p1 + n])]).astype(np.int32)
+    perm = rng.permutation(N).astype(np.int32)
+    nodep = np.empty_like(node)
+    nodep[:, perm] = node
+    m = meshgen.Mesh(nodep, perm[elem], np.zeros(elem.shape, np.int8), np.exp(rng.standard_normal(elem.shape[1])))
+    assert m.n_elem > SCAN_TILE_EDGE
+    plan, asm, g = _sampled_full_size(m, [(FE_FN_CONST, (1.0,))], nsample=32)
+    assert not plan.info["sort_runs"]
+    assert plan.nnz == 3 * N + 2 * m.n_elem - 2
+
+
 def test_full_size_kuhn129_sampled():
     log("case: 129^3 Kuhn, full size")
     m = meshgen.workload("kuhn129")
