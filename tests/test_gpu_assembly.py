@@ -177,7 +177,10 @@ def test_prefix_sum_tile_limit(extra, labels):
     the two-launch form and one past it (a one-block scan of the tile sums in
     between).  Labels either lead (0.., element order: label-order processing) or
     are scattered over the whole range (the general path, which scans three
-    per-vertex arrays).  f = 1, so the oracle's own term sums set the b scale."""
+    per-vertex arrays).  With leading labels the used vertices fill a few buckets
+    sized for the (tiny) average degree, far beyond their LDS capacity, so those
+    buckets take the level-2 kernel's global-memory path.  f = 1, so the oracle's
+    own term sums set the b scale."""
     N = SCAN_TILE_EDGE + extra
     log(f"case: prefix-sum tile limit, N = {N}, labels {labels}")
     small = meshgen.square_mesh(129, jitter=0.2, permute=False, seed=91, kappa="lognormal")
