@@ -89,6 +89,7 @@ struct fe_plan {
     uint8_t *isdp;        // N      Dirichlet flag (processing order)
     int4 *precp;          // N      row record (processing order), see rowrec
     int4 *rslot;          // 4*N    3-D: each row's column set (register form, padded), count -> final pass
+    int2 *rmask;          // N      3-D label-order register form: row Dirichlet-column masks, count -> final
     uint8_t *ownf;        // ninc   1 if incidence t*nv+a is the first one of its vertex
     int32_t *hist1;       // nb*nblk1+1  level-1 bucket histogram (bucket-major) -> offsets
     int2 *pairs;          // ninc   (vertex, key) grouped by coarse bucket (shares memory with pincm)

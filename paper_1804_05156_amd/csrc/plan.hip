@@ -504,6 +504,7 @@ struct RowArgs {
     uint32_t *prow_info;  // final
     int4 *precp;          // final
     int4 *rslot;          // 3-D register form: count: each row's column set written; final: read
+    int2 *rmask;          // 3-D label-order register form: each row's Dirichlet-column mask
     int32_t *status;
 };
 
@@ -706,9 +707,77 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         if (!FINAL) R.prowptr[k] = 0;
         return;
     }
+    // Metadata word of every incidence of the row (local vertex, column offsets of the
+    // other vertices, Dirichlet / Neumann / Robin bits) to pincm; returns the row's
+    // Dirichlet-column mask.
+    auto meta_walk = [&]() -> uint64_t {
+        uint64_t dmask = 0;
+        const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
+        for (int32_t j0 = 0; j0 < d; j0 += RUNR) {
+            int32_t key[RUNR];
+            int4 ep[RUNR];
+            int32_t c[RUNR][NV - 1];
+            uint8_t dz[RUNR][NV - 1];
+            int8_t code[RUNR][NV - 1];
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) key[q] = klist[src + j0 + q];
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) {
+                    const int32_t t = key[q] / NV;
+                    const int a = key[q] - t * NV;
+                    ep[q] = ep4[t];
+#pragma unroll
+                    for (int jj = 0; jj < NV - 1; ++jj) {
+                        const int b = fe_other<NV>(a, jj);
+                        if (!LBL) c[q][jj] = R.elem[(int64_t)b * R.NT + t];   // labels (LBL: from ep[q])
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) {
+                    const int a = key[q] % NV;
+#pragma unroll
+                    for (int jj = 0; jj < NV - 1; ++jj) {
+                        const int b = fe_other<NV>(a, jj);
+                        const uint32_t wb = (uint32_t)word_i4(ep[q], b);   // packed code and flag
+                        if (LBL) c[q][jj] = (int32_t)(wb & EREC_POS);      // processing position = label
+                        code[q][jj] = (int8_t)((wb >> EREC_CODE) & 3u);
+                        dz[q][jj] = (uint8_t)((wb >> EREC_DIR) & 1u);
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) {
+                    uint32_t meta = (uint32_t)(key[q] % NV);
+#pragma unroll
+                    for (int jj = 0; jj < NV - 1; ++jj) {
+                        const int m = set.find(c[q][jj]);   // present by construction
+                        meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
+                        if (dz[q][jj]) {
+                            meta |= 1u << (Meta<NV>::DBIT + jj);
+                            dmask |= 1ull << m;
+                        }
+                        if (code[q][jj] == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
+                        if (code[q][jj] == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
+                    }
+                    R.pincm[s + j0 + q] = make_int2(key[q], (int32_t)meta);
+                }
+        }
+        return dmask;
+    };
+    // 3-D label-order processing with stored sets: the count pass writes the
+    // metadata while the row's element records are still in cache, and the final
+    // pass only writes the columns and the row record.
+    constexpr bool MERGE = LBL && SLOT;
     const int u = set.u;
     if (!FINAL) {
         if constexpr (SLOT) set.store(R.rslot + (int64_t)k * (REGCAP / 4));
+        if constexpr (MERGE) {
+            const uint64_t dm = meta_walk();
+            R.rmask[k] = make_int2((int32_t)(uint32_t)dm, (int32_t)(uint32_t)(dm >> 32));
+        }
         R.prowptr[k] = u;
         return;
     }
@@ -721,59 +790,12 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         R.colindp[ps + m] = c;
         if (c == i) diag = m;
     }
-    uint64_t dmask = 0;
-    const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
-    for (int32_t j0 = 0; j0 < d; j0 += RUNR) {
-        int32_t key[RUNR];
-        int4 ep[RUNR];
-        int32_t c[RUNR][NV - 1];
-        uint8_t dz[RUNR][NV - 1];
-        int8_t code[RUNR][NV - 1];
-#pragma unroll
-        for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d) key[q] = klist[src + j0 + q];
-#pragma unroll
-        for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d) {
-                const int32_t t = key[q] / NV;
-                const int a = key[q] - t * NV;
-                ep[q] = ep4[t];
-#pragma unroll
-                for (int jj = 0; jj < NV - 1; ++jj) {
-                    const int b = fe_other<NV>(a, jj);
-                    if (!LBL) c[q][jj] = R.elem[(int64_t)b * R.NT + t];   // labels (LBL: from ep[q])
-                }
-            }
-#pragma unroll
-        for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d) {
-                const int a = key[q] % NV;
-#pragma unroll
-                for (int jj = 0; jj < NV - 1; ++jj) {
-                    const int b = fe_other<NV>(a, jj);
-                    const uint32_t wb = (uint32_t)word_i4(ep[q], b);   // packed code and flag
-                    if (LBL) c[q][jj] = (int32_t)(wb & EREC_POS);      // processing position = label
-                    code[q][jj] = (int8_t)((wb >> EREC_CODE) & 3u);
-                    dz[q][jj] = (uint8_t)((wb >> EREC_DIR) & 1u);
-                }
-            }
-#pragma unroll
-        for (int q = 0; q < RUNR; ++q)
-            if (j0 + q < d) {
-                uint32_t meta = (uint32_t)(key[q] % NV);
-#pragma unroll
-                for (int jj = 0; jj < NV - 1; ++jj) {
-                    const int m = set.find(c[q][jj]);   // present by construction
-                    meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
-                    if (dz[q][jj]) {
-                        meta |= 1u << (Meta<NV>::DBIT + jj);
-                        dmask |= 1ull << m;
-                    }
-                    if (code[q][jj] == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
-                    if (code[q][jj] == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
-                }
-                R.pincm[s + j0 + q] = make_int2(key[q], (int32_t)meta);
-            }
+    uint64_t dmask;
+    if constexpr (MERGE) {
+        const int2 mm = R.rmask[k];
+        dmask = (uint64_t)(uint32_t)mm.x | ((uint64_t)(uint32_t)mm.y << 32);
+    } else {
+        dmask = meta_walk();
     }
     const uint32_t info = (uint32_t)u | ((uint32_t)diag << 8) | ((uint32_t)(R.isdp[k] ? 1 : 0) << 16);
     R.prow_info[k] = info;
@@ -943,7 +965,7 @@ int64_t nnz_bound(int64_t N, int64_t NT, int nv)
 enum {
     W_STATUS, W_TOTALS, W_PART, W_VINFO, W_INCLP, W_ISD, W_ISDP, W_OWNF, W_HIST1, W_OWNCNT, W_PI, W_PIINV,
     W_PINCPTR, W_PINC, W_PINCM, W_ELEMP, W_ROWLEN, W_PROWPTR, W_PROWINFO, W_PRECP, W_ROWREC, W_XYP, W_FP,
-    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_RSLOT, W_COUNT
+    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_RSLOT, W_RMASK, W_COUNT
 };
 
 struct Layout {
@@ -991,6 +1013,7 @@ Layout plan_layout(int64_t N, int64_t NT, int nv)
     sz[W_SORTED] = sizeof(int32_t) * (size_t)ninc;
     sz[W_PAIRS2] = sizeof(int2) * (size_t)ninc;
     sz[W_FSTART] = sizeof(int32_t) * (size_t)(Bk.nb + 1);
+    sz[W_RMASK] = nv == 4 ? sizeof(int2) * (size_t)N : 0;
     sz[W_RSLOT] = nv == 4 ? sizeof(int32_t) * (size_t)REGCAP * (size_t)N : 0;   // 3-D row slots
     Layout L{};
     size_t o = 0;
@@ -1033,6 +1056,7 @@ RowArgs row_args(fe_plan *P)
     R.prow_info = P->prow_info;
     R.precp = P->precp;
     R.rslot = P->rslot;
+    R.rmask = P->rmask;
     R.status = P->status;
     return R;
 }
@@ -1293,6 +1317,7 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     P->pairs2 = reinterpret_cast<int2 *>(base + L.off[W_PAIRS2]);
     P->fstart = reinterpret_cast<int32_t *>(base + L.off[W_FSTART]);
     P->rslot = reinterpret_cast<int4 *>(base + L.off[W_RSLOT]);
+    P->rmask = reinterpret_cast<int2 *>(base + L.off[W_RMASK]);
     P->nnz_max = nnz_bound(mesh->n_node, mesh->n_elem, nv);
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = (nv == 3) ? plan_build<3>(P, s) : plan_build<4>(P, s);
