@@ -10,17 +10,25 @@ lists, row pattern, Dirichlet set), fe_plan_pattern (rowptr/colind) and fe_assem
 Also reported on the same JSON line:
   warm         fe_assemble alone (plan reused, new kappa each call)
   kernels      every kernel of the step timed with HIP events on its launch stream
-  roofline     the kernel with the largest time per step: its algorithmic bytes
-               (each array it must read or write, once) over its mean duration
-               against the 8 TB/s HBM peak; traffic from hardware counters when the
-               committed counter summary matches the current sources
+  roofline     the kernel with the largest time per step (the dominant kernel): the
+               compulsory bytes of the assembly per element (inputs read once,
+               outputs written once: 79 B per triangle for the cold step of the
+               2049^2 mesh) times the elements one launch processes, over its mean
+               launch duration, against the 8 TB/s HBM peak; traffic (FETCH_SIZE +
+               WRITE_SIZE per launch, copy-calibrated) and its ratio to those bytes
+               when the committed counter summary matches the current sources; the
+               kernel's own implementation byte model under a separate key; and the
+               whole cold and warm steps' compulsory bytes over their wall time
   batched      256 uneven jittered meshes assembled + Jacobi-PCG solved (1e-10) by
                one graph launch, against a loop of the plain path over the same
                instances (plans built beforehand in both)
   adjoint      1025^2 mesh: forward solve + adjoint solve + gradient kernel against
                the forward solve alone
   next         assembly on the L-shaped domain, and the pure Neumann solve
-  cpu_baseline the CPU oracle (single thread) on a bounded sample of the recipe
+  cpu_baseline the CPU oracle as it stands, timed before any GPU call: single thread
+               pinned to one core, median of 3, on bounded samples of the 2-D and
+               3-D recipes, and a process pool (one oracle assemble + solve per
+               instance) over a sample of the batched workload
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload jitter2049|kuhn129]
                        [--no-cpu] [--no-batch] [--no-adjoint] [--no-next]
@@ -106,6 +114,69 @@ def read_counters(workload):
     return out
 
 
+def step_bytes(N, NT, nnz, dim, nodal):
+    """Compulsory bytes of one assembly: the inputs read once (node, elem, bdflag,
+    kappa, nodal f when used) and the outputs written once (rowptr, colind, val, b).
+    Cold step: all of them (79 B per triangle on the 2049^2 mesh, 65.8 B per
+    tetrahedron on the 129^3 cube with nodal f).  Warm step (pattern cached): without
+    rowptr and colind (63 B per triangle, 55 B per tetrahedron)."""
+    nv = dim + 1
+    inputs = 8 * dim * N + 4 * nv * NT + nv * NT + 8 * NT + (8 * N if nodal else 0)
+    cold = inputs + 4 * (N + 1) + 4 * nnz + 8 * nnz + 8 * N
+    warm = inputs + 8 * nnz + 8 * N
+    return cold, warm
+
+
+NUMERIC = ("k_scatter_coords", "k_assemble_2d", "k_assemble_3d", "k_values_to_label")
+
+
+def kernel_table(kern, steps, N, NT, nnz, dim, nodal):
+    out = {}
+    for name, k in kern.items():
+        nb = kernel_bytes(name, N, NT, nnz, dim, nodal)
+        out[name] = {"launches_per_step": k["launches"] / steps, "avg_us": k["avg_ms"] * 1e3,
+                     "us_per_step": k["total_ms"] * 1e3 / steps,
+                     "impl_GBps": (nb / (k["avg_ms"] * 1e-3) / 1e9) if nb else None}
+    return out
+
+
+def roofline(kernels, counters, N, NT, nnz, dim, nodal, cold_ms, warm_ms):
+    """Roofline of the dominant kernel (largest time per step) on the compulsory bytes
+    of the cold step, plus the traffic the counters measured and the whole steps'
+    effective fractions."""
+    cold_b, warm_b = step_bytes(N, NT, nnz, dim, nodal)
+    dom = max(kernels, key=lambda n: kernels[n]["us_per_step"])
+    us = kernels[dom]["avg_us"]
+    achieved = cold_b / (us * 1e-6) / 1e9
+    traffic = None
+    if counters and dom in counters:
+        traffic = counters[dom][0] + counters[dom][1]
+    impl = kernel_bytes(dom, N, NT, nnz, dim, nodal)
+    out = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+           "bytes_per_element": cold_b / NT, "elements_per_launch": NT, "algorithmic_bytes": cold_b,
+           "avg_us": us,
+           "traffic_ratio": (traffic / cold_b) if traffic else None,
+           "impl_model": None if impl is None else {
+               "bytes_per_launch": impl, "GBps": impl / (us * 1e-6) / 1e9,
+               "frac": impl / (us * 1e-6) / 1e9 / HBM_PEAK_GBS},
+           "cold_step": {"bytes": cold_b, "bytes_per_element": cold_b / NT, "ms": cold_ms,
+                         "effective_GBps": cold_b / (cold_ms * 1e-3) / 1e9,
+                         "frac": cold_b / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+           "warm_step": {"bytes": warm_b, "bytes_per_element": warm_b / NT, "ms": warm_ms,
+                         "effective_GBps": warm_b / (warm_ms * 1e-3) / 1e9,
+                         "frac": warm_b / (warm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+    if counters and all(n in counters for n in kernels):
+        def moved(names):
+            return sum((counters[n][0] + counters[n][1]) * kernels[n]["launches_per_step"] for n in names)
+        num = [n for n in kernels if n in NUMERIC]
+        out["cold_step"]["counter_bytes"] = moved(list(kernels))
+        out["cold_step"]["traffic_ratio"] = moved(list(kernels)) / cold_b
+        out["warm_step"]["counter_bytes"] = moved(num)
+        out["warm_step"]["traffic_ratio"] = moved(num) / warm_b
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,14 +190,23 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 3-D (129^3 Kuhn cube) assembly section")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (for counter calibration)")
+    ap.add_argument("--cpu-baseline-only", action="store_true",
+                    help="only time the CPU oracle (no GPU use) and print its JSON object")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline()), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): every figure here is a single-GPU "
               "figure, and the multi-GPU sharding is a design note, not built", file=sys.stderr)
         sys.exit(2)
+
+    # the CPU baseline runs first, in a child process started before anything touches
+    # the GPU (its pinning and its process pool stay out of this process)
+    cpu = None if args.no_cpu else cpu_baseline_child()
 
     import numpy as np
     import torch
@@ -210,45 +290,12 @@ def main():
     ms_step_prof = (time.perf_counter() - t0) / args.steps * 1e3
     kern = femhip.fe_prof_read()
     femhip.fe_prof_enable(False)
-    kernels = {}
-    for name, k in kern.items():
-        nb = kernel_bytes(name, N, NT, nnz, dim, nodal)
-        kernels[name] = {"launches_per_step": k["launches"] / args.steps, "avg_us": k["avg_ms"] * 1e3,
-                         "us_per_step": k["total_ms"] * 1e3 / args.steps,
-                         "GBps": (nb / (k["avg_ms"] * 1e-3) / 1e9) if nb else None}
-    # the roofline kernel: the largest time per step among the kernels with a byte model
-    # (the unmodelled ones are the small scan, fill and statistics kernels)
-    dom = max((n for n in kernels if kernels[n]["GBps"] is not None), key=lambda n: kernels[n]["us_per_step"])
-    dom_bytes = kernel_bytes(dom, N, NT, nnz, dim, nodal)
-    dom_us = kernels[dom]["avg_us"]
-    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    kernels = kernel_table(kern, args.steps, N, NT, nnz, dim, nodal)
     counters = read_counters(args.workload)
-    traffic = None
-    if counters and dom in counters:
-        traffic = counters[dom][0] + counters[dom][1]
-    # counter-measured bandwidth (FETCH_SIZE + WRITE_SIZE per dispatch, copy-calibrated:
-    # bytes between the L2s and the fabric, MALL hits included) over the kernel times
-    # of this run, for the numeric phase and for the whole cold step
-    rocprof = None
-    if counters and all(n in counters for n in kernels):
-        def rate(names):
-            by = sum((counters[n][0] + counters[n][1]) * kernels[n]["launches_per_step"] for n in names)
-            us = sum(kernels[n]["us_per_step"] for n in names)
-            return by / (us * 1e-6) / 1e9
-        numeric = [n for n in kernels if n in ("k_scatter_coords", "k_assemble_2d", "k_assemble_3d",
-                                               "k_values_to_label")]
-        rocprof = {"numeric_phase_GBps": rate(numeric), "cold_step_GBps": rate(list(kernels)),
-                   "peak_GBps": HBM_PEAK_GBS}
-        rocprof["numeric_phase_frac"] = rocprof["numeric_phase_GBps"] / HBM_PEAK_GBS
-        rocprof["cold_step_frac"] = rocprof["cold_step_GBps"] / HBM_PEAK_GBS
 
     # what a plain device copy reaches on this GPU (read + write bytes over its time)
     log("[bench] timing a plain device copy")
     copy = copy_rate(torch, dev, 512)
-    if rocprof:
-        rocprof["copy_GBps"] = copy["GBps"]
-        rocprof["numeric_phase_frac_of_copy"] = rocprof["numeric_phase_GBps"] / copy["GBps"]
-        rocprof["cold_step_frac_of_copy"] = rocprof["cold_step_GBps"] / copy["GBps"]
 
     # warm numeric phase: plan reused, a different kappa each call
     log("[bench] timing warm numeric phase")
@@ -267,17 +314,16 @@ def main():
     torch.cuda.synchronize()
     warm_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in wev]))
     femhip.fe_plan_destroy(plan)
-
-    # compulsory bytes of the whole assembly (inputs once, outputs once)
-    in_bytes = dim * N * 8 + (dim + 1) * NT * 4 + (dim + 1) * NT + NT * 8 + (N * 8 if nodal else 0)
-    cold_bytes = in_bytes + (N + 1) * 4 + nnz * 4 + 2 * nnz * 8 + 2 * N * 8 + N
-    warm_bytes = in_bytes - (dim + 1) * NT + 2 * nnz * 8 + 2 * N * 8 + N
+    roof = roofline(kernels, counters, N, NT, nnz, dim, nodal, ms_step, warm_ms)
+    roof["copy_kernel_GBps"] = copy["GBps"]
+    del node, elem, bd, kappa, kappa2, val, val_bc, b, b_load, isd, rowptr, colind, ws, mesh
+    torch.cuda.empty_cache()
 
     c3 = None if (args.no_c3 or args.workload == "kuhn129") else bench_c3(args)
     nxt = None if args.no_next else bench_next(args)
     batched = None if args.no_batch else bench_batched(args)
     adjoint = None if args.no_adjoint else bench_adjoint(args)
-    cpu = None if args.no_cpu else cpu_baseline(args.workload)
+    torch.cuda.synchronize()
 
     out = {
         "metric": "assembled elements/s + HBM GB/s; batched & adjoint vs plain on 1 GPU",
@@ -295,14 +341,9 @@ def main():
         "config": {"workload": args.workload, "n_node": N, "n_elem": NT, "nnz": nnz, "dim": dim,
                    "step": "cold: plan + pattern + numeric assembly with boundary conditions"},
         "phases_ms": {"plan_create": sym_ms, "pattern": pat_ms, "assemble": num_ms},
-        "effective_GBps_cold": cold_bytes / (ms_step * 1e-3) / 1e9,
-        "warm": {"ms": warm_ms, "elements_per_s": NT / (warm_ms * 1e-3),
-                 "effective_GBps": warm_bytes / (warm_ms * 1e-3) / 1e9},
+        "warm": {"ms": warm_ms, "elements_per_s": NT / (warm_ms * 1e-3)},
         "kernels": {"ms_per_step_with_events": ms_step_prof, "by_kernel": kernels},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
-                     "avg_us": dom_us},
-        "rocprof_bandwidth": rocprof,
+        "roofline": roof,
         "copy_kernel": copy,
         "c3": c3,
         "batched": batched,
@@ -361,6 +402,11 @@ def bench_batched(args):
     t_plain = time.perf_counter() - t0
     same = its == list(it)
     info = B.info()
+    # release the captured graph and every plan now, not at interpreter exit
+    for p in plans:
+        p.close()
+    B.close()
+    torch.cuda.synchronize()
     return {"workload": "256 jittered meshes, sides U{17..513}, lognormal kappa, rtol 1e-10",
             "n_inst": len(ms), "n_node": int(B.N), "n_elem": NT, "nnz": int(B.plan.nnz),
             "ms_batched": t_batch * 1e3, "ms_plain_loop": t_plain * 1e3, "speedup": t_plain / t_batch,
@@ -374,8 +420,9 @@ def bench_batched(args):
 def bench_c3(args):
     """The 3-D configuration: 129^3 Kuhn cube (12.6M tetrahedra), lognormal kappa, nodal
     f, Dirichlet on x = 0, 1 and Neumann g_N = du/dn elsewhere.  Cold step (plan +
-    pattern + numeric assembly) and warm numeric assembly, event-timed, plus the 3-D
-    numeric kernel's algorithmic rate."""
+    pattern + numeric assembly) and warm numeric assembly, event-timed, every kernel
+    of the cold step timed on its stream, and the roofline of its dominant kernel on
+    the compulsory bytes of the step."""
     import numpy as np
     import torch
     from paper_1804_05156_amd import femhip, meshgen
@@ -421,28 +468,34 @@ def bench_c3(args):
     rc = femhip.fe_plan_status(plans[-1])
     if rc != 0:
         raise RuntimeError(f"kernel status {rc}")
-    for p in plans[:-1]:
+    for p in plans:
         femhip.fe_plan_destroy(p)
-    plan = plans[-1]
+    # every kernel of the cold step on its stream
     femhip.fe_prof_enable(True)
+    for _ in range(reps):
+        femhip.fe_plan_destroy(cold())
+    torch.cuda.synchronize()
+    kern = femhip.fe_prof_read()
+    femhip.fe_prof_enable(False)
+    kernels = kernel_table(kern, reps, N, NT, nnz, 3, True)
+    # warm numeric assembly
+    plan = cold()
+    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
         femhip.fe_assemble(plan, node, kappa, f, None, gn, val, val_bc, b, b_load, isd)
     e1.record(stream)
     e1.synchronize()
-    kern = femhip.fe_prof_read()
-    femhip.fe_prof_enable(False)
     femhip.fe_plan_destroy(plan)
     warm_ms = e0.elapsed_time(e1) / reps
-    k3 = kern.get("k_assemble_3d")
-    k3_us = k3["avg_ms"] * 1e3 if k3 else None
-    k3_bytes = kernel_bytes("k_assemble_3d", N, NT, nnz, 3, True)
+    roof = roofline(kernels, read_counters("kuhn129"), N, NT, nnz, 3, True, cold_ms, warm_ms)
+    k3 = kernels.get("k_assemble_3d")
     return {"workload": "kuhn129: 129^3 Kuhn cube, lognormal kappa, nodal f, Dirichlet x = 0, 1, Neumann elsewhere",
             "n_node": N, "n_elem": NT, "nnz": nnz, "cold_ms": cold_ms, "cold_elements_per_s": NT / (cold_ms * 1e-3),
             "warm_ms": warm_ms, "warm_elements_per_s": NT / (warm_ms * 1e-3),
-            "k_assemble_3d_us": k3_us,
-            "k_assemble_3d_GBps": (k3_bytes / (k3_us * 1e-6) / 1e9) if k3_us else None}
+            "k_assemble_3d_us": k3["avg_us"] if k3 else None,
+            "kernels": kernels, "roofline": roof}
 
 
 def bench_next(args):
@@ -555,6 +608,7 @@ def bench_adjoint(args):
     _, iters, _ = plan.solve(asm, rtol=rtol)
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
+    plan.close()
     return {"workload": "1025^2 jittered mesh, lognormal kappa, u_obs from a second kappa, rtol 1e-10",
             "forward_pcg_iterations": int(iters), "us_per_pcg_iteration": t_s / max(int(iters), 1) * 1e6,
             "ms_forward": t_f * 1e3, "ms_forward_adjoint_grad": t_fb * 1e3, "ratio": t_fb / t_f,
@@ -594,28 +648,88 @@ def copy_calibration(mb):
     print(json.dumps({"copy_bytes_per_launch": n * 8, "launches": 5}), flush=True)
 
 
-def cpu_baseline(workload):
-    """The oracle, single-threaded, on a bounded sample of the same recipe."""
+def _median_time(fn, reps=3):
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    return sorted(ts)[len(ts) // 2], ts
+
+
+def _pool_instance(args):
+    """One instance of the batched workload on the CPU: oracle assembly and solve."""
+    import oracle
+    from paper_1804_05156_amd import meshgen
+    k, side = args
+    m = meshgen.square_mesh(int(side), jitter=0.2, seed=4000 + k, kappa="lognormal")
+    t = time.perf_counter()
+    a = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=oracle.Fn(oracle.FN_SINPROD, (2 * math.pi ** 2,)))
+    _, it, _ = oracle.solve(a, rtol=1e-10)
+    return m.n_elem, it, time.perf_counter() - t
+
+
+def cpu_baseline_child():
+    """cpu_baseline() in a child interpreter (this process has not used the GPU yet)."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only"], capture_output=True,
+                       text=True)
+    sys.stderr.write(r.stderr)
+    if r.returncode != 0:
+        raise RuntimeError(f"CPU baseline failed with status {r.returncode}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_baseline():
+    """The oracle as it stands (plain single-threaded C), on the host, before any GPU
+    call.  Single-thread legs are pinned to one core and take the median of 3 runs:
+    the 2-D recipe (jittered, permuted, lognormal kappa, analytic f) at 1025^2 and the
+    3-D recipe (Kuhn cube, lognormal kappa, nodal f, Dirichlet/Neumann) at 65^3.  The
+    batched leg runs one process per instance on a 16-instance sample of the batch
+    (every 16th instance of the 256), oracle assembly + solve to 1e-10 each."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
     import numpy as np
     import oracle
     from paper_1804_05156_amd import meshgen
-    if workload == "jitter2049":
+    oracle.lib()
+    allowed = sorted(os.sched_getaffinity(0))
+    out = {"kind": "oracle", "unit": "elements/s", "cores": 1, "cpu": _cpu_model(), "host_threads": len(allowed)}
+    log(f"[bench] cpu baseline: pinned to core {allowed[0]} of {len(allowed)}")
+    os.sched_setaffinity(0, {allowed[0]})
+    try:
         m = meshgen.square_mesh(1025, jitter=0.2, permute=True, seed=2, kappa="lognormal")
         f = oracle.Fn(oracle.FN_SINPROD, (2 * math.pi ** 2,))
-        gn = None
-        sample = "1025^2 jittered permuted mesh, same recipe (2,097,152 triangles), one oracle assembly"
-    else:
-        m = meshgen.kuhn_cube(49, seed=3, kappa="lognormal")
+        med, ts = _median_time(lambda: oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=f))
+        out.update({"value": m.n_elem / med, "seconds_median": med, "seconds": ts,
+                    "sample": "2-D recipe of the 2049^2 workload at 1025^2 (jittered, permuted, lognormal kappa, "
+                              "analytic f, Dirichlet): 2,097,152 triangles, one oracle assembly, median of 3"})
+        m = meshgen.kuhn_cube(65, seed=3, kappa="lognormal")
         u = np.prod(np.sin(math.pi * m.node), axis=0)
         f = oracle.Fn(oracle.FN_NODAL, (0,), 3 * math.pi ** 2 * u)
         gn = oracle.Fn(oracle.FN_DUDN_SINPROD, (1.0,))
-        sample = "49^3 Kuhn cube, same recipe, one oracle assembly"
-    log(f"[bench] cpu baseline: {sample}")
+        med, ts = _median_time(lambda: oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=f, gN=gn))
+        out["c3"] = {"value": m.n_elem / med, "unit": "elements/s", "cores": 1, "seconds_median": med,
+                     "seconds": ts, "sample": f"3-D recipe of the 129^3 workload at 65^3: {m.n_elem} tetrahedra, "
+                                               "one oracle assembly, median of 3"}
+    finally:
+        os.sched_setaffinity(0, set(allowed))
+    sizes = meshgen.batch_sizes()
+    sample = [(k, int(sizes[k])) for k in range(0, len(sizes), 16)]
+    workers = min(16, len(allowed), len(sample))
+    log(f"[bench] cpu baseline: batched sample of {len(sample)} instances on {workers} processes")
     t = time.perf_counter()
-    oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=f, gN=gn)
-    dt = time.perf_counter() - t
-    return {"value": m.n_elem / dt, "unit": "elements/s", "cores": 1, "kind": "oracle", "sample": sample,
-            "seconds": dt, "cpu": _cpu_model()}
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        res = list(ex.map(_pool_instance, sample))
+    wall = time.perf_counter() - t
+    nel = sum(r[0] for r in res)
+    out["c4_pool"] = {"value": nel / wall, "unit": "elements/s (assembly + solve)", "cores": workers,
+                      "instances_per_s": len(sample) / wall, "seconds": wall,
+                      "iterations_max": max(r[1] for r in res),
+                      "sample": f"{len(sample)} instances of the 256-mesh batch (every 16th; sides "
+                                f"{min(s for _, s in sample)}..{max(s for _, s in sample)}), one process per "
+                                "instance, oracle assembly + solve to rtol 1e-10"}
+    return out
 
 
 def _cpu_model():

@@ -337,7 +337,8 @@ typedef struct fe_prof_entry {
     double total_ms, min_ms, max_ms;  /* per launch, from HIP events on the launch stream */
 } fe_prof_entry;
 
-/* Enable (on != 0) or disable timing and drop the records kept so far.  While
+/* Enable (on != 0) or disable timing and drop the records kept so far (disabling
+ * also destroys the timer's HIP events, so none outlives its use).  While
  * enabled, each launch of the library's kernels is bracketed by two HIP events
  * recorded on its stream (launches into a capturing stream are skipped).  Process
  * wide; do not call it while another thread launches library work. */

@@ -66,10 +66,18 @@ class Batch:
     def info(self) -> dict:
         return femhip.fe_batch_get_info(self.handle)
 
-    def __del__(self):
+    def close(self):
+        """Release the batch (its captured graph) and the union plan now, rather than
+        when the interpreter collects them."""
         if getattr(self, "handle", None) is not None and femhip is not None and femhip._lib is not None:
             femhip._lib.fe_batch_destroy(self.handle)
             self.handle = None
+        plan = getattr(self, "plan", None)
+        if plan is not None:
+            plan.close()
+
+    def __del__(self):
+        self.close()
 
 
 def _time_call(fn, reps: int) -> float:

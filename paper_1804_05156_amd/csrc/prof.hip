@@ -3,7 +3,8 @@
 // When enabled, every instrumented launch is bracketed by two events recorded on
 // its own stream; fe_prof_read synchronizes them and aggregates elapsed times by
 // kernel name.  Launches made while the stream is being captured into a graph are
-// not timed.  Off by default: a disabled timer costs one branch per launch.
+// not timed.  Off by default: a disabled timer costs one branch per launch, and
+// switching it off destroys its events.
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -44,6 +45,15 @@ void recycle_all()
     g_recs.clear();
 }
 
+// Destroy every pooled event (timing switched off: nothing of the timer stays
+// alive in the runtime until process exit).
+void release_pool()
+{
+    for (hipEvent_t e : g_pool) (void)hipEventDestroy(e);
+    g_pool.clear();
+    g_pool.shrink_to_fit();
+}
+
 }  // namespace
 
 int fe_prof_begin(const char *name, hipStream_t s)
@@ -76,6 +86,7 @@ extern "C" int fe_prof_enable(int on)
         if (r.closed) (void)hipEventSynchronize(r.b);
     recycle_all();
     g_on = on != 0;
+    if (!g_on) release_pool();
     return FE_OK;
 }
 

@@ -471,10 +471,14 @@ class Plan:
         fe_grad(self.handle, self.node if node is None else node, u, lam, g, stream)
         return g
 
-    def __del__(self):
+    def close(self):
+        """Release the host-side plan object now (the workspace is a tensor of this object)."""
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.fe_plan_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        self.close()
 
 
 def solve(rowptr, colind, val, b, u0, rtol=1e-10, maxit=100000, stream=None):
@@ -497,6 +501,9 @@ class PoissonSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, kappa, plan: Plan, f=None, gD=None, gN=None, rtol=1e-12):
         asm = plan.assemble(kappa.detach().contiguous(), f, gD, gN)
+        # a kappa that is not positive and finite, or a degenerate element, is found by
+        # the numeric kernel; report it here rather than solve a meaningless system
+        plan.check()
         u, it, rel = plan.solve(asm, rtol=rtol)
         ctx.plan = plan
         ctx.asm = asm

@@ -106,3 +106,26 @@ def test_homogeneity_identity_full_size():
     rhs = -float(torch.dot(u.detach() - u_obs, u.detach()))
     log(f"  lhs {lhs:.12e} rhs {rhs:.12e}")
     assert abs(lhs - rhs) <= 1e-6 * abs(rhs)
+
+
+def test_autograd_rejects_bad_kappa():
+    """A coefficient that is not positive (say after an optimizer step) is reported by
+    the forward pass through the plan status, not turned into a meaningless gradient."""
+    from paper_1804_05156_amd import femhip
+    log("case: autograd with a non-positive kappa")
+    m, _ = _fd_problem()
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    f = femhip.Fn(femhip.FE_FN_SINPROD, (2 * math.pi ** 2,))
+    k = kap.clone()
+    k[11] = -0.5
+    with pytest.raises(femhip.FemhipError) as e:
+        femhip.PoissonSolve.apply(k.requires_grad_(True), plan, f, None, None, 1e-12)
+    assert e.value.code == femhip.FE_EINVAL
+    k = kap.clone()
+    k[3] = float("nan")
+    with pytest.raises(femhip.FemhipError) as e:
+        femhip.PoissonSolve.apply(k, plan, f, None, None, 1e-12)
+    assert e.value.code == femhip.FE_EINVAL
+    u = femhip.PoissonSolve.apply(kap, plan, f, None, None, 1e-12)   # the status was cleared
+    assert torch.isfinite(u).all()

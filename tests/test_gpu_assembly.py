@@ -333,31 +333,6 @@ def _sampled_full_size(m, specs, nsample=64, seed=0):
     return plan, asm, g
 
 
-def test_full_size_jittered_2049_sampled():
-    """The 2049^2 permuted jittered mesh at full size: sampled rows against the
-    oracle on their two-ring submesh, plus properties that hold at any size."""
-    log("case: 2049^2 jittered permuted, full size")
-    m = meshgen.workload("jitter2049")
-    plan, asm, g = _sampled_full_size(m, [(FE_FN_SINPROD, (TWO_PI2,))])
-    N, NT = m.n_node, m.n_elem
-    assert plan.nnz == 3 * N + 2 * NT - 2
-    # zero row sums of A (gradients sum to zero) and symmetry of the pattern/values
-    rows = torch.repeat_interleave(torch.arange(N, device="cuda"), (plan.rowptr[1:] - plan.rowptr[:-1]).long())
-    val = asm.val[:plan.nnz]
-    col = plan.colind[:plan.nnz].long()
-    diag = torch.zeros(N, dtype=torch.float64, device="cuda")
-    on = col == rows
-    diag[rows[on]] = val[on]
-    rs = torch.zeros(N, dtype=torch.float64, device="cuda").index_add_(0, rows, val)
-    assert torch.all(rs.abs() <= 1e-13 * diag)
-    key = rows * N + col
-    tkey = col * N + rows
-    order = torch.argsort(tkey)
-    assert torch.equal(tkey[order], key)
-    scale = torch.sqrt(diag[rows] * diag[col])
-    assert torch.all((val[order] - val).abs() <= 1e-13 * scale)
-
-
 def test_element_prefix_sum_beyond_tile_limit_sampled():
     """A 2898^2 grid with scattered labels has 16,785,218 > 4096^2 triangles, so the
     prefix sum of first incidences per element (general path) takes its three-launch
@@ -380,14 +355,3 @@ def test_element_prefix_sum_beyond_tile_limit_sampled():
     plan, asm, g = _sampled_full_size(m, [(FE_FN_CONST, (1.0,))], nsample=32)
     assert not plan.info["sort_runs"]
     assert plan.nnz == 3 * N + 2 * m.n_elem - 2
-
-
-def test_full_size_kuhn129_sampled():
-    log("case: 129^3 Kuhn, full size")
-    m = meshgen.workload("kuhn129")
-    u = np.prod(np.sin(math.pi * m.node), axis=0)
-    specs = [(FE_FN_NODAL, (0,), 3 * math.pi ** 2 * u), None, (FE_FN_DUDN_SINPROD, (1.0,))]
-    plan, asm, g = _sampled_full_size(m, specs)
-    n = 129
-    E = 3 * n * n * (n - 1) + 3 * n * (n - 1) ** 2 + (n - 1) ** 3
-    assert plan.nnz == n ** 3 + 2 * E

@@ -161,8 +161,8 @@ def test_batch_edge_cases():
 def test_full_size_batch_sampled():
     """The 256-instance batch (grid sides uniform in [17, 513], jittered,
     lognormal kappa, rtol 1e-10) in the launch configuration of the benchmark: every
-    instance converges; sampled instances equal the plain path bit for bit, the
-    smallest ones also satisfy the oracle residual bound."""
+    instance converges; sampled instances (the two smallest, the median and the
+    largest) equal the plain path bit for bit and satisfy the oracle residual bound."""
     log("case: 256-instance batch (full size), sampled instances")
     sizes = meshgen.batch_sizes()
     ms = meshgen.batch_meshes(sizes)
@@ -176,7 +176,7 @@ def test_full_size_batch_sampled():
     sample = [int(order[0]), int(order[1]), int(order[len(order) // 2]), int(order[-1])]
     for k in sample:
         log(f"  instance {k}: side {sizes[k]}, iterations {it[k]}")
-        _check_instance(B, k, ms[k], u, it, rel, f, None, 1e-10, fo, None, oracle_check=sizes[k] <= 128)
+        _check_instance(B, k, ms[k], u, it, rel, f, None, 1e-10, fo, None)
 
 
 def test_both_plain_solve_forms_match_batched():

@@ -266,3 +266,54 @@ def test_kernel_timing_api():
     assert all(r["launches"] == 1 and r["total_ms"] > 0 for r in rec.values())
     plan.assemble(kap, out=asm)
     assert femhip.fe_prof_read() == {}
+
+
+@pytest.mark.parametrize("permute", [False, True])
+@pytest.mark.parametrize("case", ["robin", "nodal", "centroid", "trapezoid"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_both_processing_orders_parity(dim, case, permute):
+    """Robin sides, nodal data and the load rules of Section 4 through both processing
+    orders, against the oracle.  Labels that follow the element order (permute False)
+    take label-order processing: rows written in place and, in 3-D, the stored
+    column sets in the numeric kernel; a random relabelling takes the processing-
+    order rows and the label-order copies.  The plan reports which (sort_runs 1 / 0);
+    the sizes make the choice certain (at least 9 buckets, so random labels rarely
+    repeat a neighbour's bucket)."""
+    from paper_1804_05156_amd import femhip
+    log(f"case: both orders, dim {dim}, {case}, permute {permute}")
+    if dim == 2:
+        m = meshgen.square_mesh(65, jitter=0.2, permute=permute, seed=500 + len(case), kappa="lognormal",
+                                sides=(1, 3, 2, 3))
+        lin = (FE_FN_LINEAR, (0.3, 1.1, -0.7))
+        lin2 = (FE_FN_LINEAR, (0.2, -0.5, 0.4))
+        fa = (FE_FN_SINPROD, (2 * math.pi ** 2,))
+    else:
+        m = meshgen.kuhn_cube(17, jitter=0.15, permute=permute, seed=600 + len(case), kappa="lognormal",
+                              faces=(1, 3, 2, 3, 2, 1))
+        lin = (FE_FN_LINEAR, (0.3, 1.1, -0.7, 0.4))
+        lin2 = (FE_FN_LINEAR, (0.5, 0.2, 0.1, -0.3))
+        fa = (FE_FN_SINPROD, (3 * math.pi ** 2,))
+    rng = np.random.default_rng(700 + dim)
+    rule, alpha = 0, 1.3
+    if case == "robin":
+        specs, gr = [fa, lin, (FE_FN_DUDN_SINPROD, (1.0,))], (FE_FN_DUDN_SINPROD, (0.7,))
+    elif case == "nodal":
+        nodal = [rng.standard_normal(m.n_node) for _ in range(4)]
+        specs = [(FE_FN_NODAL, (0.0,), nodal[k]) for k in range(3)]
+        gr, alpha = (FE_FN_NODAL, (0.0,), nodal[3]), 0.7
+    elif case == "centroid":
+        specs, gr, rule = [fa, lin, (FE_FN_CONST, (0.9,))], lin2, 1
+    else:
+        fnod = (FE_FN_NODAL, (0.0,), np.cos(math.pi * m.node).prod(axis=0) + 0.5)
+        specs, gr, rule = [fnod, lin, (FE_FN_DUDN_SINPROD, (1.0,))], lin2, 2
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    (grf, gro), _, _ = fns(gr)
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    assert plan.info["sort_runs"] == (0 if permute else 1)
+    asm = plan.assemble(kap, f, gd, gn, gR=grf, robin_alpha=alpha, load_rule=rule)
+    plan.check()
+    torch.cuda.synchronize()
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno, gR=gro, alpha=alpha, rule=rule)
+    worst = compare(host(plan, asm), ora, data=data_scale(m, specs, gr))
+    log(f"  sort_runs {plan.info['sort_runs']}, worst scaled value error {worst:.2e}")
