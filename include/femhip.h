@@ -217,6 +217,21 @@ int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const doub
              const double *b, double *u, double rtol, int32_t maxit, void *ws, size_t ws_bytes,
              int32_t *iters, double *relres, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): fe_solve without a workspace
+ * argument.  Its workspace is a fixed 64 MiB device array inside the library, one
+ * per GPU, held until the process ends; its device address is looked up on the
+ * first call on each device.  The call allocates nothing (no hipMalloc, no
+ * allocating library routine).  Arguments, stopping rule, results (bit for bit),
+ * synchronization and errors are those of fe_solve, plus FE_ELIMIT for n above
+ * FE_SOLVE_NOALLOC_MAX_N.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (two streams or two host threads) race and must
+ * be serialized by the caller. */
+#define FE_SOLVE_NOALLOC_MAX_N 1310720
+int fe_solve_noalloc(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                     const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+                     double *relres, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Pure Neumann problem (Section 3.3, equations (compatible) and (meanb)).
  * ------------------------------------------------------------------------- */

@@ -18,6 +18,8 @@
 // inside the row kernels (one per workgroup would serialize on the L2s).
 // Scalars live in device memory; the host launches iterations in chunks and reads
 // the "done" flag once per chunk, kernels after convergence return at once.
+#include <mutex>
+
 #include "cg_common.h"
 
 namespace {
@@ -327,17 +329,11 @@ extern "C" int fe_solve_workspace_bytes(int64_t n, size_t *bytes)
     return FE_OK;
 }
 
-extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, const double *b,
-                        double *u, double rtol, int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters,
-                        double *relres, void *stream)
+// The iteration itself, on a workspace already laid out by ws_layout.
+static int solve_run(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, const double *b,
+                     double *u, double rtol, int32_t maxit, const SolveWs &W, int32_t *iters, double *relres,
+                     hipStream_t s)
 {
-    if (n <= 0 || n >= INT32_MAX || maxit < 0 || !(rtol >= 0.0)) return FE_EINVAL;
-    if (!rowptr || !colind || !val || !b || !u || !ws || !iters || !relres) return FE_EINVAL;
-    if ((uintptr_t)ws & 255) return FE_EINVAL;
-    SolveWs W;
-    const size_t need = ws_layout(n, &W, static_cast<char *>(ws));
-    if (ws_bytes < need) return FE_ESIZE;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const int32_t nn = (int32_t)n;
     const unsigned nb = (unsigned)cdiv(n, SB);
     int rc;
@@ -408,4 +404,76 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
     *iters = fl[F_ITER];
     *relres = sqrt(sc[S_RR] / sc[S_BB]);
     return fl[F_DONE] ? FE_OK : FE_ENOCONV;
+}
+
+static bool solve_args_ok(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                          const double *b, double *u, double rtol, int32_t maxit, int32_t *iters, double *relres)
+{
+    if (n <= 0 || n >= INT32_MAX || maxit < 0 || !(rtol >= 0.0)) return false;
+    return rowptr && colind && val && b && u && iters && relres;
+}
+
+extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, const double *b,
+                        double *u, double rtol, int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters,
+                        double *relres, void *stream)
+{
+    if (!solve_args_ok(n, rowptr, colind, val, b, u, rtol, maxit, iters, relres) || !ws) return FE_EINVAL;
+    if ((uintptr_t)ws & 255) return FE_EINVAL;
+    SolveWs W;
+    const size_t need = ws_layout(n, &W, static_cast<char *>(ws));
+    if (ws_bytes < need) return FE_ESIZE;
+    return solve_run(n, rowptr, colind, val, b, u, rtol, maxit, W, iters, relres, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace is a fixed device array of this file.
+//
+// The array's name is only a host-side stand-in for it; its device address is
+// looked up with hipGetSymbolAddress, once per device (with that device current),
+// and only that address is handed to kernels.  Every call on one device reuses
+// that device's array: the flags are cleared by a fill kernel at the start of each
+// solve, and every other vector and partial is written before it is read, so
+// nothing of an earlier call leaks into a later one.  Calls that overlap on one
+// device (two streams or two host threads) race on the array.
+// ---------------------------------------------------------------------------
+static_assert(FE_SOLVE_NOALLOC_MAX_N < INT32_MAX, "row limit");
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES];   // device address of `scratch` per device, once looked up
+}  // namespace
+
+// Device address of this device's array, looked up on its first use.
+static int scratch_ptr(void **out)
+{
+    int dev = -1;
+    FE_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return FE_ELIMIT;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        FE_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return FE_EHIP;
+        scratch_dev[dev] = p;
+    }
+    *out = scratch_dev[dev];
+    return FE_OK;
+}
+
+extern "C" int fe_solve_noalloc(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
+                                const double *b, double *u, double rtol, int32_t maxit, int32_t *iters,
+                                double *relres, void *stream)
+{
+    if (!solve_args_ok(n, rowptr, colind, val, b, u, rtol, maxit, iters, relres)) return FE_EINVAL;
+    if (n > FE_SOLVE_NOALLOC_MAX_N || ws_layout(n, nullptr, nullptr) > NOALLOC_BYTES) return FE_ELIMIT;
+    void *base = nullptr;
+    int rc = scratch_ptr(&base);
+    if (rc) return rc;
+    SolveWs W;
+    ws_layout(n, &W, static_cast<char *>(base));
+    return solve_run(n, rowptr, colind, val, b, u, rtol, maxit, W, iters, relres, static_cast<hipStream_t>(stream));
 }

@@ -27,7 +27,7 @@ ENTRY_POINTS = (
     "fe_version", "fe_status_string", "fe_plan_workspace_bytes", "fe_plan_create", "fe_plan_pattern",
     "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_assemble_robin",
     "fe_assemble_quad", "fe_spmv",
-    "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_neumann_workspace_bytes", "fe_neumann_solve",
+    "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_solve_noalloc", "fe_neumann_workspace_bytes", "fe_neumann_solve",
     "fe_grad", "fe_batch_solve_workspace_bytes",
     "fe_batch_solve", "fe_batch_create", "fe_batch_set_grid", "fe_batch_get_info", "fe_batch_assemble_solve",
     "fe_batch_destroy", "fe_prof_enable", "fe_prof_read",
@@ -91,6 +91,7 @@ def _load():
         "fe_spmv": ([I64, P, P, P, P, P, P], C.c_int),
         "fe_solve_workspace_bytes": ([I64, C.POINTER(SZ)], C.c_int),
         "fe_solve": ([I64, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), P], C.c_int),
+        "fe_solve_noalloc": ([I64, P, P, P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P], C.c_int),
         "fe_grad": ([P, P, P, P, P, P], C.c_int),
         "fe_neumann_workspace_bytes": ([P, I64, C.POINTER(SZ)], C.c_int),
         "fe_neumann_solve": ([P, P, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), C.POINTER(D), P],
@@ -268,6 +269,21 @@ def fe_solve(rowptr, colind, val, b, u, rtol: float, maxit: int, ws, stream=None
     if rc == FE_ENOCONV and allow_noconv:
         return int(it.value), float(rel.value), rc
     _check(rc, "fe_solve")
+    return int(it.value), float(rel.value), rc
+
+
+FE_SOLVE_NOALLOC_MAX_N = 1310720
+
+
+def fe_solve_noalloc(rowptr, colind, val, b, u, rtol: float, maxit: int, stream=None, allow_noconv=False):
+    it = C.c_int32()
+    rel = C.c_double()
+    rc = _lib.fe_solve_noalloc(rowptr.numel() - 1, _ptr(rowptr, torch.int32), _ptr(colind, torch.int32),
+                               _ptr(val, torch.float64), _ptr(b, torch.float64), _ptr(u, torch.float64),
+                               float(rtol), int(maxit), C.byref(it), C.byref(rel), _stream(stream))
+    if rc == FE_ENOCONV and allow_noconv:
+        return int(it.value), float(rel.value), rc
+    _check(rc, "fe_solve_noalloc")
     return int(it.value), float(rel.value), rc
 
 

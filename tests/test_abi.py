@@ -80,5 +80,10 @@ def test_argument_errors_before_any_device_call(femhip):
     assert lib.fe_spmv(-1, None, None, None, None, None, None) == femhip.FE_EINVAL
     it, rel = C.c_int32(), C.c_double()
     assert lib.fe_solve(0, None, None, None, None, None, 1e-8, 10, None, 0, C.byref(it), C.byref(rel), None) == femhip.FE_EINVAL
+    # the allocation-free solve: missing arguments, and more rows than its fixed array
+    assert lib.fe_solve_noalloc(10, None, None, None, None, None, 1e-8, 10, C.byref(it), C.byref(rel), None) == femhip.FE_EINVAL
+    fake = [C.c_void_p(0x1000 * (k + 1)) for k in range(5)]
+    assert lib.fe_solve_noalloc(femhip.FE_SOLVE_NOALLOC_MAX_N + 1, *fake, 1e-8, 10, C.byref(it), C.byref(rel),
+                                None) == femhip.FE_ELIMIT
     assert lib.fe_plan_status(None, None) == femhip.FE_EINVAL
     assert lib.fe_plan_destroy(None) == femhip.FE_OK
