@@ -98,6 +98,8 @@ typedef struct fe_plan_info {
                                runs of equal buckets in neighbouring elements): the sort aggregates
                                its counter updates per wavefront and rows are processed in label
                                order; else 0 (a choice of kernels; results do not depend on it) */
+    int32_t n_long;         /* rows with more than 32 (2-D) / 64 (3-D) stored entries, which take
+                               the long-row kernels (one workgroup per row) */
 } fe_plan_info;
 
 /* Library version string (host, static). */
@@ -124,8 +126,9 @@ int fe_plan_workspace_bytes(const fe_mesh *mesh, size_t *bytes);
  * Errors: FE_EINVAL (NULL, sizes, vertex index out of range, bdflag code not in
  * 0..3), FE_EUNSUPPORTED (dim), FE_EMESH (repeated vertex in an
  * element), FE_EOVERFLOW, FE_ESIZE, FE_EHIP, and FE_ELIMIT when the mesh exceeds
- * the fixed capacities: more than 2^26 vertices, or a vertex with more than 32
- * (2D) or 64 (3D) distinct neighbours, itself included. */
+ * a capacity: more than 2^29 vertices in use by elements, or a vertex in more than
+ * 4095 (2-D) / 2730 (3-D) elements (a row's candidate columns, dim per incident
+ * element plus the vertex itself, must fit 8192 LDS slots). */
 int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe_plan **plan, int64_t *nnz,
                    void *stream);
 

@@ -46,6 +46,11 @@ struct AsmArgs {
     // 3-D label-order processing with the register column set: each row's sorted
     // columns (processing positions), 16 per row, padded (the row passes' slots)
     const int32_t *rcols;
+    // long rows (INFO_LONG), done by k_assemble_long: their processing positions, the
+    // mesh's element array (labels), the label-order row pointer, the label-order
+    // Dirichlet flags
+    const int32_t *longk, *elem, *lrowptr;
+    const uint8_t *isdl;
     double *val, *val_bc, *b, *b_load;
     uint8_t *isd;
     int32_t *status;
@@ -145,12 +150,14 @@ __global__ __launch_bounds__(256) void k_values_to_label(int32_t N, const int32_
     int4 rec = make_int4(0, 0, 0, 0);
     if (i < N) {
         rec = rowrec[i];
-        rec.x += 2 * piinv[i];                         // start of the row in valp
-        const int len = rec.y & 0xff;
-        const double bi = valp[rec.x + len], bl = b_load ? valp[rec.x + len + 1] : 0.0;
-        b[i] = bi;
-        if (b_load) b_load[i] = bl;
-        if (isd) isd[i] = (uint8_t)((rec.y >> 16) & 1);
+        if (!(rec.y & INFO_LONG)) {   // (a long row's outputs come from k_assemble_long)
+            rec.x += 2 * piinv[i];                     // start of the row in valp
+            const int len = rec.y & 0xff;
+            const double bi = valp[rec.x + len], bl = b_load ? valp[rec.x + len + 1] : 0.0;
+            b[i] = bi;
+            if (b_load) b_load[i] = bl;
+            if (isd) isd[i] = (uint8_t)((rec.y >> 16) & 1);
+        }
     }
     srec[w][lane] = rec;
     __syncthreads();
@@ -161,6 +168,7 @@ __global__ __launch_bounds__(256) void k_values_to_label(int32_t N, const int32_
     for (int32_t e0 = lane; e0 < total; e0 += 64 * CU) {
         double v[CU];
         int row[CU], col[CU];
+        bool lng[CU];
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
             const int32_t e = e0 + 64 * u;
@@ -174,12 +182,14 @@ __global__ __launch_bounds__(256) void k_values_to_label(int32_t N, const int32_
             }
             row[u] = lo;
             col[u] = pos - sdst[w][lo];
-            v[u] = valp[srec[w][lo].x + col[u]];
+            lng[u] = (srec[w][lo].y & INFO_LONG) != 0;
+            v[u] = lng[u] ? 0.0 : valp[srec[w][lo].x + col[u]];
         }
 #pragma unroll
         for (int u = 0; u < CU; ++u) {
             const int32_t e = e0 + 64 * u;
             if (e >= total) break;
+            if (lng[u]) continue;
             const int32_t pos = base + e;
             val[pos] = v[u];
             if (val_bc) {
@@ -214,6 +224,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
     if (k >= A.N) return;
     const int32_t s = A.pincptr[k], e = A.pincptr[k + 1];
     const uint32_t info = A.prow_info[k];
+    if (info & INFO_LONG) return;   // k_assemble_long
     const int len = info & 0xff, diag = (info >> 8) & 0xff;
     const bool rowd = (info >> 16) & 1;
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
@@ -447,6 +458,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     if (k >= A.N) return;
     const int32_t s = A.pincptr[k], e = A.pincptr[k + 1];
     const uint32_t info = A.prow_info[k];
+    if (info & INFO_LONG) return;   // k_assemble_long
     const int len = info & 0xff, diag = (info >> 8) & 0xff;
     const bool rowd = (info >> 16) & 1;
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
@@ -698,6 +710,330 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
 }
 
+// ----------------------------------------------------------------------------- long rows
+// Rows with more columns than the accumulators of the kernels above hold (INFO_LONG;
+// a vertex with more than 31 / 63 neighbours): one workgroup per row.  The row's
+// column set (labels, ascending) is formed again in LDS from its incidences, as the
+// plan formed it.  Each chunk of LNB incidences is computed in parallel, one
+// incidence per thread, with the same local matrix, load and side terms as above;
+// thread 0 then adds the chunk's contributions in incidence (ascending element)
+// order, so the sums have a fixed order.  The row goes straight to the label-order
+// outputs.
+constexpr int LNB = 256;
+
+FE_DEV int lower_bound_i32(const int32_t *a, int n, int32_t x)
+{
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int NV>
+__global__ __launch_bounds__(LNB) void k_assemble_long(AsmArgs A)
+{
+    constexpr int DIM = NV - 1;
+    __shared__ int32_t cols[LCAND];
+    __shared__ double acc[LCAND];
+    __shared__ double cv[LNB][NV];       // chunk: contributions to the diagonal and the other columns
+    __shared__ int32_t co[LNB][NV - 1];  // chunk: column offsets of the other vertices
+    __shared__ double cb[LNB][2];        // chunk: contributions to b_load and to the lifting
+    __shared__ int32_t sl[2 * (LNB / 64)];
+    const int tid = threadIdx.x;
+    const int32_t k = A.longk[blockIdx.x];
+    const int32_t s = A.pincptr[k], d = A.pincptr[k + 1] - s;
+    const int4 rec = A.precp[k];   // (start, info, length, diagonal offset)
+    const int len = rec.z, diag = rec.w;
+    const bool rowd = (rec.y >> 16) & 1;
+    const int32_t i = A.pi[k];
+    const int32_t nc = DIM * d + 1;
+    if (nc > LCAND || len > nc) {
+        if (tid == 0) atomicOr(A.status + ST_ERR, ERR_LIMIT);
+        return;
+    }
+    // the column set: the other vertices of every incident element and i, sorted, unique
+    int32_t M = 1;
+    while (M < nc) M <<= 1;
+    for (int32_t j = tid; j < d; j += LNB) {
+        const int32_t key = A.pincm[s + j].x;
+        const int32_t t = key / NV;
+        const int a = key - t * NV;
+#pragma unroll
+        for (int jj = 0; jj < NV - 1; ++jj) cols[DIM * j + jj] = A.elem[(int64_t)fe_other<NV>(a, jj) * A.NT + t];
+    }
+    for (int32_t j = DIM * d + tid; j < M; j += LNB) cols[j] = (j == DIM * d) ? i : INT32_MAX;
+    __syncthreads();
+    for (int32_t kk = 2; kk <= M; kk <<= 1)
+        for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+            for (int32_t x = tid; x < M; x += LNB) {
+                const int32_t l = x ^ jj;
+                if (l > x) {
+                    const int32_t p = cols[x], q = cols[l];
+                    if (((x & kk) == 0) ? p > q : p < q) {
+                        cols[x] = q;
+                        cols[l] = p;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    int32_t u = 0;
+    for (int32_t x0 = 0; x0 < M; x0 += LNB) {
+        const int32_t x = x0 + tid;
+        const int32_t c = x < M ? cols[x] : INT32_MAX;
+        const bool first = c != INT32_MAX && (x == 0 || cols[x - 1] != c);
+        int32_t tot;
+        const int32_t ex = block_exclusive_i32<LNB>(first ? 1 : 0, sl, &tot);   // (reads before its barriers)
+        if (first) cols[u + ex] = c;                                          // compaction: u + ex <= x
+        u += tot;
+        __syncthreads();
+    }
+    for (int c = tid; c < len; c += LNB) acc[c] = 0.0;
+    // the row's own coordinates (and nodal f)
+    double Y0[DIM], fi = 0.0;
+    if (DIM == 2) {
+        const double2 q = reinterpret_cast<const double2 *>(A.xyp)[k];
+        Y0[0] = q.x; Y0[1] = q.y;
+        if (A.f.kind == FE_FN_NODAL) fi = A.fp[k];
+    } else {
+        const double2 q0 = reinterpret_cast<const double2 *>(A.xyp)[2 * (int64_t)k];
+        const double2 q1 = reinterpret_cast<const double2 *>(A.xyp)[2 * (int64_t)k + 1];
+        Y0[0] = q0.x; Y0[1] = q0.y; Y0[DIM - 1] = q1.x;
+        fi = q1.y;
+    }
+    const bool nodal_f = A.f.kind == FE_FN_NODAL;
+    double fvert = 0.0;
+    if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) fvert = nodal_f ? fi : fn_point<DIM>(A.f, Y0);
+    const int4 *ep4 = reinterpret_cast<const int4 *>(A.elemp);
+    double bsum = 0.0, lift = 0.0;
+    int32_t err = 0;
+    __syncthreads();
+    for (int32_t c0 = 0; c0 < d; c0 += LNB) {
+        const int32_t j = c0 + tid;
+        if (j < d) {
+            const int2 km = A.pincm[s + j];
+            const int32_t t = km.x / NV;
+            const int a = km.x - t * NV;
+            const uint32_t meta = (uint32_t)km.y;
+            const int4 ep = ep4[t];
+            const double kt = A.kappa ? A.kappa[t] : 1.0;
+            int32_t pq[NV - 1], lab[NV - 1];
+            double Y[NV - 1][DIM], F[NV - 1];
+#pragma unroll
+            for (int q = 0; q < NV - 1; ++q) {
+                const int b = fe_other<NV>(a, q);
+                pq[q] = (b == 0 ? ep.x : (b == 1 ? ep.y : (b == 2 ? ep.z : ep.w))) & EREC_POS;
+                lab[q] = A.elem[(int64_t)b * A.NT + t];
+                co[tid][q] = lower_bound_i32(cols, len, lab[q]);
+                if (DIM == 2) {
+                    const double2 c = reinterpret_cast<const double2 *>(A.xyp)[pq[q]];
+                    Y[q][0] = c.x; Y[q][1] = c.y;
+                    F[q] = nodal_f ? A.fp[pq[q]] : 0.0;
+                } else {
+                    const double2 c0v = reinterpret_cast<const double2 *>(A.xyp)[2 * (int64_t)pq[q]];
+                    const double2 c1v = reinterpret_cast<const double2 *>(A.xyp)[2 * (int64_t)pq[q] + 1];
+                    Y[q][0] = c0v.x; Y[q][1] = c0v.y; Y[q][DIM - 1] = c1v.x;
+                    F[q] = c1v.y;
+                }
+            }
+            if (!(kt > 0.0) || !isfinite(kt)) err |= ERR_KAPPA;
+            double kv[NV];
+            double bl = 0.0, lf = 0.0;
+            const uint32_t nb = (meta >> Meta<NV>::NBIT) & ((1u << (NV - 1)) - 1);
+            const uint32_t rb = (meta >> Meta<NV>::RBIT) & ((1u << (NV - 1)) - 1);
+            const uint32_t db = (meta >> Meta<NV>::DBIT) & ((1u << (NV - 1)) - 1);
+            if constexpr (DIM == 2) {
+                const double *X1 = Y[0], *X2 = Y[1];
+                const double E0x = X2[0] - X1[0], E0y = X2[1] - X1[1];
+                const double E1x = Y0[0] - X2[0], E1y = Y0[1] - X2[1];
+                const double E2x = X1[0] - Y0[0], E2y = X1[1] - Y0[1];
+                const double area2 = E1x * E2y - E1y * E2x;
+                if (!(area2 > 0.0) || !isfinite(area2)) err |= ERR_MEASURE;
+                const double sc = kt / (2.0 * area2);
+                const double k01 = sc * (E0x * E1x + E0y * E1y), k02 = sc * (E0x * E2x + E0y * E2y);
+                kv[0] = sc * (E0x * E0x + E0y * E0y);
+                kv[1] = k01;
+                kv[2] = k02;
+                if (A.f.kind != FE_FN_ZERO) {
+                    if (A.load_rule == FE_LOAD_DEFAULT) {
+                        double f1, f2;
+                        if (nodal_f) {
+                            f1 = 0.5 * (F[1] + fi);
+                            f2 = 0.5 * (fi + F[0]);
+                        } else {
+                            const double m1[2] = {0.5 * (X2[0] + Y0[0]), 0.5 * (X2[1] + Y0[1])};
+                            const double m2[2] = {0.5 * (Y0[0] + X1[0]), 0.5 * (Y0[1] + X1[1])};
+                            f1 = fn_point<2>(A.f, m1);
+                            f2 = fn_point<2>(A.f, m2);
+                        }
+                        bl += area2 * (f1 + f2) / 12.0;
+                    } else if (A.load_rule == FE_LOAD_CENTROID) {
+                        double fc;
+                        if (nodal_f) {
+                            fc = (fi + F[0] + F[1]) / 3.0;
+                        } else {
+                            const double c[2] = {(Y0[0] + X1[0] + X2[0]) / 3.0, (Y0[1] + X1[1] + X2[1]) / 3.0};
+                            fc = fn_point<2>(A.f, c);
+                        }
+                        bl += area2 * fc / 6.0;
+                    } else {
+                        bl += area2 * fvert / 6.0;
+                    }
+                }
+                // sides through the row's vertex: opposite X1 (to X2, edge E1) and
+                // opposite X2 (to X1, edge E2)
+                for (int jj = 0; jj < 2; ++jj) {
+                    const bool nside = (nb >> jj) & 1u, rside = (rb >> jj) & 1u;
+                    if (!nside && !rside) continue;
+                    const double *Xo = jj == 0 ? X2 : X1;
+                    const int32_t lo = jj == 0 ? lab[1] : lab[0];
+                    const double ex = jj == 0 ? E1x : E2x, ey = jj == 0 ? E1y : E2y;
+                    const double L = sqrt(ex * ex + ey * ey);
+                    const double mid[2] = {0.5 * (Y0[0] + Xo[0]), 0.5 * (Y0[1] + Xo[1])};
+                    const double nrm[2] = {ey / L, -ex / L};   // outward unit normal
+                    auto side_value = [&](const DevFn &g) {
+                        if (g.kind == FE_FN_DUDN_SINPROD) return fn_dudn<2>(g, mid, nrm);
+                        if (g.kind == FE_FN_NODAL) return 0.5 * (g.nodal[i] + g.nodal[lo]);
+                        return fn_point<2>(g, mid);
+                    };
+                    if (nside) bl += L * side_value(A.gn) / 2.0;
+                    if (rside) {
+                        const double m1 = A.ralpha * L / 6.0;
+                        kv[0] += A.ralpha * L / 3.0;
+                        kv[jj == 0 ? 2 : 1] += m1;
+                        const bool other_d = jj == 0 ? ((db >> 1) & 1u) : (db & 1u);
+                        if (other_d && A.gd.kind != FE_FN_ZERO) lf += m1 * dirichlet_value<2>(A.gd, lo, Xo);
+                        if (A.gr.kind != FE_FN_ZERO) bl += L * side_value(A.gr) / 2.0;
+                    }
+                }
+                if (db && A.gd.kind != FE_FN_ZERO) {
+                    if (db & 1u) lf += k01 * dirichlet_value<2>(A.gd, lab[0], X1);
+                    if (db & 2u) lf += k02 * dirichlet_value<2>(A.gd, lab[1], X2);
+                }
+            } else {
+                const double *Y1 = Y[0], *Y2 = Y[1], *Y3 = Y[2];
+                double d10[3], d20[3], d30[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    d10[c] = Y1[c] - Y0[c];
+                    d20[c] = Y2[c] - Y0[c];
+                    d30[c] = Y3[c] - Y0[c];
+                }
+                double n1[3], n2[3], n3[3], n0[3];
+                cross3(d20, d30, n1);
+                cross3(d30, d10, n2);
+                cross3(d10, d20, n3);
+                for (int c = 0; c < 3; ++c) n0[c] = -(n1[c] + n2[c] + n3[c]);
+                const double vol6 = dot3(n3, d30);
+                if (!(vol6 > 0.0) || !isfinite(vol6)) err |= ERR_MEASURE;
+                const double sc = kt / (6.0 * vol6);
+                const double kr[3] = {sc * dot3(n0, n1), sc * dot3(n0, n2), sc * dot3(n0, n3)};
+                kv[0] = sc * dot3(n0, n0);
+                kv[1] = kr[0]; kv[2] = kr[1]; kv[3] = kr[2];
+                const double vol = vol6 / 6.0;
+                const double alpha = 0.58541019662496845446;   // (5 + 3 sqrt 5) / 20
+                const double beta = 0.13819660112501051518;    // (5 - sqrt 5) / 20
+                if (A.load_rule == FE_LOAD_CENTROID && A.f.kind != FE_FN_ZERO) {
+                    double fc;
+                    if (nodal_f) {
+                        fc = (fi + F[0] + F[1] + F[2]) / 4.0;
+                    } else {
+                        double c[3];
+                        for (int q = 0; q < 3; ++q) c[q] = (Y0[q] + Y1[q] + Y2[q] + Y3[q]) / 4.0;
+                        fc = fn_point<3>(A.f, c);
+                    }
+                    bl += vol * fc / 4.0;
+                } else if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) {
+                    bl += vol * fvert / 4.0;
+                } else if (nodal_f) {
+                    const double sf = fi + F[0] + F[1] + F[2];
+                    bl += vol * (fi + sf) / 20.0;
+                } else if (A.f.kind != FE_FN_ZERO) {
+                    double S[3];
+                    for (int c = 0; c < 3; ++c) S[c] = Y0[c] + Y1[c] + Y2[c] + Y3[c];
+                    double q = 0.0;
+                    for (int kq = 0; kq < 4; ++kq) {
+                        const double *Yk = kq == 0 ? Y0 : Y[kq - 1];
+                        double pt[3];
+                        for (int c = 0; c < 3; ++c) pt[c] = beta * S[c] + (alpha - beta) * Yk[c];
+                        q += fn_point<3>(A.f, pt) * (kq == 0 ? alpha : beta);
+                    }
+                    bl += vol * q / 4.0;
+                }
+                // faces through the row's vertex: opposite Y1, Y2, Y3
+                const double *nq[3] = {n1, n2, n3};
+                for (int jj = 0; jj < 3; ++jj) {
+                    const bool nside = (nb >> jj) & 1u, rside = (rb >> jj) & 1u;
+                    if (!nside && !rside) continue;
+                    const double *nf = nq[jj];
+                    const double nn = sqrt(dot3(nf, nf));
+                    const double area = 0.5 * nn;
+                    double cen[3];
+                    for (int c = 0; c < 3; ++c) cen[c] = (Y0[c] + Y1[c] + Y2[c] + Y3[c] - Y[jj][c]) / 3.0;
+                    const double nrm[3] = {-nf[0] / nn, -nf[1] / nn, -nf[2] / nn};
+                    auto face_value = [&](const DevFn &g) {
+                        if (g.kind == FE_FN_DUDN_SINPROD) return fn_dudn<3>(g, cen, nrm);
+                        if (g.kind == FE_FN_NODAL) {
+                            double sg = g.nodal[i];
+                            for (int c = 0; c < 3; ++c)
+                                if (c != jj) sg += g.nodal[lab[c]];
+                            return sg / 3.0;
+                        }
+                        return fn_point<3>(g, cen);
+                    };
+                    if (nside) bl += area * face_value(A.gn) / 3.0;
+                    if (rside) {
+                        const double m1 = A.ralpha * area / 12.0;
+                        kv[0] += A.ralpha * area / 6.0;
+                        for (int r = 0; r < 3; ++r) {
+                            if (r == jj) continue;
+                            kv[1 + r] += m1;
+                            if (((db >> r) & 1u) && A.gd.kind != FE_FN_ZERO)
+                                lf += m1 * dirichlet_value<3>(A.gd, lab[r], Y[r]);
+                        }
+                        if (A.gr.kind != FE_FN_ZERO) bl += area * face_value(A.gr) / 3.0;
+                    }
+                }
+                if (db && A.gd.kind != FE_FN_ZERO)
+                    for (int jj = 0; jj < 3; ++jj)
+                        if ((db >> jj) & 1u) lf += kr[jj] * dirichlet_value<3>(A.gd, lab[jj], Y[jj]);
+            }
+#pragma unroll
+            for (int q = 0; q < NV; ++q) cv[tid][q] = kv[q];
+            cb[tid][0] = bl;
+            cb[tid][1] = lf;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int32_t n = min(LNB, d - c0);
+            for (int32_t jj = 0; jj < n; ++jj) {
+                acc[diag] += cv[jj][0];
+#pragma unroll
+                for (int q = 0; q < NV - 1; ++q) acc[co[jj][q]] += cv[jj][1 + q];
+                bsum += cb[jj][0];
+                lift += cb[jj][1];
+            }
+        }
+        __syncthreads();
+    }
+    if (err) atomicOr(A.status + ST_ERR, err);
+    const int64_t lstart = A.lrowptr[i];
+    for (int c = tid; c < len; c += LNB) {
+        const double x = acc[c];
+        A.val[lstart + c] = x;
+        if (A.val_bc) A.val_bc[lstart + c] = rowd ? (c == diag ? 1.0 : 0.0) : (A.isdl[cols[c]] ? 0.0 : x);
+    }
+    if (tid == 0) {
+        const double gdi = rowd ? dirichlet_value<DIM>(A.gd, i, Y0) : 0.0;
+        A.b[i] = rowd ? gdi : bsum - lift;
+        if (A.b_load) A.b_load[i] = bsum;
+        if (A.isd) A.isd[i] = (uint8_t)rowd;
+    }
+}
+
 template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream_t s)
 {
     const unsigned g = (unsigned)cdiv(A.N, BLOCK);
@@ -746,6 +1082,10 @@ extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double 
     A.direct = plan->l1_agg;
     A.precp = plan->precp;
     A.rcols = (plan->dim == 3 && plan->l1_agg && plan->rows_reg) ? reinterpret_cast<const int32_t *>(plan->rslot) : nullptr;
+    A.longk = plan->longk;
+    A.elem = plan->elem;
+    A.lrowptr = plan->l1_agg ? plan->prowptr : plan->rowlen;   // label-order row starts
+    A.isdl = plan->isd;
     A.val = val;
     A.val_bc = val_bc;
     A.b = b;
@@ -767,9 +1107,18 @@ extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double 
     if (rc) return rc;
     const int mr = plan->max_row;
     if (mr <= 16) rc = launch<16, 256>(plan->dim, A, s);
-    else if (mr <= 32) rc = launch<32, 128>(plan->dim, A, s);
+    else if (mr <= 32 || plan->dim == 2) rc = launch<32, 128>(plan->dim, A, s);
     else rc = launch<64, 64>(plan->dim, A, s);
     if (rc) return rc;
+    if (plan->nlong > 0) {
+        if (plan->dim == 2)
+            FE_TIMED("k_assemble_long", s,
+                     hipLaunchKernelGGL(k_assemble_long<3>, dim3((unsigned)plan->nlong), dim3(LNB), 0, s, A));
+        else
+            FE_TIMED("k_assemble_long", s,
+                     hipLaunchKernelGGL(k_assemble_long<4>, dim3((unsigned)plan->nlong), dim3(LNB), 0, s, A));
+        if ((rc = fe_launch_check())) return rc;
+    }
     if (A.direct) return FE_OK;   // rows already in label order
     FE_TIMED("k_values_to_label", s,
              hipLaunchKernelGGL(k_values_to_label, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,

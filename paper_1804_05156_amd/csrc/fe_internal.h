@@ -26,10 +26,14 @@ enum : int32_t {
 };
 
 // Slots of the device status array.
-enum { ST_ERR = 0, ST_UNUSED = 1, ST_MAXROW = 2, ST_MAXDEG = 3, ST_NDIR = 4, ST_RUNS = 5, ST_COUNT = 16 };
+enum { ST_ERR = 0, ST_UNUSED = 1, ST_MAXROW = 2, ST_MAXDEG = 3, ST_NDIR = 4, ST_RUNS = 5, ST_NLONG = 6,
+       ST_COUNT = 16 };
 
-// Fixed per-row capacity (stored columns, the vertex itself included) of the row
-// kernels, and their block sizes.
+// Per-row capacity (stored columns, the vertex itself included) of the row kernels
+// and the numeric kernels, and their block sizes.  Longer rows ("long rows") are
+// handled by kernels of their own, one workgroup per row, whose LDS holds up to
+// LCAND candidate columns: (dim) * (incidences of the vertex) + 1 <= LCAND.
+constexpr int LCAND = 8192;
 template <int NV> struct RowCaps;
 template <> struct RowCaps<3> { static constexpr int COL = 32, BLOCK = 128; };
 template <> struct RowCaps<4> { static constexpr int COL = 64, BLOCK = 64; };
@@ -70,7 +74,10 @@ template <int NV> __host__ __device__ __forceinline__ int fe_other(int a, int jj
 }
 
 // Row info word (one per row, in processing order): bits 0-7 row length,
-// bits 8-15 offset of the diagonal, bit 16 the row's vertex is a Dirichlet node.
+// bits 8-15 offset of the diagonal, bit 16 the row's vertex is a Dirichlet node,
+// bit 17 (INFO_LONG) a long row: length and diagonal offset are then kept in the
+// row record's .z and .w (in place of the Dirichlet-column mask) and bits 0-15 are 0.
+constexpr uint32_t INFO_LONG = 1u << 17;
 
 struct fe_plan {
     int32_t dim, nv;
@@ -120,6 +127,9 @@ struct fe_plan {
                           //        pattern pass keeps its column indices here as int32
     int64_t nnz_max;      // capacity of valp
     int64_t *stat_part;   // per-block partial statistics
+    int32_t *longk;       // nlcap  processing positions of the long rows
+    int32_t nlcap;        // capacity of longk
+    int32_t nlong;        // long rows (host copy)
     // host copies
     int64_t nnz, ndir;
     int32_t max_row, max_deg;
@@ -244,11 +254,12 @@ FE_DEV int32_t wave_rank_add(int32_t *cnt, int32_t key, bool active, bool *runs)
 // Per-lane LDS counter increment (AGG false) or the wavefront-aggregated one above
 // (AGG true; then every lane of the wavefront must call it).
 // Element records (elemp, one int4 per element): word a holds the processing
-// position of vertex a in its low 26 bits (at most 2^26 vertices), the side code
-// of the face opposite vertex a in bits 26-27 and the Dirichlet flag of vertex a
-// in bit 28.
-constexpr int32_t EREC_POS = (1 << 26) - 1;
-constexpr int EREC_CODE = 26, EREC_DIR = 28;
+// position of vertex a in its low 29 bits, the side code of the face opposite
+// vertex a in bits 29-30 and the Dirichlet flag of vertex a in bit 31.  Positions
+// of vertices in use are below 2^29 (a plan with more vertices in use is refused);
+// unused vertices never appear in a record.
+constexpr int32_t EREC_POS = (1 << 29) - 1;
+constexpr int EREC_CODE = 29, EREC_DIR = 31;
 
 // Logical block of hardware block b in a grid of nblk.  Blocks are dealt to the 8
 // XCDs round-robin (b, b + 8, ... share one XCD and its L2); this bijection gives

@@ -33,11 +33,11 @@ namespace {
 constexpr int EBLOCK = 256;     // element-parallel kernels
 constexpr int L1B = 1024;       // threads of the level-1 kernels
 constexpr int L1CH = 32768;     // elements per level-1 chunk
-constexpr int NBMAX = 16384;    // buckets held in LDS by the level-1 kernels
+constexpr int NBMAX = 524288;   // buckets (2^19: with 2^12 vertices each, every int32 label)
 constexpr int VBMAX = 4096;     // vertices per bucket (2^bs) at most
 constexpr int BKB = 256;        // threads of the bucket kernel
 constexpr int BCAPMAX = 24576;  // incidences per bucket sorted in LDS at most (larger: global path)
-constexpr int FINE = 32;        // buckets per coarse bucket at most
+constexpr int FINE = 1024;      // buckets per coarse bucket at most
 constexpr int L1SLOTS = 512;    // coarse-to-fine blocks resident at once (2 of FB threads per CU)
 constexpr int FB = 1024;        // threads of the coarse-to-fine kernel
 constexpr int L1SUB = 2048;     // elements per LDS-staged sub-chunk of the level-1 scatter
@@ -50,8 +50,10 @@ constexpr int RUNR = 8;         // incidences per batch in the row kernels
 FE_DEV int32_t l1_chunk(int32_t b, int32_t nblk) { return xcd_block(b, nblk); }
 
 // Coarse bucket of vertex v: its bucket v >> bs divided by the buckets per coarse
-// bucket, as a multiply by cmul = ceil(2^32 / fine), exact for bucket numbers
-// below 2^22 and fine <= 32 (vertex labels are below 2^26, bs >= 4).
+// bucket, as a multiply by cmul = ceil(2^32 / fine).  With q = v >> bs and
+// cmul = 2^32/fine + e (0 <= e < 1), q cmul / 2^32 exceeds q / fine by less than
+// 1/fine whenever q fine < 2^32, so the floor is exact: here q < NBMAX = 2^19 and
+// fine <= 1024.
 FE_DEV int32_t coarse_of(int32_t v, int32_t bs, uint64_t cmul)
 {
     return (int32_t)(((uint64_t)(uint32_t)(v >> bs) * cmul) >> 32);
@@ -236,8 +238,10 @@ __global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t 
                                                 int32_t nblk1, int64_t ninc, const int2 *__restrict__ pairs,
                                                 int2 *pairs2, int32_t *fstart)
 {
+    static_assert(FINE <= FB, "one fine bucket per thread");
     __shared__ int32_t cnt[FINE];
     __shared__ int32_t cur[FINE];
+    __shared__ int32_t sl[2 * (FB / 64)];
     const int32_t cb = blockIdx.x;
     const int32_t s = offs[(int64_t)cb * nblk1];
     const int32_t e = (cb + 1 < ncb) ? offs[(int64_t)(cb + 1) * nblk1] : (int32_t)ninc;
@@ -249,14 +253,15 @@ __global__ __launch_bounds__(FB) void k_l1_fine(int32_t nb, int32_t bs, int32_t 
         lds_rank_add<AGG>(cnt, j < e ? (pairs[j].x >> bs) - fbase : 0, j < e);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int32_t run = s;
-        for (int f = 0; f < fine; ++f) {
-            cur[f] = run;
-            if (fbase + f < nb) fstart[fbase + f] = run;
-            run += cnt[f];
+    {
+        const int f = threadIdx.x;
+        int32_t tot;
+        const int32_t ex = block_exclusive_i32<FB>(f < fine ? cnt[f] : 0, sl, &tot);
+        if (f < fine) {
+            cur[f] = s + ex;
+            if (fbase + f < nb) fstart[fbase + f] = s + ex;
         }
-        if (cb == ncb - 1) fstart[nb] = (int32_t)ninc;
+        if (f == 0 && cb == ncb - 1) fstart[nb] = (int32_t)ninc;
     }
     __syncthreads();
     for (int32_t jb = s; jb < e; jb += FB) {
@@ -505,6 +510,8 @@ struct RowArgs {
     int4 *precp;          // final
     int4 *rslot;          // 3-D register form: count: each row's column set written; final: read
     int2 *rmask;          // 3-D label-order register form: each row's Dirichlet-column mask
+    int32_t *longk;       // LDS form, count: long rows appended here
+    int32_t nlcap;
     int32_t *status;
 };
 
@@ -646,10 +653,12 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         }
         return;
     }
+    // a long row (more columns than the LDS set holds) is left to k_rows_long
+    if (FINAL && !REG && R.prowptr[k + 1] - R.prowptr[k] > SETCAP) return;
     const bool from_pinc = FINAL && !LBL;
     // general path: the count pass writes the element record words of this row's
     // vertex (position, side code opposite it, its Dirichlet flag)
-    const int32_t rowdir = (!FINAL && !LBL && R.isdp[k]) ? (1 << EREC_DIR) : 0;
+    const int32_t rowdir = (!FINAL && !LBL && R.isdp[k]) ? (int32_t)(1u << EREC_DIR) : 0;
     const int32_t src = from_pinc ? s : R.inclp[k];
     const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
@@ -693,7 +702,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                         const int32_t t = key[q] / NV;
                         const int a = key[q] - t * NV;
                         R.pinc[s + j0 + q] = key[q];
-                        R.elemp[(int64_t)t * 4 + a] = k | (code[q] << EREC_CODE) | rowdir;
+                        R.elemp[(int64_t)t * 4 + a] = k | (int32_t)((uint32_t)code[q] << EREC_CODE) | rowdir;
                     }
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
@@ -703,7 +712,14 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         }
     }
     if (!ok) {
-        atomicOr(R.status + ST_ERR, REG ? ERR_RETRY : ERR_LIMIT);
+        if (REG) {
+            atomicOr(R.status + ST_ERR, ERR_RETRY);
+        } else if (!FINAL) {
+            // a long row: k_rows_long counts it (and writes its incidences' words)
+            const int32_t j = atomicAdd(R.status + ST_NLONG, 1);
+            if (j < R.nlcap) R.longk[j] = k;
+            else atomicOr(R.status + ST_ERR, ERR_LIMIT);
+        }
         if (!FINAL) R.prowptr[k] = 0;
         return;
     }
@@ -802,6 +818,121 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     R.precp[k] = make_int4(ps, (int32_t)info, (int32_t)(uint32_t)dmask, (int32_t)(uint32_t)(dmask >> 32));
 }
 
+// Long rows: rows with more columns than the LDS column set holds (a vertex with
+// more than 31 neighbours in 2-D, 63 in 3-D).  One workgroup per long row forms the
+// row's column set from all its incidences at once: the other vertices of every
+// incident element and the vertex itself go to LDS, are sorted by a bitonic network
+// and made unique.  The count form (FINAL false) records the length and, in the
+// general path, writes what the count pass writes for every incidence (the
+// processing-order key copy and the element record word).  The final form writes
+// the columns, each incidence's metadata word (local vertex and Dirichlet /
+// Neumann / Robin bits; no column offsets: the numeric long-row kernel finds them
+// by search) and the row record, with INFO_LONG and the length and diagonal offset
+// in the record's .z and .w.  The count form loops over the long rows counted on
+// the device (any grid); the final form takes one block per row.
+constexpr int LB = 256;
+
+template <int NV, bool FINAL, bool LBL>
+__global__ __launch_bounds__(LB) void k_rows_long(RowArgs R)
+{
+    __shared__ int32_t cand[LCAND];
+    __shared__ int32_t sl[2 * (LB / 64)];
+    __shared__ int32_t sh_diag;
+    const int32_t nlong = min(R.status[ST_NLONG], R.nlcap);
+    const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
+    for (int32_t r = blockIdx.x; r < nlong; r += gridDim.x) {
+        const int32_t k = R.longk[r];
+        const int32_t i = R.pi[k];
+        const int32_t s = R.pincptr[k];
+        const int32_t d = R.pincptr[k + 1] - s;
+        const int32_t nc = (NV - 1) * d + 1;
+        if (nc > LCAND) {   // block-uniform
+            if (threadIdx.x == 0) atomicOr(R.status + ST_ERR, ERR_LIMIT);
+            continue;
+        }
+        const bool from_pinc = FINAL && !LBL;
+        const int32_t src = from_pinc ? s : R.inclp[k];
+        const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
+        const int32_t rowdir = (!FINAL && !LBL && R.isdp[k]) ? (int32_t)(1u << EREC_DIR) : 0;
+        int32_t M = 1;
+        while (M < nc) M <<= 1;
+        for (int32_t j = threadIdx.x; j < d; j += LB) {
+            const int32_t key = klist[src + j];
+            const int32_t t = key / NV;
+            const int a = key - t * NV;
+            int4 e4 = make_int4(0, 0, 0, 0);
+            if (LBL) e4 = ep4[t];
+#pragma unroll
+            for (int jj = 0; jj < NV - 1; ++jj)
+                cand[(NV - 1) * j + jj] = LBL ? sel_i4(e4, fe_other<NV>(a, jj))
+                                              : R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
+            if (!FINAL && !LBL) {
+                const int32_t code = R.bd ? (int32_t)(R.bd[(int64_t)a * R.NT + t] & 3) : 0;
+                R.pinc[s + j] = key;
+                R.elemp[(int64_t)t * 4 + a] = k | (int32_t)((uint32_t)code << EREC_CODE) | rowdir;
+            }
+        }
+        for (int32_t j = (NV - 1) * d + threadIdx.x; j < M; j += LB) cand[j] = (j == (NV - 1) * d) ? i : INT32_MAX;
+        __syncthreads();
+        for (int32_t kk = 2; kk <= M; kk <<= 1)
+            for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                for (int32_t x = threadIdx.x; x < M; x += LB) {
+                    const int32_t l = x ^ jj;
+                    if (l > x) {
+                        const int32_t p = cand[x], q = cand[l];
+                        if (((x & kk) == 0) ? p > q : p < q) {
+                            cand[x] = q;
+                            cand[l] = p;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        const int32_t ps = FINAL ? R.prowptr[k] : 0;
+        int32_t u = 0;
+        for (int32_t x0 = 0; x0 < M; x0 += LB) {
+            const int32_t x = x0 + threadIdx.x;
+            const int32_t c = x < M ? cand[x] : INT32_MAX;
+            const bool first = c != INT32_MAX && (x == 0 || cand[x - 1] != c);
+            int32_t tot;
+            const int32_t ex = block_exclusive_i32<LB>(first ? 1 : 0, sl, &tot);
+            if (FINAL && first) {
+                R.colindp[ps + u + ex] = c;
+                if (c == i) sh_diag = u + ex;
+            }
+            u += tot;
+        }
+        if (!FINAL) {
+            if (threadIdx.x == 0) R.prowptr[k] = u;
+            __syncthreads();
+            continue;
+        }
+        for (int32_t j = threadIdx.x; j < d; j += LB) {
+            const int32_t key = klist[src + j];
+            const int32_t t = key / NV;
+            const int a = key - t * NV;
+            const int4 ep = ep4[t];
+            uint32_t meta = (uint32_t)a;
+#pragma unroll
+            for (int jj = 0; jj < NV - 1; ++jj) {
+                const uint32_t wb = (uint32_t)word_i4(ep, fe_other<NV>(a, jj));
+                const uint32_t code = (wb >> EREC_CODE) & 3u;
+                if ((wb >> EREC_DIR) & 1u) meta |= 1u << (Meta<NV>::DBIT + jj);
+                if (code == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
+                if (code == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
+            }
+            R.pincm[s + j] = make_int2(key, (int32_t)meta);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t info = INFO_LONG | ((uint32_t)(R.isdp[k] ? 1 : 0) << 16);
+            R.prow_info[k] = info;
+            R.precp[k] = make_int4(ps, (int32_t)info, u, sh_diag);
+        }
+        __syncthreads();
+    }
+}
+
 // Label-order row records and lengths: rowrec[i] = precp[piinv[i]], rowlen[i] =
 // its length (one gather per row; the stores are coalesced).
 __global__ __launch_bounds__(256) void k_label_rows(int32_t N, const int32_t *__restrict__ piinv,
@@ -811,7 +942,7 @@ __global__ __launch_bounds__(256) void k_label_rows(int32_t N, const int32_t *__
     if (i >= N) return;
     const int4 r = precp[piinv[i]];
     rowrec[i] = r;
-    rowlen[i] = r.y & 0xff;
+    rowlen[i] = (r.y & INFO_LONG) ? r.z : (r.y & 0xff);
 }
 
 // Label-order copy of the column indices from the processing-order rows: one
@@ -953,19 +1084,24 @@ Buckets choose_buckets(int64_t N, int64_t NT, int nv)
     return B;
 }
 
-// Upper bound of the number of stored entries: every row has at most the per-row
-// capacity, and every element adds at most nv*(nv-1) off-diagonal entries.
-int64_t nnz_bound(int64_t N, int64_t NT, int nv)
+// Upper bound of the number of stored entries: every element adds at most
+// nv*(nv-1) off-diagonal entries.
+int64_t nnz_bound(int64_t N, int64_t NT, int nv) { return N + NT * nv * (nv - 1); }
+
+// Capacity of the long-row list: a long row has more than COL columns, so its vertex
+// is in at least COL / (nv - 1) elements.
+int64_t long_cap(int64_t N, int64_t NT, int nv)
 {
-    const int64_t a = N * (nv == 3 ? RowCaps<3>::COL : RowCaps<4>::COL);
-    const int64_t b = N + NT * nv * (nv - 1);
-    return a < b ? a : b;
+    const int64_t col = nv == 3 ? RowCaps<3>::COL : RowCaps<4>::COL;
+    const int64_t per = cdiv(col, nv - 1);
+    const int64_t c = (int64_t)nv * NT / per + 1;
+    return c < N ? c : N;
 }
 
 enum {
     W_STATUS, W_TOTALS, W_PART, W_VINFO, W_INCLP, W_ISD, W_ISDP, W_OWNF, W_HIST1, W_OWNCNT, W_PI, W_PIINV,
     W_PINCPTR, W_PINC, W_PINCM, W_ELEMP, W_ROWLEN, W_PROWPTR, W_PROWINFO, W_PRECP, W_ROWREC, W_XYP, W_FP,
-    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_RSLOT, W_RMASK, W_COUNT
+    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_RSLOT, W_RMASK, W_LONGK, W_COUNT
 };
 
 struct Layout {
@@ -1015,6 +1151,7 @@ Layout plan_layout(int64_t N, int64_t NT, int nv)
     sz[W_FSTART] = sizeof(int32_t) * (size_t)(Bk.nb + 1);
     sz[W_RMASK] = nv == 4 ? sizeof(int2) * (size_t)N : 0;
     sz[W_RSLOT] = nv == 4 ? sizeof(int32_t) * (size_t)REGCAP * (size_t)N : 0;   // 3-D row slots
+    sz[W_LONGK] = sizeof(int32_t) * (size_t)long_cap(N, NT, nv);
     Layout L{};
     size_t o = 0;
     for (int k = 0; k < W_COUNT; ++k) {
@@ -1032,7 +1169,7 @@ int check_mesh(const fe_mesh *m)
     if (m->n_node <= 0 || m->n_elem < 0) return FE_EINVAL;
     const int64_t nv = m->dim + 1;
     if (m->n_node >= INT32_MAX || m->n_elem >= INT32_MAX / nv) return FE_EOVERFLOW;
-    if (cdiv(m->n_node, (int64_t)VBMAX) > NBMAX) return FE_ELIMIT;   // more than 2^26 vertices
+    static_assert((int64_t)VBMAX * NBMAX >= (int64_t)INT32_MAX, "every int32 label has a bucket");
     return FE_OK;
 }
 
@@ -1057,6 +1194,8 @@ RowArgs row_args(fe_plan *P)
     R.precp = P->precp;
     R.rslot = P->rslot;
     R.rmask = P->rmask;
+    R.longk = P->longk;
+    R.nlcap = P->nlcap;
     R.status = P->status;
     return R;
 }
@@ -1114,7 +1253,8 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
             const int64_t len = std::min<int64_t>(L1CH, (int64_t)NT - ch * L1CH);
             calls += cdiv(len, L1B) * NV * (L1B / 64);
         }
-        P->l1_agg = 2 * (int64_t)st0[ST_RUNS] > calls;
+        // (label-order processing stores labels as positions in the element records)
+        P->l1_agg = 2 * (int64_t)st0[ST_RUNS] > calls && (int64_t)N <= (int64_t)EREC_POS + 1;
         if ((rc = fe_scan_exclusive(P->hist1, P->hist1, nh, P->totals + 4, P->part, P->status, s))) return rc;
         if (P->l1_agg) {
             FE_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_l1_scatter<NV, true>),
@@ -1188,6 +1328,17 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     P->rows_reg = 1;
     for (int attempt = 0; attempt < 2; ++attempt) {
         launch_rows<NV, false>(P, R, s);
+        if (!P->rows_reg) {
+            // rows beyond the LDS set: counted by k_rows_long (the grid loops over
+            // however many the count pass found, none for most meshes)
+            const unsigned lg = (unsigned)std::min<int64_t>(P->nlcap, 1024);
+            if (P->l1_agg)
+                FE_TIMED("k_rows_long_count", s,
+                         hipLaunchKernelGGL((k_rows_long<NV, false, true>), dim3(lg), dim3(LB), 0, s, R));
+            else
+                FE_TIMED("k_rows_long_count", s,
+                         hipLaunchKernelGGL((k_rows_long<NV, false, false>), dim3(lg), dim3(LB), 0, s, R));
+        }
         if ((rc = fe_launch_check())) return rc;
         if ((rc = fe_scan_exclusive(P->prowptr, P->prowptr, N, P->totals + 2, P->part, P->status, s))) return rc;
         const unsigned sb = (unsigned)(cdiv(N, STB) < 1024 ? cdiv(N, STB) : 1024);   // grid-stride beyond
@@ -1210,11 +1361,14 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
             continue;
         }
         if (st[ST_ERR]) return fe_status_from_bits(st[ST_ERR]);
+        P->nlong = st[ST_NLONG];
         P->nnz = tot[2];
         P->max_row = st[ST_MAXROW];
         P->max_deg = st[ST_MAXDEG];
         P->ndir = st[ST_NDIR];
         if (!P->l1_agg && tot[1] != P->ninc) return FE_EHIP;   // every incidence must be placed
+        // the element records hold 29-bit positions of the vertices in use
+        if (!P->l1_agg && tot[0] > (int64_t)EREC_POS + 1) return FE_ELIMIT;
         if (P->nnz > P->nnz_max) return FE_EHIP;
         return FE_OK;
     }
@@ -1230,12 +1384,18 @@ template <int NV> int plan_pattern(fe_plan *P, int32_t *rowptr, int32_t *colind,
         // indices, and the row pointer is the processing-order one
         R.colindp = colind;
         launch_rows<NV, true>(P, R, s);
+        if (P->nlong > 0)
+            FE_TIMED("k_rows_long_final", s,
+                     hipLaunchKernelGGL((k_rows_long<NV, true, true>), dim3((unsigned)P->nlong), dim3(LB), 0, s, R));
         int rc;
         if ((rc = fe_launch_check())) return rc;
         FE_HIP_CHECK(hipMemcpyAsync(rowptr, P->prowptr, sizeof(int32_t) * (size_t)(N + 1), hipMemcpyDeviceToDevice, s));
         return FE_OK;
     }
     launch_rows<NV, true>(P, R, s);
+    if (P->nlong > 0)
+        FE_TIMED("k_rows_long_final", s,
+                 hipLaunchKernelGGL((k_rows_long<NV, true, false>), dim3((unsigned)P->nlong), dim3(LB), 0, s, R));
     FE_TIMED("k_label_rows", s,
              hipLaunchKernelGGL(k_label_rows, dim3((unsigned)cdiv(N, 256)), dim3(256), 0, s, N, (const int32_t *)P->piinv,
                            (const int4 *)P->precp, P->rowrec, P->rowlen));
@@ -1318,6 +1478,9 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     P->fstart = reinterpret_cast<int32_t *>(base + L.off[W_FSTART]);
     P->rslot = reinterpret_cast<int4 *>(base + L.off[W_RSLOT]);
     P->rmask = reinterpret_cast<int2 *>(base + L.off[W_RMASK]);
+    P->longk = reinterpret_cast<int32_t *>(base + L.off[W_LONGK]);
+    P->nlcap = (int32_t)long_cap(mesh->n_node, mesh->n_elem, nv);
+    P->nlong = 0;
     P->nnz_max = nnz_bound(mesh->n_node, mesh->n_elem, nv);
     hipStream_t s = static_cast<hipStream_t>(stream);
     rc = (nv == 3) ? plan_build<3>(P, s) : plan_build<4>(P, s);
@@ -1351,6 +1514,7 @@ extern "C" int fe_plan_get_info(const fe_plan *plan, fe_plan_info *info)
     info->max_deg = plan->max_deg;
     info->n_dirichlet = plan->ndir;
     info->sort_runs = plan->l1_agg;
+    info->n_long = plan->nlong;
     return FE_OK;
 }
 

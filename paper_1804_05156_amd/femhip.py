@@ -46,7 +46,7 @@ class fe_fn(C.Structure):
 class fe_plan_info(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_node", C.c_int64), ("n_elem", C.c_int64), ("nnz", C.c_int64),
                 ("n_inc", C.c_int64), ("max_row", C.c_int32), ("max_deg", C.c_int32),
-                ("n_dirichlet", C.c_int64), ("sort_runs", C.c_int32)]
+                ("n_dirichlet", C.c_int64), ("sort_runs", C.c_int32), ("n_long", C.c_int32)]
 
 
 class fe_batch_info(C.Structure):

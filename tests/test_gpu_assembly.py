@@ -248,14 +248,154 @@ def test_high_degree_vertex_3d(k):
             data=data_scale(m, specs))
 
 
-def test_row_capacity_limit_is_reported():
+def _open_fan(k):
+    """k triangles over a half disk around vertex 0, which sits on the straight side:
+    the end spokes and the arc are boundary sides (codes set by the caller)."""
+    ang = math.pi * np.arange(k + 1) / k
+    node = np.vstack([np.r_[0.5, 0.5 + 0.4 * np.cos(ang)], np.r_[0.1, 0.1 + 0.4 * np.sin(ang)]])
+    elem = np.array([[0] * k, list(range(1, k + 1)), list(range(2, k + 2))], np.int32)
+    bd = np.zeros((3, k), np.int8)
+    return meshgen.Mesh(node, elem, bd, np.exp(np.sin(np.arange(k))))
+
+
+def _check_long(m, specs, gr=None, alpha=0.0, rule=0, n_long=None):
     from paper_1804_05156_amd import femhip
-    log("case: fan beyond row capacity")
-    m = _fan(40)
-    node, elem, bd, _ = to_dev(m)
+    (f, fo), (gd, gdo), (gn, gno) = fns(*(list(specs) + [None] * 3)[:3])
+    (grf, gro), _, _ = fns(gr)
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    asm = plan.assemble(kap, f, gd, gn, gR=grf, robin_alpha=alpha, load_rule=rule)
+    plan.check()
+    torch.cuda.synchronize()
+    if n_long is not None:
+        assert plan.info["n_long"] == n_long
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo, gN=gno, gR=gro, alpha=alpha, rule=rule)
+    worst = compare(host(plan, asm), ora, data=data_scale(m, specs, gr))
+    log(f"  max_row {plan.info['max_row']} n_long {plan.info['n_long']} sort_runs {plan.info['sort_runs']}, "
+        f"worst scaled error {worst:.2e}")
+    return plan
+
+
+@pytest.mark.parametrize("k", [32, 40, 100, 1000])
+def test_long_row_fan(k):
+    """A vertex with more neighbours than the row kernels hold (31 in 2-D) takes the
+    long-row kernels of the plan and of the numeric phase; the row is checked
+    against the oracle like any other."""
+    log(f"case: long row, fan k={k}")
+    m = _fan(k)
+    specs = [(FE_FN_SINPROD, (1.0,)), (FE_FN_LINEAR, (1.0, 0.5, 0.25))]
+    plan = _check_long(m, specs, n_long=1 if k + 1 > 32 else 0)
+    assert plan.info["max_row"] == k + 1
+
+
+@pytest.mark.parametrize("code", [1, 2, 3])
+@pytest.mark.parametrize("rule", [0, 1, 2])
+def test_long_row_on_the_boundary(code, rule):
+    """The long row of a boundary vertex: its two end spokes are Dirichlet (lifting),
+    Neumann or Robin sides (side terms and side mass in the long-row kernel), with
+    nodal data and each load rule of Section 4."""
+    log(f"case: long boundary row, side code {code}, load rule {rule}")
+    k = 60
+    m = _open_fan(k)
+    m.bdflag[2, 0] = code            # spoke (0, 1)
+    m.bdflag[1, k - 1] = code        # spoke (k + 1, 0)
+    m.bdflag[0, :] = 1 if code != 1 else 2
+    rng = np.random.default_rng(30 + code)
+    nod = [rng.standard_normal(m.n_node) for _ in range(4)]
+    specs = [(FE_FN_NODAL, (0.0,), nod[0]), (FE_FN_NODAL, (0.0,), nod[1]), (FE_FN_NODAL, (0.0,), nod[2])]
+    gr, alpha = ((FE_FN_NODAL, (0.0,), nod[3]), 0.8) if code == 3 else (None, 0.0)
+    if rule == 0 and code != 1:
+        specs = [(FE_FN_SINPROD, (2.0,)), (FE_FN_LINEAR, (0.3, 1.0, -0.5)), (FE_FN_DUDN_SINPROD, (1.0,))]
+        gr = (FE_FN_DUDN_SINPROD, (0.5,)) if code == 3 else None
+    _check_long(m, specs, gr, alpha, rule, n_long=1)
+
+
+@pytest.mark.parametrize("k", [64, 80, 200])
+def test_long_row_edge_fan(k):
+    """3-D: the two vertices of an edge shared by k tetrahedra have k + 2 columns
+    (more than 64 for k >= 63): Dirichlet faces on one side, Neumann faces through
+    the other vertex's long row."""
+    log(f"case: long rows, edge fan k={k}")
+    m = _edge_fan(k)
+    specs = [(FE_FN_SINPROD, (1.0,)), (FE_FN_LINEAR, (1.0, 0.5, 0.25, 0.125)), (FE_FN_CONST, (0.5,))]
+    plan = _check_long(m, specs, n_long=2 if k + 2 > 64 else 0)
+    assert plan.info["max_row"] == k + 2
+
+
+@pytest.mark.parametrize("rule", [0, 1, 2])
+def test_long_row_edge_fan_robin(rule):
+    """3-D long rows with Robin faces through them and nodal data."""
+    log(f"case: long rows, edge fan with Robin faces, load rule {rule}")
+    m = _edge_fan(70)
+    m.bdflag[1] = 3
+    rng = np.random.default_rng(40 + rule)
+    nod = [rng.standard_normal(m.n_node) for _ in range(4)]
+    specs = [(FE_FN_NODAL, (0.0,), nod[0]), (FE_FN_NODAL, (0.0,), nod[1]), (FE_FN_NODAL, (0.0,), nod[2])]
+    _check_long(m, specs, (FE_FN_NODAL, (0.0,), nod[3]), 0.6, rule, n_long=2)
+
+
+def _union(a, b):
+    """Disjoint union of two meshes: b's labels follow a's."""
+    node = np.hstack([a.node, b.node])
+    elem = np.hstack([a.elem, b.elem + a.n_node]).astype(np.int32)
+    return meshgen.Mesh(node, elem, np.hstack([a.bdflag, b.bdflag]), np.r_[a.kappa, b.kappa])
+
+
+@pytest.mark.parametrize("permute", [False, True])
+def test_long_rows_in_a_large_mesh(permute):
+    """A 129^2 jittered mesh with a fan of 100 beside it, labels in element order or
+    randomly permuted: the long row goes through both processing orders (the label-
+    order copies skip it; it writes its own label-order outputs)."""
+    log(f"case: long row in a large mesh, permute {permute}")
+    sq = meshgen.square_mesh(129, jitter=0.2, permute=permute, seed=88, kappa="lognormal")
+    fan = _fan(100)
+    fan.node[0] += 2.0
+    m = _union(sq, fan)
+    specs = [(FE_FN_SINPROD, (2 * math.pi ** 2,)), (FE_FN_LINEAR, (0.2, 0.1, -0.3))]
+    plan = _check_long(m, specs, n_long=1)
+    assert plan.info["sort_runs"] == (0 if permute else 1)
+
+
+def test_vertex_degree_limit_is_reported():
+    """A vertex in 4096 triangles has 8193 candidate columns, one more than the long-
+    row kernels hold: the plan refuses it with FE_ELIMIT.  4095 still fits."""
+    from paper_1804_05156_amd import femhip
+    log("case: vertex degree limit")
+    node, elem, bd, _ = to_dev(_fan(4096))
     with pytest.raises(femhip.FemhipError) as e:
         femhip.Plan(node, elem, bd)
     assert e.value.code == femhip.FE_ELIMIT
+    _check_long(_fan(4095), [(FE_FN_CONST, (1.0,))], n_long=1)
+
+
+@pytest.mark.parametrize("labels", ["leading", "scattered", "trailing"])
+def test_more_than_2_26_labels(labels):
+    """A 129^2 jittered mesh whose vertices sit among N = 2^26 + 1 labels (the rest
+    unused): more buckets than 2^26 labels fill at 4096 per bucket, and, with
+    trailing labels in element order, element records holding labels above 2^26."""
+    N = 2 ** 26 + 1
+    log(f"case: N = {N}, labels {labels}")
+    small = meshgen.square_mesh(129, jitter=0.2, permute=False, seed=93, kappa="lognormal")
+    rng = np.random.default_rng(94)
+    if labels == "leading":
+        emb = np.arange(small.n_node)
+    elif labels == "trailing":
+        emb = N - small.n_node + np.arange(small.n_node)
+    else:
+        emb = rng.choice(N, small.n_node, replace=False)
+        emb[-1] = N - 1
+    node = np.zeros((2, N))
+    node[:, emb] = small.node
+    m = meshgen.Mesh(node, emb[small.elem].astype(np.int32), small.bdflag, small.kappa)
+    (f, fo), _, _ = fns((FE_FN_CONST, (1.0,)))
+    plan, asm = run_gpu(m, None, f)
+    assert plan.info["sort_runs"] == (labels != "scattered")
+    g = host(plan, asm)
+    del asm
+    torch.cuda.empty_cache()
+    ora = oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo)
+    compare(g, ora)
+    assert g["rowptr"][-1] == ora.rowptr[-1] == plan.nnz
 
 
 def test_error_paths():
