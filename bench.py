@@ -313,6 +313,8 @@ def main():
         wev.append((e0, e1))
     torch.cuda.synchronize()
     warm_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in wev]))
+    log("[bench] symmetric storage (upper triangle)")
+    sym = symmetric_storage(femhip, torch, plan, node, kappa2, f, gn, rowptr, colind, val, N, args.steps)
     femhip.fe_plan_destroy(plan)
     roof = roofline(kernels, counters, N, NT, nnz, dim, nodal, ms_step, warm_ms)
     roof["copy_kernel_GBps"] = copy["GBps"]
@@ -342,6 +344,7 @@ def main():
                    "step": "cold: plan + pattern + numeric assembly with boundary conditions"},
         "phases_ms": {"plan_create": sym_ms, "pattern": pat_ms, "assemble": num_ms},
         "warm": {"ms": warm_ms, "elements_per_s": NT / (warm_ms * 1e-3)},
+        "symmetric_storage": sym,
         "kernels": {"ms_per_step_with_events": ms_step_prof, "by_kernel": kernels},
         "roofline": roof,
         "copy_kernel": copy,
@@ -352,6 +355,47 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def symmetric_storage(femhip, torch, plan, node, kappa, f, gn, rowptr, colind, val, N, reps):
+    """Upper-triangle storage on a plan whose pattern is written: warm fe_assemble_upper
+    against warm fe_assemble (the same kernels, fewer entries written), and one SpMV
+    in symmetric storage (A read as val_u[vidx[q]]) against one in full storage."""
+    dev = node.device
+    stream = torch.cuda.current_stream()
+    rp_u = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    nnz_u = femhip.fe_plan_upper(plan, rowptr, colind, rp_u)
+    ci_u = torch.empty(nnz_u, dtype=torch.int32, device=dev)
+    vidx = torch.empty(colind.numel(), dtype=torch.int32, device=dev)
+    femhip.fe_plan_upper(plan, rowptr, colind, rp_u, ci_u, vidx)
+    val_u = torch.empty(nnz_u, dtype=torch.float64, device=dev)
+    vbc_u = torch.empty_like(val_u)
+    b = torch.empty(N, dtype=torch.float64, device=dev)
+    bl = torch.empty_like(b)
+    isd = torch.empty(N, dtype=torch.uint8, device=dev)
+    full_bc = torch.empty_like(val)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    up_ms = timed(lambda: femhip.fe_assemble_upper(plan, rp_u, node, kappa, f, None, gn, None, 0.0, 0, val_u, vbc_u,
+                                                   b, bl, isd))
+    full_ms = timed(lambda: femhip.fe_assemble(plan, node, kappa, f, None, gn, val, full_bc, b, bl, isd))
+    x = torch.randn(N, dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(3))
+    y = torch.empty_like(x)
+    spmv_ms = timed(lambda: femhip.fe_spmv(rowptr, colind, val, x, y))
+    spmv_sym_ms = timed(lambda: femhip.fe_spmv_sym(rowptr, colind, vidx, val_u, x, y))
+    return {"nnz_upper": nnz_u, "warm_upper_ms": up_ms, "warm_full_ms": full_ms,
+            "spmv_full_us": spmv_ms * 1e3, "spmv_symmetric_us": spmv_sym_ms * 1e3,
+            "matrix_bytes_full": 12 * colind.numel(), "matrix_bytes_symmetric": 8 * nnz_u + 8 * colind.numel()}
 
 
 def bench_batched(args):
@@ -487,6 +531,7 @@ def bench_c3(args):
         femhip.fe_assemble(plan, node, kappa, f, None, gn, val, val_bc, b, b_load, isd)
     e1.record(stream)
     e1.synchronize()
+    sym = symmetric_storage(femhip, torch, plan, node, kappa, f, gn, rowptr, colind, val, N, reps)
     femhip.fe_plan_destroy(plan)
     warm_ms = e0.elapsed_time(e1) / reps
     roof = roofline(kernels, read_counters("kuhn129"), N, NT, nnz, 3, True, cold_ms, warm_ms)
@@ -494,7 +539,7 @@ def bench_c3(args):
     return {"workload": "kuhn129: 129^3 Kuhn cube, lognormal kappa, nodal f, Dirichlet x = 0, 1, Neumann elsewhere",
             "n_node": N, "n_elem": NT, "nnz": nnz, "cold_ms": cold_ms, "cold_elements_per_s": NT / (cold_ms * 1e-3),
             "warm_ms": warm_ms, "warm_elements_per_s": NT / (warm_ms * 1e-3),
-            "k_assemble_3d_us": k3["avg_us"] if k3 else None,
+            "k_assemble_3d_us": k3["avg_us"] if k3 else None, "symmetric_storage": sym,
             "kernels": kernels, "roofline": roof}
 
 
@@ -608,9 +653,31 @@ def bench_adjoint(args):
     _, iters, _ = plan.solve(asm, rtol=rtol)
     torch.cuda.synchronize()
     t_s = time.perf_counter() - t0
+    # the same solve with A_bc in symmetric (upper-triangle) storage
+    N = m.n_node
+    rp_u = torch.empty(N + 1, dtype=torch.int32, device=dev)
+    ci = plan.colind[:plan.nnz]
+    nnz_u = femhip.fe_plan_upper(plan.handle, plan.rowptr, ci, rp_u)
+    ci_u = torch.empty(nnz_u, dtype=torch.int32, device=dev)
+    vidx = torch.empty(plan.nnz, dtype=torch.int32, device=dev)
+    femhip.fe_plan_upper(plan.handle, plan.rowptr, ci, rp_u, ci_u, vidx)
+    val_u = torch.empty(nnz_u, dtype=torch.float64, device=dev)
+    vbc_u = torch.empty_like(val_u)
+    bu = torch.empty(N, dtype=torch.float64, device=dev)
+    isd = torch.empty(N, dtype=torch.uint8, device=dev)
+    femhip.fe_assemble_upper(plan.handle, rp_u, node, kap, f, None, None, None, 0.0, 0, val_u, vbc_u, bu, None, isd)
+    u_sym = torch.empty_like(bu)
+    femhip.fe_select(isd, bu, None, u_sym)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_sym, _, _ = femhip.fe_solve_sym(plan.rowptr, ci, vidx, vbc_u, bu, u_sym, rtol, 100000, plan.solve_workspace())
+    torch.cuda.synchronize()
+    t_sym = time.perf_counter() - t0
     plan.close()
     return {"workload": "1025^2 jittered mesh, lognormal kappa, u_obs from a second kappa, rtol 1e-10",
             "forward_pcg_iterations": int(iters), "us_per_pcg_iteration": t_s / max(int(iters), 1) * 1e6,
+            "symmetric_storage_pcg": {"iterations": it_sym, "ms": t_sym * 1e3,
+                                      "us_per_iteration": t_sym / max(it_sym, 1) * 1e6},
             "ms_forward": t_f * 1e3, "ms_forward_adjoint_grad": t_fb * 1e3, "ratio": t_fb / t_f,
             "ms_grad_kernel": g_ms, "grad_elements_per_s": NT / (g_ms * 1e-3),
             "fd_equivalent_ms": 2 * NT * t_f * 1e3}

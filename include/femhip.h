@@ -190,6 +190,39 @@ int fe_assemble_quad(fe_plan *plan, const double *node, const double *kappa, con
                      int32_t load_rule, double *val, double *val_bc, double *b, double *b_load,
                      uint8_t *is_dirichlet, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Symmetric storage: the upper triangle of A (Section 3.1.3, the remark on
+ * symmetry: the local matrices are symmetric, so the entries j >= i hold A).
+ * ------------------------------------------------------------------------- */
+
+/* The pattern of triu(A) (diagonal included) from the pattern of A (rowptr,
+ * colind from fe_plan_pattern, device): rowptr_u (device, N+1, 16-byte aligned) and
+ * colind_u (device, nnz_u; label order, columns ascending), and vidx (device, nnz):
+ * for every entry q of A's pattern, the position in the upper storage of the entry
+ * (column >= row) or of its mirror across the diagonal (column < row), so A's value
+ * q is val_u[vidx[q]].  Call once with colind_u = vidx = NULL to get *nnz_u (host;
+ * rowptr_u is filled), then with both allocated.  Synchronizes.  FE_EINVAL for NULL
+ * arguments, a misaligned rowptr_u, only one of colind_u and vidx, or a plan whose
+ * pattern was not yet written. */
+int fe_plan_upper(fe_plan *plan, const int32_t *rowptr, const int32_t *colind, int32_t *rowptr_u,
+                  int32_t *colind_u, int32_t *vidx, int64_t *nnz_u, void *stream);
+
+/* As fe_assemble_quad, with the matrices written in the symmetric storage of
+ * fe_plan_upper: val_u[nnz_u] = triu(A), val_bc_u[nnz_u] = triu(A_bc) (nullable).
+ * The values are bitwise those of the same entries of fe_assemble_quad's val and
+ * val_bc; b, b_load and is_dirichlet are the same arrays.  rowptr_u: device, from
+ * fe_plan_upper. */
+int fe_assemble_upper(fe_plan *plan, const int32_t *rowptr_u, const double *node, const double *kappa,
+                      const fe_fn *f, const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r,
+                      double robin_alpha, int32_t load_rule, double *val_u, double *val_bc_u, double *b,
+                      double *b_load, uint8_t *is_dirichlet, void *stream);
+
+/* y = A x for A in symmetric storage: A's pattern (rowptr, colind: n rows, device)
+ * with the values val_u[vidx[q]] (fe_plan_upper).  Row sums run in column order, as
+ * in fe_spmv. */
+int fe_spmv_sym(int64_t n, const int32_t *rowptr, const int32_t *colind, const int32_t *vidx,
+                const double *val_u, const double *x, double *y, void *stream);
+
 /* y = A x for a CSR matrix (device arrays; n rows). */
 int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
             const double *x, double *y, void *stream);
@@ -219,6 +252,13 @@ int fe_solve_workspace_bytes(int64_t n, size_t *bytes);
 int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val,
              const double *b, double *u, double rtol, int32_t maxit, void *ws, size_t ws_bytes,
              int32_t *iters, double *relres, void *stream);
+
+/* fe_solve for A_bc in symmetric storage (val_u = val_bc_u of fe_assemble_upper;
+ * rowptr, colind, vidx as for fe_spmv_sym).  Arguments, workspace, stopping rule,
+ * synchronization and errors as for fe_solve. */
+int fe_solve_sym(int64_t n, const int32_t *rowptr, const int32_t *colind, const int32_t *vidx,
+                 const double *val_u, const double *b, double *u, double rtol, int32_t maxit, void *ws,
+                 size_t ws_bytes, int32_t *iters, double *relres, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): fe_solve without a workspace

@@ -51,6 +51,10 @@ struct AsmArgs {
     // Dirichlet flags
     const int32_t *longk, *elem, *lrowptr;
     const uint8_t *isdl;
+    // upper: only the upper triangle (columns from the diagonal on) is written, to
+    // the symmetric storage whose label-order row starts are urowptr
+    int32_t upper;
+    const int32_t *urowptr;
     double *val, *val_bc, *b, *b_load;
     uint8_t *isd;
     int32_t *status;
@@ -103,15 +107,16 @@ FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, i
     if (A.direct) {
         // label order: A_bc replaces a Dirichlet row by the identity row and zeroes
         // Dirichlet columns (the row record holds the row's Dirichlet-column mask)
-        const int64_t start = A.prowptr[k];
+        const int4 r = A.precp[k];
+        const int diag = (r.y >> 8) & 0xff;
+        const int c0 = A.upper ? diag : 0;                          // first column written
+        const int64_t start = A.upper ? (int64_t)A.urowptr[k] - c0 : A.prowptr[k];
         double *v = A.val + start;
-        for (int c = 0; c < len; ++c) v[c] = acc[c * BLOCK + tid];
+        for (int c = c0; c < len; ++c) v[c] = acc[c * BLOCK + tid];
         if (A.val_bc) {
-            const int4 r = A.precp[k];
-            const int diag = (r.y >> 8) & 0xff;
             const uint64_t dm = (uint64_t)(uint32_t)r.z | ((uint64_t)(uint32_t)r.w << 32);
             double *vb = A.val_bc + start;
-            for (int c = 0; c < len; ++c) {
+            for (int c = c0; c < len; ++c) {
                 double x = acc[c * BLOCK + tid];
                 if (rowd) x = (c == diag) ? 1.0 : 0.0;
                 else if ((dm >> c) & 1ull) x = 0.0;
@@ -124,7 +129,8 @@ FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, i
         return;
     }
     double *row = A.valp + A.prowptr[k] + 2 * (int64_t)k;
-    for (int c = 0; c < len; ++c) row[c] = acc[c * BLOCK + tid];
+    // (the upper form needs the columns from the diagonal on)
+    for (int c = A.upper ? (int)((A.prow_info[k] >> 8) & 0xff) : 0; c < len; ++c) row[c] = acc[c * BLOCK + tid];
     row[len] = rowd ? gdi : bsum - lift;
     row[len + 1] = bsum;
 }
@@ -134,6 +140,9 @@ FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, i
 // output range (fully coalesced stores); each source row is read once, whole.
 // A_bc replaces Dirichlet rows by the identity row and zeroes Dirichlet columns
 // (the row record holds the row's info word and its Dirichlet-column mask).
+// UPPER: only each row's suffix from its diagonal, to the symmetric storage (rowptr
+// is then its row pointer).
+template <bool UPPER>
 __global__ __launch_bounds__(256) void k_values_to_label(int32_t N, const int32_t *__restrict__ rowptr,
                                                          const int4 *__restrict__ rowrec,
                                                          const int32_t *__restrict__ piinv,
@@ -157,6 +166,16 @@ __global__ __launch_bounds__(256) void k_values_to_label(int32_t N, const int32_
             b[i] = bi;
             if (b_load) b_load[i] = bl;
             if (isd) isd[i] = (uint8_t)((rec.y >> 16) & 1);
+            if (UPPER) {
+                // the row from its diagonal on: source, Dirichlet-column mask and the
+                // diagonal's offset (0) shifted to the suffix
+                const int doff = (rec.y >> 8) & 0xff;
+                const uint64_t dm = ((uint64_t)(uint32_t)rec.z | ((uint64_t)(uint32_t)rec.w << 32)) >> doff;
+                rec.x += doff;
+                rec.y &= ~0xff00;
+                rec.z = (int32_t)(uint32_t)dm;
+                rec.w = (int32_t)(uint32_t)(dm >> 32);
+            }
         }
     }
     srec[w][lane] = rec;
@@ -1020,8 +1039,9 @@ __global__ __launch_bounds__(LNB) void k_assemble_long(AsmArgs A)
         __syncthreads();
     }
     if (err) atomicOr(A.status + ST_ERR, err);
-    const int64_t lstart = A.lrowptr[i];
-    for (int c = tid; c < len; c += LNB) {
+    const int c0 = A.upper ? diag : 0;   // first column written
+    const int64_t lstart = A.upper ? (int64_t)A.urowptr[i] - c0 : (int64_t)A.lrowptr[i];
+    for (int c = c0 + tid; c < len; c += LNB) {
         const double x = acc[c];
         A.val[lstart + c] = x;
         if (A.val_bc) A.val_bc[lstart + c] = rowd ? (c == diag ? 1.0 : 0.0) : (A.isdl[cols[c]] ? 0.0 : x);
@@ -1048,10 +1068,11 @@ template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream
 
 }  // namespace
 
-extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
-                                const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
-                                int32_t load_rule, double *val, double *val_bc, double *b, double *b_load,
-                                uint8_t *is_dirichlet, void *stream)
+namespace {
+
+int assemble_impl(fe_plan *plan, const int32_t *urowptr, const double *node, const double *kappa, const fe_fn *f,
+                  const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha, int32_t load_rule,
+                  double *val, double *val_bc, double *b, double *b_load, uint8_t *is_dirichlet, void *stream)
 {
     if (!plan || !node || !val || !b) return FE_EINVAL;
     if (load_rule != FE_LOAD_DEFAULT && load_rule != FE_LOAD_CENTROID && load_rule != FE_LOAD_TRAPEZOID)
@@ -1086,6 +1107,8 @@ extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double 
     A.elem = plan->elem;
     A.lrowptr = plan->l1_agg ? plan->prowptr : plan->rowlen;   // label-order row starts
     A.isdl = plan->isd;
+    A.upper = urowptr != nullptr;
+    A.urowptr = urowptr;
     A.val = val;
     A.val_bc = val_bc;
     A.b = b;
@@ -1120,11 +1143,39 @@ extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double 
         if ((rc = fe_launch_check())) return rc;
     }
     if (A.direct) return FE_OK;   // rows already in label order
-    FE_TIMED("k_values_to_label", s,
-             hipLaunchKernelGGL(k_values_to_label, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,
-                           (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,
-                           (const double *)plan->valp, val, val_bc, b, b_load, is_dirichlet));
+    if (A.upper)
+        FE_TIMED("k_values_to_label", s,
+                 hipLaunchKernelGGL(k_values_to_label<true>, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,
+                                    urowptr, (const int4 *)plan->rowrec, (const int32_t *)plan->piinv,
+                                    (const double *)plan->valp, val, val_bc, b, b_load, is_dirichlet));
+    else
+        FE_TIMED("k_values_to_label", s,
+                 hipLaunchKernelGGL(k_values_to_label<false>, dim3((unsigned)cdiv(A.N, 256)), dim3(256), 0, s, A.N,
+                                    (const int32_t *)plan->rowlen, (const int4 *)plan->rowrec,
+                                    (const int32_t *)plan->piinv, (const double *)plan->valp, val, val_bc, b, b_load,
+                                    is_dirichlet));
     return fe_launch_check();
+}
+
+}  // namespace
+
+extern "C" int fe_assemble_quad(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,
+                                const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r, double robin_alpha,
+                                int32_t load_rule, double *val, double *val_bc, double *b, double *b_load,
+                                uint8_t *is_dirichlet, void *stream)
+{
+    return assemble_impl(plan, nullptr, node, kappa, f, g_d, g_n, g_r, robin_alpha, load_rule, val, val_bc, b, b_load,
+                         is_dirichlet, stream);
+}
+
+extern "C" int fe_assemble_upper(fe_plan *plan, const int32_t *rowptr_u, const double *node, const double *kappa,
+                                 const fe_fn *f, const fe_fn *g_d, const fe_fn *g_n, const fe_fn *g_r,
+                                 double robin_alpha, int32_t load_rule, double *val_u, double *val_bc_u, double *b,
+                                 double *b_load, uint8_t *is_dirichlet, void *stream)
+{
+    if (!rowptr_u) return FE_EINVAL;
+    return assemble_impl(plan, rowptr_u, node, kappa, f, g_d, g_n, g_r, robin_alpha, load_rule, val_u, val_bc_u, b,
+                         b_load, is_dirichlet, stream);
 }
 
 extern "C" int fe_assemble_robin(fe_plan *plan, const double *node, const double *kappa, const fe_fn *f,

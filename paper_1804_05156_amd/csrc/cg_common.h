@@ -8,16 +8,26 @@
 
 constexpr int CG_UNIT = 256;   // rows per reduction unit (= threads per block)
 
+// Stored value of entry q of the pattern: val[q], or with IND (symmetric storage of
+// the upper triangle) val[vidx[q]], the entry itself or its mirror across the
+// diagonal.
+template <bool IND> FE_DEV double cg_value(const double *__restrict__ val, const int32_t *__restrict__ vidx, int32_t q)
+{
+    return IND ? val[vidx[q]] : val[q];
+}
+
 // Row i at the start: r_i = b_i - (A x)_i and the diagonal entry.
+template <bool IND = false>
 FE_DEV void cg_init_row(int32_t i, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colind,
                         const double *__restrict__ val, const double *__restrict__ b, const double *__restrict__ x,
-                        double *ri, double *di)
+                        double *ri, double *di, const int32_t *__restrict__ vidx = nullptr)
 {
     double s = 0.0, d = 0.0;
     for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) {
         const int32_t c = colind[q];
-        s += val[q] * x[c];
-        if (c == i) d = val[q];
+        const double v = cg_value<IND>(val, vidx, q);
+        s += v * x[c];
+        if (c == i) d = v;
     }
     *di = d;
     *ri = b[i] - s;
@@ -29,10 +39,11 @@ FE_DEV void cg_init_row(int32_t i, const int32_t *__restrict__ rowptr, const int
 // of z and p_old, then the products are added in column order, so the loads of a
 // chunk overlap instead of forming one dependent chain per entry.  The products are
 // added in column order whatever CH is, so CH never changes a result bit.
-template <int K, int CH = (K >= 4 ? 2 : (K == 2 ? 4 : 8))>
+template <int K, int CH = (K >= 4 ? 2 : (K == 2 ? 4 : 8)), bool IND = false>
 FE_DEV void cg_apply_rows(const int32_t *i, const bool *ok, const int32_t *__restrict__ rowptr,
                           const int32_t *__restrict__ colind, const double *__restrict__ val,
-                          const double *__restrict__ z, const double *__restrict__ pold, const double *beta, double *s)
+                          const double *__restrict__ z, const double *__restrict__ pold, const double *beta, double *s,
+                          const int32_t *__restrict__ vidx = nullptr)
 {
     int32_t q[K], e[K];
     int32_t len = 0;
@@ -52,7 +63,7 @@ FE_DEV void cg_apply_rows(const int32_t *i, const bool *ok, const int32_t *__res
             for (int t = 0; t < CH; ++t)
                 if (q[j] + m0 + t < e[j]) {
                     c[j][t] = colind[q[j] + m0 + t];
-                    v[j][t] = val[q[j] + m0 + t];
+                    v[j][t] = cg_value<IND>(val, vidx, q[j] + m0 + t);
                 }
 #pragma unroll
         for (int j = 0; j < K; ++j)

@@ -67,30 +67,34 @@ size_t ws_layout(int64_t n, SolveWs *w, char *base)
     return o;
 }
 
+template <bool IND>
 __global__ __launch_bounds__(SB) void k_spmv(int32_t n, const int32_t *__restrict__ rowptr,
                                              const int32_t *__restrict__ colind, const double *__restrict__ val,
-                                             const double *__restrict__ x, double *__restrict__ y)
+                                             const double *__restrict__ x, double *__restrict__ y,
+                                             const int32_t *__restrict__ vidx)
 {
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) s += val[q] * x[colind[q]];
+    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) s += cg_value<IND>(val, vidx, q) * x[colind[q]];
     y[i] = s;
 }
 
 // diag(A)^-1, r = b - A x, z = r * dinv, p_old = 0; partials r.z, r.r, b.b.
+// IND: values through vidx (symmetric upper-triangle storage), here and below.
+template <bool IND>
 __global__ __launch_bounds__(SB) void k_cg_init(int32_t n, const int32_t *__restrict__ rowptr,
                                                 const int32_t *__restrict__ colind, const double *__restrict__ val,
                                                 const double *__restrict__ b, const double *__restrict__ x,
                                                 double *r, double *z, double *p0, double *dinv, double *part,
-                                                int32_t *flag)
+                                                int32_t *flag, const int32_t *__restrict__ vidx)
 {
     __shared__ double lds[SB / 64];
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     double rz = 0.0, rr = 0.0, bb = 0.0;
     if (i < n) {
         double ri, d;
-        cg_init_row(i, rowptr, colind, val, b, x, &ri, &d);
+        cg_init_row<IND>(i, rowptr, colind, val, b, x, &ri, &d, vidx);
         if (!(d > 0.0)) atomicOr(flag + F_BAD, 1);
         const double di = 1.0 / d;
         dinv[i] = di;
@@ -134,11 +138,13 @@ __global__ __launch_bounds__(SB) void k_cg_init_sum(int32_t nb, const double *pa
 }
 
 // p = z + beta p_old; q = A p (as A z + beta A p_old); partial p.q.
+template <bool IND>
 __global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restrict__ rowptr,
                                              const int32_t *__restrict__ colind, const double *__restrict__ val,
                                              const double *__restrict__ z, const double *__restrict__ pold,
                                              double *__restrict__ pnew, double *__restrict__ qv, double *part,
-                                             const double *scal, const int32_t *flag)
+                                             const double *scal, const int32_t *flag,
+                                             const int32_t *__restrict__ vidx)
 {
     __shared__ double lds[SB / 64];
     if (*(volatile const int32_t *)(flag + F_DONE)) return;
@@ -148,7 +154,7 @@ __global__ __launch_bounds__(SB) void k_cg_a(int32_t n, const int32_t *__restric
     if (i < n) {
         const bool ok = true;
         double s;
-        cg_apply_rows<1>(&i, &ok, rowptr, colind, val, z, pold, &beta, &s);
+        cg_apply_rows<1, 8, IND>(&i, &ok, rowptr, colind, val, z, pold, &beta, &s, vidx);
         const double pi = z[i] + beta * pold[i];
         pnew[i] = pi;
         qv[i] = s;
@@ -218,12 +224,13 @@ __global__ __launch_bounds__(SB) void k_cg_b_sum(int32_t nb, const double *part,
 // Fused K_A of iteration it: r.z and r.r of the previous K_B from its partials,
 // beta and the stopping test (recorded by block 0), then p = z + beta p_old,
 // q = A p and the partial p.q.  check_only: record the stopping test and stop.
+template <bool IND>
 __global__ __launch_bounds__(SB) void k_cg_a_fused(int32_t n, int32_t it, int32_t check_only,
                                                    const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ colind, const double *__restrict__ val,
                                                    const double *__restrict__ z, const double *__restrict__ pold,
                                                    double *__restrict__ pnew, double *__restrict__ qv, double *part,
-                                                   double *scal, int32_t *flag)
+                                                   double *scal, int32_t *flag, const int32_t *__restrict__ vidx)
 {
     __shared__ double lds[SB / 64];
     __shared__ double bc[2];
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(SB) void k_cg_a_fused(int32_t n, int32_t it, int32_
     if (i < n) {
         const bool ok = true;
         double sv;
-        cg_apply_rows<1>(&i, &ok, rowptr, colind, val, z, pold, &beta, &sv);
+        cg_apply_rows<1, 8, IND>(&i, &ok, rowptr, colind, val, z, pold, &beta, &sv, vidx);
         const double pi = z[i] + beta * pold[i];
         pnew[i] = pi;
         qv[i] = sv;
@@ -317,8 +324,20 @@ extern "C" int fe_spmv(int64_t n, const int32_t *rowptr, const int32_t *colind, 
     if (n == 0) return FE_OK;
     if (!rowptr || !colind || !val || !x || !y) return FE_EINVAL;
     FE_TIMED("k_spmv", static_cast<hipStream_t>(stream),
-             hipLaunchKernelGGL(k_spmv, dim3((unsigned)cdiv(n, SB)), dim3(SB), 0, static_cast<hipStream_t>(stream),
-                           (int32_t)n, rowptr, colind, val, x, y));
+             hipLaunchKernelGGL(k_spmv<false>, dim3((unsigned)cdiv(n, SB)), dim3(SB), 0,
+                                static_cast<hipStream_t>(stream), (int32_t)n, rowptr, colind, val, x, y, nullptr));
+    return fe_launch_check();
+}
+
+extern "C" int fe_spmv_sym(int64_t n, const int32_t *rowptr, const int32_t *colind, const int32_t *vidx,
+                           const double *val_u, const double *x, double *y, void *stream)
+{
+    if (n < 0 || n >= INT32_MAX) return FE_EINVAL;
+    if (n == 0) return FE_OK;
+    if (!rowptr || !colind || !vidx || !val_u || !x || !y) return FE_EINVAL;
+    FE_TIMED("k_spmv_sym", static_cast<hipStream_t>(stream),
+             hipLaunchKernelGGL(k_spmv<true>, dim3((unsigned)cdiv(n, SB)), dim3(SB), 0,
+                                static_cast<hipStream_t>(stream), (int32_t)n, rowptr, colind, val_u, x, y, vidx));
     return fe_launch_check();
 }
 
@@ -330,17 +349,18 @@ extern "C" int fe_solve_workspace_bytes(int64_t n, size_t *bytes)
 }
 
 // The iteration itself, on a workspace already laid out by ws_layout.
+template <bool IND>
 static int solve_run(int64_t n, const int32_t *rowptr, const int32_t *colind, const double *val, const double *b,
                      double *u, double rtol, int32_t maxit, const SolveWs &W, int32_t *iters, double *relres,
-                     hipStream_t s)
+                     hipStream_t s, const int32_t *vidx)
 {
     const int32_t nn = (int32_t)n;
     const unsigned nb = (unsigned)cdiv(n, SB);
     int rc;
     if ((rc = fe_fill_i32(W.flag, F_NFLAG, 0, s))) return rc;
     FE_TIMED("k_cg_init", s,
-             hipLaunchKernelGGL(k_cg_init, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, b, (const double *)u,
-                                W.r, W.z, W.p0, W.dinv, W.part, W.flag));
+             hipLaunchKernelGGL(k_cg_init<IND>, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val, b,
+                                (const double *)u, W.r, W.z, W.p0, W.dinv, W.part, W.flag, vidx));
     FE_TIMED("k_cg_init_sum", s,
              hipLaunchKernelGGL(k_cg_init_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part, W.scal,
                                 W.flag, rtol));
@@ -363,18 +383,18 @@ static int solve_run(int64_t n, const int32_t *rowptr, const int32_t *colind, co
             if (fused) {
                 const int32_t it = launched + c;
                 FE_TIMED("k_cg_a_fused", s,
-                         hipLaunchKernelGGL(k_cg_a_fused, dim3(nb), dim3(SB), 0, s, nn, it, 0, rowptr, colind, val,
+                         hipLaunchKernelGGL(k_cg_a_fused<IND>, dim3(nb), dim3(SB), 0, s, nn, it, 0, rowptr, colind, val,
                                             (const double *)W.z, (const double *)pold, pnew, W.q, W.part, W.scal,
-                                            W.flag));
+                                            W.flag, vidx));
                 FE_TIMED("k_cg_b_fused", s,
                          hipLaunchKernelGGL(k_cg_b_fused, dim3(nb), dim3(SB), 0, s, nn, it, u, (const double *)pnew,
                                             (const double *)W.q, W.r, W.z, (const double *)W.dinv, W.part, W.scal,
                                             W.flag));
             } else {
                 FE_TIMED("k_cg_a", s,
-                         hipLaunchKernelGGL(k_cg_a, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val,
+                         hipLaunchKernelGGL(k_cg_a<IND>, dim3(nb), dim3(SB), 0, s, nn, rowptr, colind, val,
                                             (const double *)W.z, (const double *)pold, pnew, W.q, W.part,
-                                            (const double *)W.scal, (const int32_t *)W.flag));
+                                            (const double *)W.scal, (const int32_t *)W.flag, vidx));
                 FE_TIMED("k_cg_a_sum", s,
                          hipLaunchKernelGGL(k_cg_a_sum, dim3(1), dim3(SB), 0, s, (int32_t)nb, (const double *)W.part,
                                             W.scal, (const int32_t *)W.flag));
@@ -393,9 +413,9 @@ static int solve_run(int64_t n, const int32_t *rowptr, const int32_t *colind, co
         if (fused && launched >= maxit) {
             // the stopping test after the last iteration (no further work)
             FE_TIMED("k_cg_a_fused", s,
-                     hipLaunchKernelGGL(k_cg_a_fused, dim3(nb), dim3(SB), 0, s, nn, launched, 1, rowptr, colind, val,
-                                        (const double *)W.z, (const double *)W.p0, W.p1, W.q, W.part, W.scal,
-                                        W.flag));
+                     hipLaunchKernelGGL(k_cg_a_fused<IND>, dim3(nb), dim3(SB), 0, s, nn, launched, 1, rowptr, colind,
+                                        val, (const double *)W.z, (const double *)W.p0, W.p1, W.q, W.part, W.scal,
+                                        W.flag, vidx));
             if ((rc = fe_launch_check())) return rc;
         }
     }
@@ -422,7 +442,21 @@ extern "C" int fe_solve(int64_t n, const int32_t *rowptr, const int32_t *colind,
     SolveWs W;
     const size_t need = ws_layout(n, &W, static_cast<char *>(ws));
     if (ws_bytes < need) return FE_ESIZE;
-    return solve_run(n, rowptr, colind, val, b, u, rtol, maxit, W, iters, relres, static_cast<hipStream_t>(stream));
+    return solve_run<false>(n, rowptr, colind, val, b, u, rtol, maxit, W, iters, relres,
+                            static_cast<hipStream_t>(stream), nullptr);
+}
+
+extern "C" int fe_solve_sym(int64_t n, const int32_t *rowptr, const int32_t *colind, const int32_t *vidx,
+                            const double *val_u, const double *b, double *u, double rtol, int32_t maxit, void *ws,
+                            size_t ws_bytes, int32_t *iters, double *relres, void *stream)
+{
+    if (!solve_args_ok(n, rowptr, colind, val_u, b, u, rtol, maxit, iters, relres) || !vidx || !ws) return FE_EINVAL;
+    if ((uintptr_t)ws & 255) return FE_EINVAL;
+    SolveWs W;
+    const size_t need = ws_layout(n, &W, static_cast<char *>(ws));
+    if (ws_bytes < need) return FE_ESIZE;
+    return solve_run<true>(n, rowptr, colind, val_u, b, u, rtol, maxit, W, iters, relres,
+                           static_cast<hipStream_t>(stream), vidx);
 }
 
 // ---------------------------------------------------------------------------
@@ -475,5 +509,6 @@ extern "C" int fe_solve_noalloc(int64_t n, const int32_t *rowptr, const int32_t 
     if (rc) return rc;
     SolveWs W;
     ws_layout(n, &W, static_cast<char *>(base));
-    return solve_run(n, rowptr, colind, val, b, u, rtol, maxit, W, iters, relres, static_cast<hipStream_t>(stream));
+    return solve_run<false>(n, rowptr, colind, val, b, u, rtol, maxit, W, iters, relres,
+                            static_cast<hipStream_t>(stream), nullptr);
 }

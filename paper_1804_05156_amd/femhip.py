@@ -26,7 +26,7 @@ FE_LOAD_DEFAULT, FE_LOAD_CENTROID, FE_LOAD_TRAPEZOID = range(3)
 ENTRY_POINTS = (
     "fe_version", "fe_status_string", "fe_plan_workspace_bytes", "fe_plan_create", "fe_plan_pattern",
     "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_assemble_robin",
-    "fe_assemble_quad", "fe_spmv",
+    "fe_assemble_quad", "fe_plan_upper", "fe_assemble_upper", "fe_spmv_sym", "fe_solve_sym", "fe_spmv",
     "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_solve_noalloc", "fe_neumann_workspace_bytes", "fe_neumann_solve",
     "fe_grad", "fe_batch_solve_workspace_bytes",
     "fe_batch_solve", "fe_batch_create", "fe_batch_set_grid", "fe_batch_get_info", "fe_batch_assemble_solve",
@@ -89,6 +89,11 @@ def _load():
         "fe_assemble_quad": ([P, P, P, C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), D,
                               I32, P, P, P, P, P, P], C.c_int),
         "fe_spmv": ([I64, P, P, P, P, P, P], C.c_int),
+        "fe_plan_upper": ([P, P, P, P, P, P, C.POINTER(I64), P], C.c_int),
+        "fe_assemble_upper": ([P, P, P, P, C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), C.POINTER(fe_fn), D,
+                               I32, P, P, P, P, P, P], C.c_int),
+        "fe_spmv_sym": ([I64, P, P, P, P, P, P, P], C.c_int),
+        "fe_solve_sym": ([I64, P, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), P], C.c_int),
         "fe_solve_workspace_bytes": ([I64, C.POINTER(SZ)], C.c_int),
         "fe_solve": ([I64, P, P, P, P, P, D, I32, P, SZ, C.POINTER(I32), C.POINTER(D), P], C.c_int),
         "fe_solve_noalloc": ([I64, P, P, P, P, P, D, I32, C.POINTER(I32), C.POINTER(D), P], C.c_int),
@@ -246,6 +251,43 @@ def fe_spmv(rowptr, colind, val, x, y, stream=None):
     _check(_lib.fe_spmv(rowptr.numel() - 1, _ptr(rowptr, torch.int32), _ptr(colind, torch.int32),
                         _ptr(val, torch.float64), _ptr(x, torch.float64), _ptr(y, torch.float64), _stream(stream)),
            "fe_spmv")
+
+
+def fe_plan_upper(plan, rowptr, colind, rowptr_u, colind_u=None, vidx=None, stream=None) -> int:
+    """Pattern of triu(A) and the value index of A's entries into it; returns nnz_u.
+    With colind_u = vidx = None only rowptr_u is written (to size the others)."""
+    n = C.c_int64()
+    _check(_lib.fe_plan_upper(plan, _ptr(rowptr, torch.int32, "rowptr"), _ptr(colind, torch.int32, "colind"),
+                              _ptr(rowptr_u, torch.int32, "rowptr_u"), _ptr(colind_u, torch.int32, "colind_u"),
+                              _ptr(vidx, torch.int32, "vidx"), C.byref(n), _stream(stream)), "fe_plan_upper")
+    return int(n.value)
+
+
+def fe_assemble_upper(plan, rowptr_u, node, kappa, f: Fn | None, gD: Fn | None, gN: Fn | None, gR: Fn | None,
+                      robin_alpha: float, load_rule: int, val_u, val_bc_u, b, b_load, is_d, stream=None):
+    _check(_lib.fe_assemble_upper(plan, _ptr(rowptr_u, torch.int32, "rowptr_u"), _ptr(node, torch.float64, "node"),
+                                  _ptr(kappa, torch.float64, "kappa"), _fnref(f), _fnref(gD), _fnref(gN), _fnref(gR),
+                                  float(robin_alpha), int(load_rule), _ptr(val_u, torch.float64, "val_u"),
+                                  _ptr(val_bc_u, torch.float64, "val_bc_u"), _ptr(b, torch.float64, "b"),
+                                  _ptr(b_load, torch.float64, "b_load"), _ptr(is_d, torch.uint8, "is_dirichlet"),
+                                  _stream(stream)), "fe_assemble_upper")
+
+
+def fe_spmv_sym(rowptr, colind, vidx, val_u, x, y, stream=None):
+    _check(_lib.fe_spmv_sym(rowptr.numel() - 1, _ptr(rowptr, torch.int32), _ptr(colind, torch.int32),
+                            _ptr(vidx, torch.int32), _ptr(val_u, torch.float64), _ptr(x, torch.float64),
+                            _ptr(y, torch.float64), _stream(stream)), "fe_spmv_sym")
+
+
+def fe_solve_sym(rowptr, colind, vidx, val_u, b, u, rtol: float, maxit: int, ws, stream=None):
+    it = C.c_int32()
+    rel = C.c_double()
+    rc = _lib.fe_solve_sym(rowptr.numel() - 1, _ptr(rowptr, torch.int32), _ptr(colind, torch.int32),
+                           _ptr(vidx, torch.int32), _ptr(val_u, torch.float64), _ptr(b, torch.float64),
+                           _ptr(u, torch.float64), float(rtol), int(maxit), _ptr(ws, torch.uint8, "ws"), ws.numel(),
+                           C.byref(it), C.byref(rel), _stream(stream))
+    _check(rc, "fe_solve_sym")
+    return int(it.value), float(rel.value), rc
 
 
 def fe_select(mask, a, b, out, stream=None):
