@@ -32,6 +32,7 @@ struct AsmArgs {
     const double *kappa;
     const int32_t *pi, *pincptr, *prowptr, *elemp;
     const int2 *pincm;
+    const int32_t *sptr;   // 3-D sliced incidence layout (status[ST_SELL]; see inc_at)
     const uint32_t *prow_info;
     const double *xyp, *fp;
     DevFn f, gd, gn, gr;
@@ -510,6 +511,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) fvert = nodal_f ? fi : fn_point<3>(A.f, Y0);
     const uint32_t BND = (7u << Meta<4>::NBIT) | (7u << Meta<4>::RBIT) |
                          (A.gd.kind != FE_FN_ZERO ? 7u << Meta<4>::DBIT : 0u);
+    const bool sell = A.status[ST_SELL] != 0;
     uint32_t bmask = 0;
     for (int32_t p0 = s; p0 < e; p0 += UNR) {
         int2 km[UNR];
@@ -519,7 +521,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
         double Y[UNR][3][3], F[UNR][3];   // F: nodal f at the other vertices
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
-            if (p0 + u < e) km[u] = A.pincm[p0 + u];
+            if (p0 + u < e) km[u] = A.pincm[inc_at(sell, A.sptr, s, k, p0 - s + u)];
 #pragma unroll
         for (int u = 0; u < UNR; ++u)
             if (p0 + u < e) {
@@ -613,7 +615,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     // bit, as in 2-D.
     if (bmask & BND) {
         for (int32_t p = s; p < e; ++p) {
-            const int2 kmv = A.pincm[p];
+            const int2 kmv = A.pincm[inc_at(sell, A.sptr, s, k, p - s)];
             const uint32_t meta = (uint32_t)kmv.y;
             if (!(meta & BND)) continue;
             const int32_t t = kmv.x >> 2;
@@ -769,6 +771,7 @@ __global__ __launch_bounds__(LNB) void k_assemble_long(AsmArgs A)
     const bool rowd = (rec.y >> 16) & 1;
     const int32_t i = A.pi[k];
     const int32_t nc = DIM * d + 1;
+    const bool sell = NV == 4 && A.status[ST_SELL] != 0;
     if (nc > LCAND || len > nc) {
         if (tid == 0) atomicOr(A.status + ST_ERR, ERR_LIMIT);
         return;
@@ -777,7 +780,7 @@ __global__ __launch_bounds__(LNB) void k_assemble_long(AsmArgs A)
     int32_t M = 1;
     while (M < nc) M <<= 1;
     for (int32_t j = tid; j < d; j += LNB) {
-        const int32_t key = A.pincm[s + j].x;
+        const int32_t key = A.pincm[inc_at(sell, A.sptr, s, k, j)].x;
         const int32_t t = key / NV;
         const int a = key - t * NV;
 #pragma unroll
@@ -833,7 +836,7 @@ __global__ __launch_bounds__(LNB) void k_assemble_long(AsmArgs A)
     for (int32_t c0 = 0; c0 < d; c0 += LNB) {
         const int32_t j = c0 + tid;
         if (j < d) {
-            const int2 km = A.pincm[s + j];
+            const int2 km = A.pincm[inc_at(sell, A.sptr, s, k, j)];
             const int32_t t = km.x / NV;
             const int a = km.x - t * NV;
             const uint32_t meta = (uint32_t)km.y;
@@ -1090,6 +1093,7 @@ int assemble_impl(fe_plan *plan, const int32_t *urowptr, const double *node, con
     A.prowptr = plan->prowptr;
     A.elemp = plan->elemp;
     A.pincm = plan->pincm;
+    A.sptr = plan->sptr;
     A.prow_info = plan->prow_info;
     A.xyp = plan->xyp;
     A.fp = plan->fp;

@@ -512,6 +512,7 @@ struct RowArgs {
     int2 *rmask;          // 3-D label-order register form: each row's Dirichlet-column mask
     int32_t *longk;       // LDS form, count: long rows appended here
     int32_t nlcap;
+    const int32_t *sptr;  // 3-D sliced incidence layout (status[ST_SELL])
     int32_t *status;
 };
 
@@ -729,6 +730,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     auto meta_walk = [&]() -> uint64_t {
         uint64_t dmask = 0;
         const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
+        const bool sell = NV == 4 && R.status[ST_SELL] != 0;
         for (int32_t j0 = 0; j0 < d; j0 += RUNR) {
             int32_t key[RUNR];
             int4 ep[RUNR];
@@ -778,7 +780,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                         if (code[q][jj] == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
                         if (code[q][jj] == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
                     }
-                    R.pincm[s + j0 + q] = make_int2(key[q], (int32_t)meta);
+                    R.pincm[inc_at(sell, R.sptr, s, k, j0 + q)] = make_int2(key[q], (int32_t)meta);
                 }
         }
         return dmask;
@@ -816,6 +818,25 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     const uint32_t info = (uint32_t)u | ((uint32_t)diag << 8) | ((uint32_t)(R.isdp[k] ? 1 : 0) << 16);
     R.prow_info[k] = info;
     R.precp[k] = make_int4(ps, (int32_t)info, (int32_t)(uint32_t)dmask, (int32_t)(uint32_t)(dmask >> 32));
+}
+
+// Sliced incidence layout (3-D): SELLW times the longest row of each slice of SELLW
+// processing positions (then scanned into slice starts), and the choice of layout
+// once the padded total is known.
+__global__ __launch_bounds__(256) void k_sell_len(int32_t N, const int32_t *__restrict__ pincptr, int32_t *sptr)
+{
+    const int32_t sl = blockIdx.x * 256 + threadIdx.x;
+    const int32_t k0 = sl * SELLW;
+    if (k0 >= N) return;
+    const int32_t k1 = min(N, k0 + SELLW);
+    int32_t m = 0;
+    for (int32_t k = k0; k < k1; ++k) m = max(m, pincptr[k + 1] - pincptr[k]);
+    sptr[sl] = SELLW * m;
+}
+
+__global__ void k_sell_choose(const int64_t *__restrict__ total, int64_t cap, int32_t *status)
+{
+    status[ST_SELL] = (status[ST_SELLERR] == 0 && *total <= cap) ? 1 : 0;
 }
 
 // Long rows: rows with more columns than the LDS column set holds (a vertex with
@@ -907,6 +928,7 @@ __global__ __launch_bounds__(LB) void k_rows_long(RowArgs R)
             __syncthreads();
             continue;
         }
+        const bool sell = NV == 4 && R.status[ST_SELL] != 0;
         for (int32_t j = threadIdx.x; j < d; j += LB) {
             const int32_t key = klist[src + j];
             const int32_t t = key / NV;
@@ -921,7 +943,7 @@ __global__ __launch_bounds__(LB) void k_rows_long(RowArgs R)
                 if (code == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
                 if (code == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
             }
-            R.pincm[s + j] = make_int2(key, (int32_t)meta);
+            R.pincm[inc_at(sell, R.sptr, s, k, j)] = make_int2(key, (int32_t)meta);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -1084,6 +1106,15 @@ Buckets choose_buckets(int64_t N, int64_t NT, int nv)
     return B;
 }
 
+// Capacity of pincm: the incidences, and in 3-D a quarter more for the padding of
+// the sliced layout (a mesh whose padded size exceeds it keeps the row-major one).
+int64_t pincm_cap(int64_t ninc, int nv)
+{
+    if (nv != 4) return ninc;
+    const int64_t c = ninc + ninc / 4 + (int64_t)SELLW * SELLW;
+    return c < (int64_t)INT32_MAX ? c : (int64_t)INT32_MAX;
+}
+
 // Upper bound of the number of stored entries: every element adds at most
 // nv*(nv-1) off-diagonal entries.
 int64_t nnz_bound(int64_t N, int64_t NT, int nv) { return N + NT * nv * (nv - 1); }
@@ -1101,7 +1132,7 @@ int64_t long_cap(int64_t N, int64_t NT, int nv)
 enum {
     W_STATUS, W_TOTALS, W_PART, W_VINFO, W_INCLP, W_ISD, W_ISDP, W_OWNF, W_HIST1, W_OWNCNT, W_PI, W_PIINV,
     W_PINCPTR, W_PINC, W_PINCM, W_ELEMP, W_ROWLEN, W_PROWPTR, W_PROWINFO, W_PRECP, W_ROWREC, W_XYP, W_FP,
-    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_RSLOT, W_RMASK, W_LONGK, W_COUNT
+    W_VALP, W_STATPART, W_SORTED, W_PAIRS2, W_FSTART, W_RSLOT, W_RMASK, W_LONGK, W_SPTR, W_COUNT
 };
 
 struct Layout {
@@ -1135,7 +1166,7 @@ Layout plan_layout(int64_t N, int64_t NT, int nv)
     sz[W_PIINV] = sizeof(int32_t) * (size_t)N;
     sz[W_PINCPTR] = sizeof(int32_t) * (size_t)(N + 1);
     sz[W_PINC] = sizeof(int32_t) * (size_t)ninc;
-    sz[W_PINCM] = sizeof(int2) * (size_t)ninc;
+    sz[W_PINCM] = sizeof(int2) * (size_t)pincm_cap(ninc, nv);
     sz[W_ELEMP] = sizeof(int32_t) * 4 * (size_t)NT;
     sz[W_ROWLEN] = sizeof(int32_t) * (size_t)(N + 1);
     sz[W_PROWPTR] = sizeof(int32_t) * (size_t)(N + 1);
@@ -1152,6 +1183,7 @@ Layout plan_layout(int64_t N, int64_t NT, int nv)
     sz[W_RMASK] = nv == 4 ? sizeof(int2) * (size_t)N : 0;
     sz[W_RSLOT] = nv == 4 ? sizeof(int32_t) * (size_t)REGCAP * (size_t)N : 0;   // 3-D row slots
     sz[W_LONGK] = sizeof(int32_t) * (size_t)long_cap(N, NT, nv);
+    sz[W_SPTR] = nv == 4 ? sizeof(int32_t) * (size_t)(cdiv(N, SELLW) + 1) : 0;
     Layout L{};
     size_t o = 0;
     for (int k = 0; k < W_COUNT; ++k) {
@@ -1196,6 +1228,7 @@ RowArgs row_args(fe_plan *P)
     R.rmask = P->rmask;
     R.longk = P->longk;
     R.nlcap = P->nlcap;
+    R.sptr = P->sptr;
     R.status = P->status;
     return R;
 }
@@ -1321,6 +1354,19 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                                     P->status));
         if ((rc = fe_launch_check())) return rc;
         if ((rc = fe_scan_exclusive(P->pincptr, P->pincptr, N, P->totals + 1, P->part, P->status, s))) return rc;
+    }
+    if (NV == 4) {
+        // the sliced incidence layout, if its padded size fits pincm (its scan may
+        // overflow int32 for huge meshes: that only rules the layout out)
+        const int64_t nsl = cdiv(N, SELLW);
+        FE_TIMED("k_sell_len", s,
+                 hipLaunchKernelGGL(k_sell_len, dim3((unsigned)cdiv(nsl, 256)), dim3(256), 0, s, N,
+                                    (const int32_t *)P->pincptr, P->sptr));
+        if ((rc = fe_scan_exclusive(P->sptr, P->sptr, nsl, P->totals + 6, P->part, P->status + ST_SELLERR, s)))
+            return rc;
+        hipLaunchKernelGGL(k_sell_choose, dim3(1), dim3(1), 0, s, (const int64_t *)(P->totals + 6),
+                           pincm_cap(P->ninc, NV), P->status);
+        if ((rc = fe_launch_check())) return rc;
     }
     const RowArgs R = row_args(P);
     // the row pass with the register column set; rows too long for it make the pass
@@ -1479,6 +1525,7 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     P->rslot = reinterpret_cast<int4 *>(base + L.off[W_RSLOT]);
     P->rmask = reinterpret_cast<int2 *>(base + L.off[W_RMASK]);
     P->longk = reinterpret_cast<int32_t *>(base + L.off[W_LONGK]);
+    P->sptr = reinterpret_cast<int32_t *>(base + L.off[W_SPTR]);
     P->nlcap = (int32_t)long_cap(mesh->n_node, mesh->n_elem, nv);
     P->nlong = 0;
     P->nnz_max = nnz_bound(mesh->n_node, mesh->n_elem, nv);
