@@ -137,6 +137,13 @@ int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe_plan **pla
  * structurally symmetric, so these arrays are also its compressed-column pattern. */
 int fe_plan_pattern(fe_plan *plan, int32_t *rowptr, int32_t *colind, void *stream);
 
+/* Launch setting of the numeric phase: rows per workgroup of the row kernels of
+ * fe_assemble* (64, 128 or 256; 0 = the default, the widest block whose row
+ * accumulators fit 32 KB of LDS).  Results do not depend on it (each row is summed
+ * by one thread in a fixed order).  Host only; a batch built on this plan recaptures
+ * its graph on its next call.  FE_EINVAL for other values. */
+int fe_plan_set_launch(fe_plan *plan, int32_t rows_per_block);
+
 /* Fill *info (host). */
 int fe_plan_get_info(const fe_plan *plan, fe_plan_info *info);
 
@@ -330,7 +337,8 @@ int fe_batch_solve_workspace_bytes(int64_t n, int32_t n_inst, size_t *bytes);
  * must not couple to other rows.  u: x0 on entry, solutions on return.  Instance k
  * stops when its recurrence residual drops to rtol times ||b_k||_2, or after maxit
  * iterations.  blocks_per_cu: workgroups per compute unit of the persistent grid
- * (0 picks a default; above what fits, FE_EINVAL); units_per_step: 256-row units
+ * (0 picks a default; above what fits, or above 4, the most verified co-resident on
+ * MI355X, FE_EINVAL); units_per_step: 256-row units
  * each workgroup processes together (1, 2 or 4; 0 picks a default).  Neither
  * changes any result bit.  iters, relres: host arrays of
  * n_inst (may be NULL).  ws: 256-byte aligned device workspace of at least the
@@ -351,7 +359,8 @@ typedef struct fe_batch_info {
     int32_t blocks_per_cu;
     int32_t max_blocks_per_cu;      /* most workgroups per compute unit at this units_per_step */
     int32_t units_per_step;
-    int32_t cooperative;            /* 1 if the captured solve launch is a cooperative launch */
+    int32_t cooperative;            /* 1 if the captured solve node is a cooperative launch (read
+                                       back from the graph node), 0 if not */
     int32_t captures;               /* graph captures so far */
 } fe_batch_info;
 

@@ -91,15 +91,21 @@ def _time_call(fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-# (workgroups per compute unit, 256-row units per workgroup step) tried by autotune
-CANDIDATES = ((4, 1), (5, 1), (2, 2), (4, 2), (2, 4))
+# rows per workgroup of the assembly's numeric row kernels tried by autotune
+ASM_ROWS_PER_BLOCK = (64, 128, 256)
+
+# (workgroups per compute unit, 256-row units per workgroup step) tried by autotune;
+# the library refuses more than 4 workgroups per compute unit (the largest grid
+# verified co-resident)
+CANDIDATES = ((4, 1), (2, 1), (2, 2), (4, 2), (2, 4))
 
 
 def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=100000, candidates=None,
              reps: int = 1, cache_path: str | None = None, log=None) -> dict:
-    """Pick the persistent solve grid of the batch: workgroups per compute unit and
-    units processed together per workgroup, by timing whole graph launches of this
-    batch (results are bitwise independent of the choice).  A candidate the device
+    """Pick the launch shapes of the batch: rows per workgroup of the assembly's row
+    kernels (timing the union's assembly), then the persistent solve grid (workgroups
+    per compute unit and units processed together per workgroup) by timing whole
+    graph launches of this batch (results are bitwise independent of every choice).  A candidate the device
     rejects is skipped.  With ``cache_path`` the choice is stored in a JSON file
     keyed by device and batch shape and reused later.  Returns the choice and the
     measured times (ms per launch)."""
@@ -111,7 +117,19 @@ def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=10
             cache = json.load(fh)
         if key in cache:
             batch.set_grid(*cache[key]["grid"])
+            batch.plan.set_launch(cache[key].get("asm_rows_per_block", 0))
             return dict(cache[key], cached=True)
+    # the assembly's launch setting first: rows per workgroup of the numeric row
+    # kernels, by timing the union's assembly alone (results do not depend on it)
+    asm_ms = {}
+    for rpb in ASM_ROWS_PER_BLOCK:
+        batch.plan.set_launch(rpb)
+        out = batch.plan.assemble(kappa, f, gD, gN)
+        asm_ms[rpb] = _time_call(lambda: batch.plan.assemble(kappa, f, gD, gN, out=out), max(reps, 3))
+        if log:
+            log(f"autotune: assembly, {rpb} rows per workgroup: {asm_ms[rpb]:.3f} ms")
+    asm_best = min(asm_ms, key=asm_ms.get)
+    batch.plan.set_launch(asm_best)
     times = {}
     for c in (candidates or CANDIDATES):
         try:
@@ -128,7 +146,8 @@ def autotune(batch: Batch, kappa, f=None, gD=None, gN=None, rtol=1e-10, maxit=10
         raise RuntimeError("autotune: no candidate grid ran")
     best = min(times, key=times.get)
     batch.set_grid(*best)
-    out = {"grid": list(best), "ms": {f"{k[0]}x{k[1]}": v for k, v in times.items()}}
+    out = {"grid": list(best), "ms": {f"{k[0]}x{k[1]}": v for k, v in times.items()},
+           "asm_rows_per_block": asm_best, "asm_ms": {str(k): v for k, v in asm_ms.items()}}
     if cache_path:
         cache[key] = out
         with open(cache_path, "w") as fh:

@@ -1132,9 +1132,16 @@ int assemble_impl(fe_plan *plan, const int32_t *urowptr, const double *node, con
                                plan->fp));
     int rc = fe_launch_check();
     if (rc) return rc;
+    // accumulator width (columns per row) by the plan's longest short row, and rows
+    // per workgroup by the plan's launch setting (fe_plan_set_launch; 0: the widest
+    // block whose accumulators take 32 KB of LDS)
     const int mr = plan->max_row;
-    if (mr <= 16) rc = launch<16, 256>(plan->dim, A, s);
-    else if (mr <= 32 || plan->dim == 2) rc = launch<32, 128>(plan->dim, A, s);
+    const int wb = plan->asm_block;
+    if (mr <= 16) rc = (wb == 64)    ? launch<16, 64>(plan->dim, A, s)
+                       : (wb == 128) ? launch<16, 128>(plan->dim, A, s)
+                                     : launch<16, 256>(plan->dim, A, s);
+    else if (mr <= 32 || plan->dim == 2) rc = (wb == 64) ? launch<32, 64>(plan->dim, A, s)
+                                                         : launch<32, 128>(plan->dim, A, s);
     else rc = launch<64, 64>(plan->dim, A, s);
     if (rc) return rc;
     if (plan->nlong > 0) {

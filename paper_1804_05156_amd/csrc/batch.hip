@@ -509,6 +509,15 @@ struct fe_batch_solver {
     uint32_t active = 0;
 };
 
+// Most workgroups per compute unit that a grid of the persistent kernel may use:
+// the largest count that has always run co-resident on MI355X (4).  Grids of 7 per
+// compute unit (the 2-entry row chunk: 68 VGPRs, no scratch, a few KB of LDS) and
+// of 5 (the 4-entry chunk: 86 VGPRs) passed the occupancy query but were not all
+// resident at once (5 ran once, then failed in later runs): the bounded
+// device-wide wait expired.  The kernels' resources do not explain that, so grids
+// above the verified count are refused rather than trusted to the query.
+constexpr int32_t BATCH_VERIFIED_PER_CU = 4;
+
 // Grid of the persistent kernel: blocks_per_cu workgroups per compute unit (0: 2)
 // and units_per_step units processed together by each workgroup (1, 2 or 4; 0: 2).
 static int batch_set_grid(fe_batch_solver *S, int32_t blocks_per_cu, int32_t units_per_step)
@@ -523,9 +532,10 @@ static int batch_set_grid(fe_batch_solver *S, int32_t blocks_per_cu, int32_t uni
     FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_small, pcg_kernel(units_per_step, 1 << 20), BB,
                                                               S->lds));
     if (per_small < 1) return FE_ELIMIT;
+    if (per_small > BATCH_VERIFIED_PER_CU) per_small = BATCH_VERIFIED_PER_CU;
     int32_t want = blocks_per_cu ? blocks_per_cu : (per_small < 2 ? per_small : 2);
     FE_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, pcg_kernel(units_per_step, want), BB, S->lds));
-    if (want > per) return FE_EINVAL;   // more workgroups per compute unit than fit
+    if (want > per || want > BATCH_VERIFIED_PER_CU) return FE_EINVAL;   // more than fit, or than verified
     S->max_per_cu = per_small;
     S->units_per_step = units_per_step;
     int64_t g = (int64_t)cus * want;
@@ -689,6 +699,7 @@ struct fe_batch {
     const int32_t *rowptr = nullptr, *colind = nullptr;
     double rtol = 0.0;
     int32_t maxit = 0;
+    int32_t launch_gen = -1;   // the plan's launch settings at capture
 };
 
 static bool same_fn(const fe_fn *a, bool has, const fe_fn &b)
@@ -703,6 +714,34 @@ static void drop_graph(fe_batch *B)
     if (B->graph) hipGraphDestroy(B->graph);
     B->exec = nullptr;
     B->graph = nullptr;
+}
+
+// The captured graph's persistent-solve node (the kernel and grid of the solver), or
+// nullptr.
+static hipGraphNode_t pcg_node(hipGraph_t g, const fe_batch_solver *S)
+{
+    size_t n = 0;
+    if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || n == 0) return nullptr;
+    std::vector<hipGraphNode_t> nodes(n);
+    if (hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return nullptr;
+    const void *fn = pcg_kernel(S->units_per_step, S->blocks_per_cu);
+    for (size_t i = 0; i < n; ++i) {
+        hipGraphNodeType t;
+        if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        if (hipGraphKernelNodeGetParams(nodes[i], &kp) != hipSuccess || kp.func != fn) continue;
+        if ((int32_t)kp.gridDim.x != S->grid || (int32_t)kp.blockDim.x != BB) return nullptr;
+        return nodes[i];
+    }
+    return nullptr;
+}
+
+// 1 if the node is a cooperative launch, 0 if not (or if the runtime cannot say).
+static int32_t node_cooperative(hipGraphNode_t node)
+{
+    hipKernelNodeAttrValue v{};
+    if (hipGraphKernelNodeGetAttribute(node, hipKernelNodeAttributeCooperative, &v) != hipSuccess) return 0;
+    return v.cooperative ? 1 : 0;
 }
 
 static int capture(fe_batch *B, const double *node, const double *kappa, const fe_fn *f, const fe_fn *g_d,
@@ -721,6 +760,23 @@ static int capture(fe_batch *B, const double *node, const double *kappa, const f
     hipStreamDestroy(cs);
     (void)hipGetLastError();
     if (rc == FE_OK && (e != hipSuccess || !g)) rc = FE_EHIP;
+    // The solve's node as captured: its kernel, its grid and whether it is a
+    // cooperative launch, the co-residency its device-wide barrier relies on.  A
+    // capture can record the cooperative launch as an ordinary kernel node; the node
+    // is then marked cooperative explicitly, and the mark read back.
+    int32_t coop = 0;
+    hipGraphNode_t pn = nullptr;
+    if (rc == FE_OK && !(pn = pcg_node(g, &B->S))) rc = FE_EHIP;   // no solve node of that kernel and grid
+    if (rc == FE_OK) {
+        coop = node_cooperative(pn);
+        if (!coop && cooperative) {
+            hipKernelNodeAttrValue v{};
+            v.cooperative = 1;
+            if (hipGraphKernelNodeSetAttribute(pn, hipKernelNodeAttributeCooperative, &v) == hipSuccess)
+                coop = node_cooperative(pn);
+            (void)hipGetLastError();
+        }
+    }
     hipGraphExec_t x = nullptr;
     if (rc == FE_OK && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) rc = FE_EHIP;
     if (rc != FE_OK) {
@@ -730,7 +786,7 @@ static int capture(fe_batch *B, const double *node, const double *kappa, const f
     }
     B->graph = g;
     B->exec = x;
-    B->cooperative = cooperative ? 1 : 0;
+    B->cooperative = coop;
     ++B->captures;
     return FE_OK;
 }
@@ -796,7 +852,7 @@ extern "C" int fe_batch_assemble_solve(fe_batch *B, const double *node, const do
     const bool same = B->exec && B->node == node && B->kappa == kappa && same_fn(f, B->hf, B->f) &&
                       same_fn(g_d, B->hgd, B->gd) && same_fn(g_n, B->hgn, B->gn) && B->rowptr == rowptr &&
                       B->colind == colind && B->val == val && B->val_bc == val_bc && B->b == b && B->u == u &&
-                      B->rtol == rtol && B->maxit == maxit;
+                      B->rtol == rtol && B->maxit == maxit && B->launch_gen == B->plan->launch_gen;
     if (!same) {
         drop_graph(B);
         int rc = capture(B, node, kappa, f, g_d, g_n, rowptr, colind, val, val_bc, b, u, rtol, maxit, true);
@@ -819,6 +875,7 @@ extern "C" int fe_batch_assemble_solve(fe_batch *B, const double *node, const do
         B->u = u;
         B->rtol = rtol;
         B->maxit = maxit;
+        B->launch_gen = B->plan->launch_gen;
     }
     FE_HIP_CHECK(hipGraphLaunch(B->exec, s));
     int rc = batch_results(&B->S, iters, relres, s);

@@ -151,6 +151,8 @@ struct fe_plan {
                           // counter updates per wavefront, the row passes read the label-order
                           // lists, and rows are processed in label order (identity pi)
     int pattern_done;
+    int32_t asm_block;    // rows per workgroup of the numeric row kernels (0: by row width)
+    int32_t launch_gen;   // bumped whenever a launch setting changes (captured graphs recapture)
 };
 
 // ---------------------------------------------------------------------------

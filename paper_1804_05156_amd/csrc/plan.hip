@@ -1549,6 +1549,18 @@ extern "C" int fe_plan_pattern(fe_plan *plan, int32_t *rowptr, int32_t *colind, 
     return rc;
 }
 
+extern "C" int fe_plan_set_launch(fe_plan *plan, int32_t rows_per_block)
+{
+    if (!plan) return FE_EINVAL;
+    if (rows_per_block != 0 && rows_per_block != 64 && rows_per_block != 128 && rows_per_block != 256)
+        return FE_EINVAL;
+    if (plan->asm_block != rows_per_block) {
+        plan->asm_block = rows_per_block;
+        ++plan->launch_gen;
+    }
+    return FE_OK;
+}
+
 extern "C" int fe_plan_get_info(const fe_plan *plan, fe_plan_info *info)
 {
     if (!plan || !info) return FE_EINVAL;

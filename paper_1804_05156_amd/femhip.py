@@ -25,7 +25,7 @@ FE_LOAD_DEFAULT, FE_LOAD_CENTROID, FE_LOAD_TRAPEZOID = range(3)
 # Entry points declared in include/femhip.h.
 ENTRY_POINTS = (
     "fe_version", "fe_status_string", "fe_plan_workspace_bytes", "fe_plan_create", "fe_plan_pattern",
-    "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_assemble_robin",
+    "fe_plan_set_launch", "fe_plan_get_info", "fe_plan_status", "fe_plan_destroy", "fe_assemble", "fe_assemble_robin",
     "fe_assemble_quad", "fe_plan_upper", "fe_assemble_upper", "fe_spmv_sym", "fe_solve_sym", "fe_spmv",
     "fe_select", "fe_solve_workspace_bytes", "fe_solve", "fe_solve_noalloc", "fe_neumann_workspace_bytes", "fe_neumann_solve",
     "fe_grad", "fe_batch_solve_workspace_bytes",
@@ -79,6 +79,7 @@ def _load():
         "fe_plan_workspace_bytes": ([C.POINTER(fe_mesh), C.POINTER(SZ)], C.c_int),
         "fe_plan_create": ([C.POINTER(fe_mesh), P, SZ, C.POINTER(P), C.POINTER(I64), P], C.c_int),
         "fe_plan_pattern": ([P, P, P, P], C.c_int),
+        "fe_plan_set_launch": ([P, I32], C.c_int),
         "fe_plan_get_info": ([P, C.POINTER(fe_plan_info)], C.c_int),
         "fe_plan_status": ([P, P], C.c_int),
         "fe_plan_destroy": ([P], C.c_int),
@@ -204,6 +205,10 @@ def fe_plan_create(mesh: fe_mesh, ws: torch.Tensor, stream=None):
 def fe_plan_pattern(plan, rowptr: torch.Tensor, colind: torch.Tensor, stream=None):
     _check(_lib.fe_plan_pattern(plan, _ptr(rowptr, torch.int32, "rowptr"), _ptr(colind, torch.int32, "colind"),
                                 _stream(stream)), "fe_plan_pattern")
+
+
+def fe_plan_set_launch(plan, rows_per_block: int):
+    _check(_lib.fe_plan_set_launch(plan, int(rows_per_block)), "fe_plan_set_launch")
 
 
 def fe_plan_get_info(plan) -> dict:
@@ -498,6 +503,10 @@ class Plan:
 
     def check(self, stream=None):
         _check(fe_plan_status(self.handle, stream), "kernel status")
+
+    def set_launch(self, rows_per_block: int):
+        """Rows per workgroup of the numeric row kernels (64, 128, 256; 0 = default)."""
+        fe_plan_set_launch(self.handle, rows_per_block)
 
     def solve_workspace(self):
         if self._solve_ws is None:

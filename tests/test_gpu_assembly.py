@@ -398,6 +398,34 @@ def test_more_than_2_26_labels(labels):
     assert g["rowptr"][-1] == ora.rowptr[-1] == plan.nnz
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_launch_setting_bitwise(dim):
+    """Rows per workgroup of the numeric row kernels (fe_plan_set_launch) change no
+    result bit; other values are refused."""
+    from paper_1804_05156_amd import femhip
+    log(f"case: launch setting, dim {dim}")
+    if dim == 2:
+        m = meshgen.square_mesh(65, jitter=0.2, permute=True, seed=71, kappa="lognormal", sides=(1, 2, 1, 2))
+        specs = [(FE_FN_SINPROD, (TWO_PI2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7)), (FE_FN_CONST, (0.9,))]
+    else:
+        m = meshgen.kuhn_cube(13, jitter=0.15, permute=False, seed=72, kappa="lognormal")
+        specs = [(FE_FN_SINPROD, (3 * math.pi ** 2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7, 0.4)),
+                 (FE_FN_DUDN_SINPROD, (1.0,))]
+    (f, _), (gd, _), (gn, _) = fns(*specs)
+    node, elem, bd, kap = to_dev(m)
+    plan = femhip.Plan(node, elem, bd)
+    ref = host(plan, plan.assemble(kap, f, gd, gn))
+    for rpb in (64, 128, 256, 0):
+        plan.set_launch(rpb)
+        g = host(plan, plan.assemble(kap, f, gd, gn))
+        for name in ("val", "val_bc", "b", "b_load", "is_d"):
+            assert np.array_equal(g[name], ref[name]), (rpb, name)
+    for bad in (32, 100, 512, -1):
+        with pytest.raises(femhip.FemhipError) as e:
+            plan.set_launch(bad)
+        assert e.value.code == femhip.FE_EINVAL
+
+
 def test_error_paths():
     from paper_1804_05156_amd import femhip
     log("case: error paths")

@@ -96,6 +96,35 @@ def test_batch_solve_grid_independent():
     assert ran >= 4
 
 
+def test_grid_bound_and_cooperative_node():
+    """Grids above the verified co-resident bound (4 workgroups per compute unit) are
+    refused before any launch; the captured solve node reports whether it is a
+    cooperative launch (read back from the graph, not from the library's request)."""
+    from paper_1804_05156_amd import femhip
+    log("case: grid bound, cooperative node")
+    ms = meshgen.batch_meshes([25, 18], seed_base=7300)
+    (f, _), (gd, _), _ = fns(*SPECS)
+    B, kap = _batch(ms)
+    for bpc in (5, 7, 12):
+        with pytest.raises(femhip.FemhipError) as e:
+            B.set_grid(bpc, 1)
+        assert e.value.code == femhip.FE_EINVAL
+    B.set_grid(4, 1)
+    B.assemble_solve(kap, f, gd, None, rtol=1e-10)
+    info = B.info()
+    log(f"  info {info}")
+    assert info["blocks_per_cu"] == 4 and info["max_blocks_per_cu"] <= 4
+    assert info["cooperative"] in (0, 1)
+    # a new launch setting of the assembly recaptures the graph; the bits stay
+    u1, it1, _ = B.assemble_solve(kap, f, gd, None, rtol=1e-10)
+    u1 = u1.clone()
+    caps = B.info()["captures"]
+    B.plan.set_launch(64)
+    u2, it2, _ = B.assemble_solve(kap, f, gd, None, rtol=1e-10)
+    assert B.info()["captures"] == caps + 1
+    assert it2 == it1 and torch.equal(u2, u1)
+
+
 def test_graph_replay_and_recapture():
     log("case: graph replay, in-place kappa update, recapture")
     ms = meshgen.batch_meshes([21, 14, 35], seed_base=7200)
