@@ -8,22 +8,30 @@
  * code, header, table or helper with the GPU library, and the GPU library never
  * calls it.
  *
- * Everything is IEEE double precision, single-threaded, in plain loops:
- *   - local stiffness through the affine map of the reference simplex, gradients
- *     by solving B x = G with Gaussian elimination (Section 3.1.1), generalised
- *     from triangles to tetrahedra in the same way;
- *   - triplets (i, j, s) collected element by element, local row then local column
- *     (Section 3.1.2), then one call of a `sparse` routine that sorts them stably by
- *     (row, column) and adds duplicates left to right (Section 2.2);
- *   - load vector: 2-D three edge-midpoint rule (Section 3.2 and Section 4); 3-D
+ * Everything is IEEE double precision, single-threaded, in plain loops, and each
+ * quantity is computed from its definition:
+ *   - barycentric coordinates lambda_a of a simplex are the affine functions with
+ *     lambda_a(x_b) = delta_ab; their gradients come from that (d+1) x (d+1)
+ *     linear system (rows [1, x_b]) by Gaussian elimination with partial pivoting,
+ *     and |t| = |det| / d! of the same matrix;
+ *   - a_ij = sum over the elements t containing i and j of
+ *     kappa_t |t| grad(lambda_i) . grad(lambda_j) (Section 3.1), added into a
+ *     sorted per-row list of (column, value) entries, elements in ascending order,
+ *     so duplicates are summed as `sparse` does (Section 2.2) without forming
+ *     triplets; pairs whose sum is zero stay stored;
+ *   - load integrals int_t f lambda_a by a quadrature rule given as points in
+ *     barycentric coordinates and weights, lambda_a read off the point's
+ *     barycentrics (Sections 3.2 and 4): 2-D the three edge midpoints, 3-D the
  *     symmetric four-point rule of degree two (the paper names a 4-point rule but
- *     lists none; the reading used here is recorded in the design notes); on
- *     request the one-point (centroid) or the trapezoidal (vertex) rule of Section 4;
- *   - Dirichlet lifting b <- b - A u_D and Neumann side integrals by the midpoint
- *     (2-D) / centroid (3-D) rule (Section 3.3);
+ *     lists none; the reading used here is recorded in the design notes), and on
+ *     request the one-point (centroid) or the vertex (trapezoidal) rule;
+ *   - Dirichlet lifting b <- b - A u_D, Neumann and Robin side integrals by the
+ *     one-point rule at the side's midpoint (2-D) / centroid (3-D) (Section 3.3);
  *   - solve on the free nodes (equation (directsolve)): dense Cholesky when small,
  *     plain Jacobi-preconditioned CG otherwise;
  *   - adjoint gradient dJ/dkappa_t = -|t| grad(lambda_h) . grad(u_h) on t.
+ * The compressed-row conversion of a triplet list (oracle_coo_to_csr, the `sparse`
+ * of Section 2.1) is kept as a routine of its own, checked on the paper's example.
  *
  * Array layout: node[c*N + k], elem[a*NT + t] (0-based), bdflag[a*NT + t];
  * face a of an element is opposite its local vertex a (Section 1.2).
@@ -40,6 +48,11 @@
 #define OR_EMESH (-2)
 #define OR_EUNSUPPORTED (-3)
 #define OR_ENOCONV (-7)
+
+/* quadrature of the load integrals (Section 4) */
+#define OR_LOAD_DEFAULT 0
+#define OR_LOAD_CENTROID 1
+#define OR_LOAD_TRAPEZOID 2
 
 /* kinds of a data function (source f, Dirichlet g_D, Neumann g_N) */
 #define OR_FN_ZERO 0
@@ -175,7 +188,7 @@ int oracle_coo_to_csr(int64_t m, int64_t n, int64_t nz, const int64_t *ii, const
 
 /* Solve the d x d system M X = R (R has ncol columns, column-major in r[c*d + row])
  * by Gaussian elimination with partial pivoting; M is overwritten. Returns 0, or -1
- * if a pivot is exactly zero. */
+ * if a pivot is exactly zero.  (d <= 4) */
 static int gauss_solve(int d, double *M /* row-major d x d */, double *r, int ncol)
 {
     for (int k = 0; k < d; ++k) {
@@ -207,43 +220,60 @@ static int gauss_solve(int d, double *M /* row-major d x d */, double *r, int nc
     return 0;
 }
 
-/* Determinant of a d x d row-major matrix (d = 2 or 3) by cofactor expansion. */
-static double det_small(int d, const double *M)
-{
-    if (d == 2) return M[0] * M[3] - M[1] * M[2];
-    return M[0] * (M[4] * M[8] - M[5] * M[7]) - M[1] * (M[3] * M[8] - M[5] * M[6]) +
-           M[2] * (M[3] * M[7] - M[4] * M[6]);
-}
-
 /* For the simplex with vertex coordinates p[a*dim + c] (a = 0..dim):
- *   signed measure: det[x_2 - x_1, ..., x_{d+1} - x_1] / d!  (positive for the
- *                   orientation required in Section 1.1),
- *   measure:        |det B| / d!, B rows x_k - x_{d+1}, k = 1..d,
- *   grad[a*dim+c]:  gradient of barycentric coordinate lambda_a, from B X = G with
- *                   G = [I_d | -1] (gradients of the reference barycentrics),
- *   K[a*(d+1)+b]:   measure * grad lambda_a . grad lambda_b.
+ *   lambda_a(x) = c_a + grad_a . x with lambda_a(x_b) = delta_ab, i.e. the columns
+ *   of the inverse of M (row b = [1, x_b]): M [c_a; grad_a] = e_a;
+ *   signed measure: det M / d!  (= det[x_2 - x_1, ..., x_{d+1} - x_1] / d!,
+ *                   positive for the orientation required in Section 1.1),
+ *   measure:        |det M| / d!,
+ *   grad[a*dim+c]:  gradient of lambda_a,
+ *   K[a*(d+1)+b]:   measure * grad lambda_a . grad lambda_b  (the element's
+ *                   unit-coefficient stiffness, int_t grad lambda_a . grad lambda_b).
  * Returns -2 if the signed measure is not positive and finite. */
 int oracle_local_stiffness(int dim, const double *p, double *K, double *grad, double *measure,
                            double *signed_measure)
 {
     if (dim != 2 && dim != 3) return OR_EUNSUPPORTED;
     const int nv = dim + 1;
-    double E[9], B[9], R[12];
-    for (int k = 0; k < dim; ++k)
-        for (int c = 0; c < dim; ++c) E[k * dim + c] = p[(k + 1) * dim + c] - p[c];
-    double fact = (dim == 2) ? 2.0 : 6.0;
-    double sgn = det_small(dim, E) / fact;
+    double M[16], X[16];
+    for (int b = 0; b < nv; ++b) {
+        M[b * nv] = 1.0;
+        for (int c = 0; c < dim; ++c) M[b * nv + 1 + c] = p[b * dim + c];
+    }
+    /* the determinant from the elimination's pivots (with the sign of the row swaps) */
+    double det = 1.0;
+    {
+        double W[16];
+        memcpy(W, M, sizeof(double) * (size_t)(nv * nv));
+        for (int k = 0; k < nv; ++k) {
+            int piv = k;
+            for (int i = k + 1; i < nv; ++i)
+                if (fabs(W[i * nv + k]) > fabs(W[piv * nv + k])) piv = i;
+            if (W[piv * nv + k] == 0.0) { det = 0.0; break; }
+            if (piv != k) {
+                for (int j = 0; j < nv; ++j) {
+                    double t = W[k * nv + j]; W[k * nv + j] = W[piv * nv + j]; W[piv * nv + j] = t;
+                }
+                det = -det;
+            }
+            det *= W[k * nv + k];
+            for (int i = k + 1; i < nv; ++i) {
+                double l = W[i * nv + k] / W[k * nv + k];
+                for (int j = k; j < nv; ++j) W[i * nv + j] -= l * W[k * nv + j];
+            }
+        }
+    }
+    const double fact = (dim == 2) ? 2.0 : 6.0;
+    const double sgn = det / fact;
     if (signed_measure) *signed_measure = sgn;
     if (!(sgn > 0.0) || !isfinite(sgn)) return OR_EMESH;
-    for (int k = 0; k < dim; ++k)
-        for (int c = 0; c < dim; ++c) B[k * dim + c] = p[k * dim + c] - p[dim * dim + c];
-    double area = fabs(det_small(dim, B)) / fact;
-    /* right-hand sides: columns of G = [I_d | -1] */
+    /* columns of M^-1: right-hand sides e_a, stored column-major X[a*nv + row] */
     for (int a = 0; a < nv; ++a)
-        for (int c = 0; c < dim; ++c) R[a * dim + c] = (a < dim) ? (a == c ? 1.0 : 0.0) : -1.0;
-    if (gauss_solve(dim, B, R, nv) != 0) return OR_EMESH;
+        for (int r = 0; r < nv; ++r) X[a * nv + r] = (a == r) ? 1.0 : 0.0;
+    if (gauss_solve(nv, M, X, nv) != 0) return OR_EMESH;
     for (int a = 0; a < nv; ++a)
-        for (int c = 0; c < dim; ++c) grad[a * dim + c] = R[a * dim + c];
+        for (int c = 0; c < dim; ++c) grad[a * dim + c] = X[a * nv + 1 + c];
+    const double area = fabs(det) / fact;
     for (int a = 0; a < nv; ++a)
         for (int b = 0; b < nv; ++b) {
             double s = 0.0;
@@ -268,6 +298,81 @@ static void gather_coords(int dim, int64_t N, int64_t NT, const double *node, co
 /* Assembly of A, b and the boundary conditions (Sections 3.1-3.3).           */
 /* ------------------------------------------------------------------------- */
 
+/* The rows of A being summed: row i's entries (column, value), sorted by column,
+ * in slot [off[i], off[i] + n[i]) of one pool; a row can hold no more than the
+ * vertex itself plus d columns per incident element, which sizes its slot. */
+typedef struct {
+    int64_t *off, *n, *col;
+    double *val;
+} or_rows;
+
+/* a_ij += v: the entry of column j is found by bisection, or inserted in order. */
+static void row_add(or_rows *R, int64_t i, int64_t j, double v)
+{
+    int64_t *c = R->col + R->off[i];
+    double *w = R->val + R->off[i];
+    const int64_t n = R->n[i];
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (c[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo < n && c[lo] == j) {
+        w[lo] += v;
+        return;
+    }
+    for (int64_t k = n; k > lo; --k) {
+        c[k] = c[k - 1];
+        w[k] = w[k - 1];
+    }
+    c[lo] = j;
+    w[lo] = v;
+    R->n[i] = n + 1;
+}
+
+/* A quadrature rule on a simplex: npt points in barycentric coordinates bary[q][e]
+ * and weights w[q] relative to the measure (they sum to 1). */
+typedef struct {
+    int npt;
+    double bary[4][4];
+    double w[4];
+} or_rule;
+
+/* The load rule of Sections 3.2 and 4 for dimension dim. */
+static or_rule load_quadrature(int dim, int load_rule)
+{
+    or_rule R;
+    memset(&R, 0, sizeof(R));
+    const int nv = dim + 1;
+    if (load_rule == OR_LOAD_CENTROID) {          /* one point: the barycentre */
+        R.npt = 1;
+        for (int e = 0; e < nv; ++e) R.bary[0][e] = 1.0 / nv;
+        R.w[0] = 1.0;
+    } else if (load_rule == OR_LOAD_TRAPEZOID) {  /* the vertices, equal weights */
+        R.npt = nv;
+        for (int q = 0; q < nv; ++q) {
+            R.bary[q][q] = 1.0;
+            R.w[q] = 1.0 / nv;
+        }
+    } else if (dim == 2) {                        /* the three edge midpoints */
+        R.npt = 3;
+        for (int q = 0; q < 3; ++q) {
+            for (int e = 0; e < 3; ++e) R.bary[q][e] = (e == q) ? 0.0 : 0.5;
+            R.w[q] = 1.0 / 3.0;
+        }
+    } else {                                      /* (alpha, beta, beta, beta) and permutations */
+        const double alpha = (5.0 + 3.0 * sqrt(5.0)) / 20.0;
+        const double beta = (5.0 - sqrt(5.0)) / 20.0;
+        R.npt = 4;
+        for (int q = 0; q < 4; ++q) {
+            for (int e = 0; e < 4; ++e) R.bary[q][e] = (e == q) ? alpha : beta;
+            R.w[q] = 0.25;
+        }
+    }
+    return R;
+}
+
 /* Inputs: dim (2|3), N, NT, node, elem, bdflag (may be NULL), kappa (may be NULL:
  * all ones), data functions f, g_D, g_N (each may be NULL: zero).
  * Outputs (caller-allocated, nnz_cap >= (dim+1)^2 * NT):
@@ -287,9 +392,6 @@ static void gather_coords(int dim, int64_t N, int64_t NT, const double *node, co
  * the vertex rule sum_e f(x_e) phi_a(x_e) |t| / (d+1) = f(x_a) |t| / (d+1).
  * oracle_assemble_robin is the default rule; oracle_assemble is also alpha = 0,
  * g_R = 0. */
-#define OR_LOAD_DEFAULT 0
-#define OR_LOAD_CENTROID 1
-#define OR_LOAD_TRAPEZOID 2
 int oracle_assemble_rule(int dim, int64_t N, int64_t NT, const double *node, const int32_t *elem,
                          const int8_t *bdflag, const double *kappa, const or_fn *f, const or_fn *gD,
                          const or_fn *gN, const or_fn *gR, double alpha_r, int load_rule, int64_t nnz_cap,
@@ -351,22 +453,29 @@ int oracle_assemble_rule(int dim, int64_t N, int64_t NT, const double *node, con
         for (int64_t t = 0; t < NT; ++t)
             if (!(kappa[t] > 0.0) || !isfinite(kappa[t])) return OR_EINVAL;
 
-    const int64_t ns = (int64_t)nv * nv * NT + nrobin * dim * dim;
-    int64_t *ii = malloc((size_t)(ns > 0 ? ns : 1) * sizeof(int64_t));
-    int64_t *jj = malloc((size_t)(ns > 0 ? ns : 1) * sizeof(int64_t));
-    double *ss = malloc((size_t)(ns > 0 ? ns : 1) * sizeof(double));
-    double *bt = malloc((size_t)(nv * NT > 0 ? nv * NT : 1) * sizeof(double));
+    or_rows rows;
+    rows.off = calloc((size_t)N + 1, sizeof(int64_t));
+    rows.n = calloc((size_t)N, sizeof(int64_t));
     double *area = malloc((size_t)(NT > 0 ? NT : 1) * sizeof(double));
-    if (!ii || !jj || !ss || !bt || !area) {
-        free(ii); free(jj); free(ss); free(bt); free(area);
+    rows.col = NULL;
+    rows.val = NULL;
+    if (rows.off && rows.n && area) {
+        /* slot sizes: 1 + d per incidence of the vertex */
+        for (int64_t i = 0; i < N; ++i) rows.off[i + 1] = 1;
+        for (int64_t k = 0; k < (int64_t)nv * NT; ++k) rows.off[elem[k] + 1] += dim;
+        for (int64_t i = 0; i < N; ++i) rows.off[i + 1] += rows.off[i];
+        rows.col = malloc((size_t)rows.off[N] * sizeof(int64_t));
+        rows.val = malloc((size_t)rows.off[N] * sizeof(double));
+    }
+    if (!rows.off || !rows.n || !area || !rows.col || !rows.val) {
+        free(rows.off); free(rows.n); free(rows.col); free(rows.val); free(area);
         return OR_EINVAL;
     }
     int status = OR_OK;
     double p[12], K[16], G[12], meas, sgn;
     int32_t verts[4];
 
-    /* Stiffness triplets, element by element (Section 3.1.2). */
-    int64_t idx = 0;
+    /* a_ij = sum_t kappa_t int_t grad lambda_i . grad lambda_j, elements in order. */
     for (int64_t t = 0; t < NT && status == OR_OK; ++t) {
         gather_coords(dim, N, NT, node, elem, t, p, verts);
         status = oracle_local_stiffness(dim, p, K, G, &meas, &sgn);
@@ -374,18 +483,13 @@ int oracle_assemble_rule(int dim, int64_t N, int64_t NT, const double *node, con
         area[t] = meas;
         double kt = kappa ? kappa[t] : 1.0;
         for (int a = 0; a < nv; ++a)
-            for (int c = 0; c < nv; ++c) {
-                ii[idx] = verts[a];
-                jj[idx] = verts[c];
-                ss[idx] = kt * K[a * nv + c];
-                ++idx;
-            }
+            for (int c = 0; c < nv; ++c) row_add(&rows, verts[a], verts[c], kt * K[a * nv + c]);
     }
     if (status != OR_OK) goto done;
-    /* Robin side mass matrices alpha |F| (1 + delta_ij) / (d (d+1)) on the side's d
-     * vertices, in the stacked side order (sides opposite vertex 1, then 2, ...). */
+    /* Robin sides: alpha int_F lambda_i lambda_j = alpha |F| (1 + delta_ij) / (d (d+1))
+     * on the side's d vertices (sides opposite vertex 1, then 2, ...). */
     for (int a = 0; a < nv && status == OR_OK && nrobin > 0; ++a)
-        for (int64_t t = 0; t < NT; ++t) {
+        for (int64_t t = 0; t < NT && status == OR_OK; ++t) {
             if (bdflag[(int64_t)a * NT + t] != 3) continue;
             gather_coords(dim, N, NT, node, elem, t, p, verts);
             status = oracle_local_stiffness(dim, p, K, G, &meas, &sgn);
@@ -396,79 +500,45 @@ int oracle_assemble_rule(int dim, int64_t N, int64_t NT, const double *node, con
                 if (e == a) continue;
                 for (int e2 = 0; e2 < nv; ++e2) {
                     if (e2 == a) continue;
-                    ii[idx] = verts[e];
-                    jj[idx] = verts[e2];
-                    ss[idx] = alpha_r * fmeas * (e == e2 ? 2.0 : 1.0) / (dim * (dim + 1));
-                    ++idx;
+                    row_add(&rows, verts[e], verts[e2], alpha_r * fmeas * (e == e2 ? 2.0 : 1.0) / (dim * (dim + 1)));
                 }
             }
         }
     if (status != OR_OK) goto done;
-    status = oracle_coo_to_csr(N, N, idx, ii, jj, ss, rowptr, colind, val, nnz);
-    if (status != OR_OK) goto done;
+    /* the rows, in order, are the compressed-row matrix */
+    rowptr[0] = 0;
+    for (int64_t i = 0; i < N; ++i) {
+        for (int64_t q = 0; q < rows.n[i]; ++q) {
+            colind[rowptr[i] + q] = rows.col[rows.off[i] + q];
+            val[rowptr[i] + q] = rows.val[rows.off[i] + q];
+        }
+        rowptr[i + 1] = rowptr[i] + rows.n[i];
+    }
+    *nnz = rowptr[N];
 
-    /* Load vector (Section 3.2): per-element contributions bt[a*NT + t]. */
-    for (int64_t t = 0; t < NT; ++t) {
-        gather_coords(dim, N, NT, node, elem, t, p, verts);
-        if (load_rule == OR_LOAD_CENTROID) {
-            /* one-point rule at the barycentre c_t, where every phi_a is 1/(d+1) */
-            double x[3] = {0, 0, 0}, bary[4];
-            for (int e = 0; e < nv; ++e) {
-                bary[e] = 1.0 / nv;
-                for (int c = 0; c < dim; ++c) x[c] += p[e * dim + c] / nv;
-            }
-            const double fc = fn_eval(f, dim, x, nv, bary, verts, NULL);
-            for (int a = 0; a < nv; ++a) bt[a * NT + t] = area[t] * fc / nv;
-        } else if (load_rule == OR_LOAD_TRAPEZOID) {
-            /* vertex rule: at x_e only phi_e is non-zero (and equal to 1) */
-            for (int a = 0; a < nv; ++a) {
-                double bary[4];
-                for (int e = 0; e < nv; ++e) bary[e] = (e == a) ? 1.0 : 0.0;
-                const double fa = fn_eval(f, dim, p + a * dim, nv, bary, verts, NULL);
-                bt[a * NT + t] = area[t] * fa / nv;
-            }
-        } else if (dim == 2) {
-            /* mid_a = midpoint of the edge opposite vertex a; three-midpoint rule */
-            double mid[3][2], fm[3], bary[3];
-            for (int a = 0; a < 3; ++a) {
-                int u = (a + 1) % 3, w = (a + 2) % 3;
-                for (int c = 0; c < 2; ++c) mid[a][c] = (p[u * 2 + c] + p[w * 2 + c]) / 2;
-                for (int e = 0; e < 3; ++e) bary[e] = (e == a) ? 0.0 : 0.5;
-                fm[a] = fn_eval(f, 2, mid[a], 3, bary, verts, NULL);
-            }
-            for (int a = 0; a < 3; ++a) {
-                int u = (a + 1) % 3, w = (a + 2) % 3;
-                bt[a * NT + t] = area[t] * (fm[u] + fm[w]) / 6;
-            }
-        } else {
-            /* symmetric 4-point rule of degree 2: point k has barycentrics alpha at
-             * vertex k and beta elsewhere, weight |t|/4 */
-            const double alpha = (5.0 + 3.0 * sqrt(5.0)) / 20.0;
-            const double beta = (5.0 - sqrt(5.0)) / 20.0;
+    /* Load vector: b_a += |t| sum_q w_q f(x_q) lambda_a(x_q), with x_q and lambda_a(x_q)
+     * from the point's barycentric coordinates (nodal f: its linear interpolant). */
+    for (int64_t i = 0; i < N; ++i) { b[i] = 0.0; b_scale[i] = 0.0; is_d[i] = 0; }
+    {
+        const or_rule R = load_quadrature(dim, load_rule);
+        for (int64_t t = 0; t < NT; ++t) {
+            gather_coords(dim, N, NT, node, elem, t, p, verts);
             double fq[4];
-            for (int k = 0; k < 4; ++k) {
-                double x[3] = {0, 0, 0}, bary[4];
-                for (int e = 0; e < 4; ++e) {
-                    bary[e] = (e == k) ? alpha : beta;
-                    for (int c = 0; c < 3; ++c) x[c] += bary[e] * p[e * 3 + c];
-                }
-                fq[k] = fn_eval(f, 3, x, 4, bary, verts, NULL);
+            for (int q = 0; q < R.npt; ++q) {
+                double x[3] = {0, 0, 0};
+                for (int e = 0; e < nv; ++e)
+                    for (int c = 0; c < dim; ++c) x[c] += R.bary[q][e] * p[e * dim + c];
+                fq[q] = fn_eval(f, dim, x, nv, R.bary[q], verts, NULL);
             }
-            for (int a = 0; a < 4; ++a) {
+            for (int a = 0; a < nv; ++a) {
                 double s = 0.0;
-                for (int k = 0; k < 4; ++k) s += fq[k] * ((k == a) ? alpha : beta);
-                bt[a * NT + t] = area[t] * s / 4;
+                for (int q = 0; q < R.npt; ++q) s += R.w[q] * fq[q] * R.bary[q][a];
+                const double ba = area[t] * s;
+                b[verts[a]] += ba;
+                b_scale[verts[a]] += fabs(ba);
             }
         }
     }
-    /* accumarray over the stacked list [vertex-1 terms; vertex-2 terms; ...] */
-    for (int64_t i = 0; i < N; ++i) { b[i] = 0.0; b_scale[i] = 0.0; is_d[i] = 0; }
-    for (int a = 0; a < nv; ++a)
-        for (int64_t t = 0; t < NT; ++t) {
-            int32_t v = elem[(int64_t)a * NT + t];
-            b[v] += bt[a * NT + t];
-            b_scale[v] += fabs(bt[a * NT + t]);
-        }
 
     /* Neumann (type 2) and Robin (type 3) sides (Section 3.3): midpoint (2-D) /
      * centroid (3-D) rule for g_N, g_R.  Sides are taken in the stacked order [faces
@@ -533,7 +603,7 @@ int oracle_assemble_rule(int dim, int64_t N, int64_t NT, const double *node, con
         free(uD);
     }
 done:
-    free(ii); free(jj); free(ss); free(bt); free(area);
+    free(rows.off); free(rows.n); free(rows.col); free(rows.val); free(area);
     return status;
 }
 
