@@ -27,18 +27,20 @@ enum : int32_t {
 
 // Slots of the device status array.
 enum { ST_ERR = 0, ST_UNUSED = 1, ST_MAXROW = 2, ST_MAXDEG = 3, ST_NDIR = 4, ST_RUNS = 5, ST_NLONG = 6,
-       ST_SELL = 7, ST_SELLERR = 8, ST_COUNT = 16 };
+       ST_SELL = 7, ST_COUNT = 16 };
 
 // Layout of the per-incidence (key, metadata) words, pincm.  Row-major: row k's
 // incidences at pincptr[k] .. pincptr[k+1].  Sliced (3-D plans whose padded size
 // fits, status word ST_SELL set): rows grouped in slices of SELLW consecutive
-// processing positions, incidence q of row k at sptr[k / SELLW] + SELLW q +
-// k % SELLW, each slice padded to its longest row.  A wavefront's rows are one
-// slice, so its q-th loads and stores are contiguous.
+// processing positions, every slice W incidences deep (W = the most incidences of
+// any row, in sptr[0]), incidence q of row k at (k / SELLW) SELLW W + SELLW q +
+// k % SELLW.  A wavefront's rows are one slice, so its q-th loads and stores are
+// contiguous, and the address needs no per-row load (W is one word for the whole
+// grid, held by the scalar cache).
 constexpr int SELLW = 64;
 __device__ __forceinline__ int64_t inc_at(bool sell, const int32_t *sptr, int32_t s, int32_t k, int32_t q)
 {
-    return sell ? (int64_t)sptr[k >> 6] + (int64_t)SELLW * q + (k & (SELLW - 1)) : (int64_t)s + q;
+    return sell ? (int64_t)(k >> 6) * SELLW * sptr[0] + (int64_t)SELLW * q + (k & (SELLW - 1)) : (int64_t)s + q;
 }
 
 // Per-row capacity (stored columns, the vertex itself included) of the row kernels
@@ -124,7 +126,8 @@ struct fe_plan {
     int32_t *pincptr;     // N+1    incidence ranges in processing order
     int32_t *pinc;        // ninc   incidence keys t*nv+a, ascending within a row
     int2 *pincm;          // pcap   (key, metadata word) per incidence, processing order (see inc_at)
-    int32_t *sptr;        // N/64+1 3-D: start of each slice of the sliced layout
+    int32_t *sptr;        // N/64+1 3-D: the longest row of each slice, then sptr[0] = the
+                          //        depth W of every slice of the sliced layout
     int32_t *elemp;       // 4*NT   processing positions of each element's vertices (AoS),
                           //        see EREC_POS
     int32_t *rowlen;      // N+1    row lengths (label order) -> row pointer (label order)

@@ -821,8 +821,9 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
 }
 
 // Sliced incidence layout (3-D): SELLW times the longest row of each slice of SELLW
-// processing positions (then scanned into slice starts), and the choice of layout
-// once the padded total is known.
+// processing positions, then (one block) the depth W of every slice, the longest
+// row of all, in sptr[0], and the choice of layout: sliced if the padded total fits
+// pincm.
 __global__ __launch_bounds__(256) void k_sell_len(int32_t N, const int32_t *__restrict__ pincptr, int32_t *sptr)
 {
     const int32_t sl = blockIdx.x * 256 + threadIdx.x;
@@ -834,9 +835,20 @@ __global__ __launch_bounds__(256) void k_sell_len(int32_t N, const int32_t *__re
     sptr[sl] = SELLW * m;
 }
 
-__global__ void k_sell_choose(const int64_t *__restrict__ total, int64_t cap, int32_t *status)
+__global__ __launch_bounds__(1024) void k_sell_choose(int32_t nsl, int64_t cap, int32_t *sptr, int32_t *status)
 {
-    status[ST_SELL] = (status[ST_SELLERR] == 0 && *total <= cap) ? 1 : 0;
+    __shared__ int32_t m;
+    if (threadIdx.x == 0) m = 0;
+    __syncthreads();
+    int32_t w = 0;
+    for (int32_t i = threadIdx.x; i < nsl; i += 1024) w = max(w, sptr[i]);
+    atomicMax(&m, w);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t W = m / SELLW;
+        sptr[0] = W;
+        status[ST_SELL] = ((int64_t)nsl * SELLW * W <= cap) ? 1 : 0;
+    }
 }
 
 // Long rows: rows with more columns than the LDS column set holds (a vertex with
@@ -1106,12 +1118,14 @@ Buckets choose_buckets(int64_t N, int64_t NT, int nv)
     return B;
 }
 
-// Capacity of pincm: the incidences, and in 3-D a quarter more for the padding of
-// the sliced layout (a mesh whose padded size exceeds it keeps the row-major one).
+// Capacity of pincm: the incidences, and in 3-D half as many more for the padding
+// of the sliced layout (a mesh whose padded size exceeds it keeps the row-major
+// one: every row padded to the longest, so for a mesh whose longest row is more
+// than 1.5 times the average).
 int64_t pincm_cap(int64_t ninc, int nv)
 {
     if (nv != 4) return ninc;
-    const int64_t c = ninc + ninc / 4 + (int64_t)SELLW * SELLW;
+    const int64_t c = ninc + ninc / 2 + (int64_t)SELLW * SELLW;
     return c < (int64_t)INT32_MAX ? c : (int64_t)INT32_MAX;
 }
 
@@ -1356,16 +1370,14 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         if ((rc = fe_scan_exclusive(P->pincptr, P->pincptr, N, P->totals + 1, P->part, P->status, s))) return rc;
     }
     if (NV == 4) {
-        // the sliced incidence layout, if its padded size fits pincm (its scan may
-        // overflow int32 for huge meshes: that only rules the layout out)
+        // the sliced incidence layout, if its padded size fits pincm
         const int64_t nsl = cdiv(N, SELLW);
         FE_TIMED("k_sell_len", s,
                  hipLaunchKernelGGL(k_sell_len, dim3((unsigned)cdiv(nsl, 256)), dim3(256), 0, s, N,
                                     (const int32_t *)P->pincptr, P->sptr));
-        if ((rc = fe_scan_exclusive(P->sptr, P->sptr, nsl, P->totals + 6, P->part, P->status + ST_SELLERR, s)))
-            return rc;
-        hipLaunchKernelGGL(k_sell_choose, dim3(1), dim3(1), 0, s, (const int64_t *)(P->totals + 6),
-                           pincm_cap(P->ninc, NV), P->status);
+        FE_TIMED("k_sell_choose", s,
+                 hipLaunchKernelGGL(k_sell_choose, dim3(1), dim3(1024), 0, s, (int32_t)nsl, pincm_cap(P->ninc, NV),
+                                    P->sptr, P->status));
         if ((rc = fe_launch_check())) return rc;
     }
     const RowArgs R = row_args(P);
