@@ -188,6 +188,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-next", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 3-D (129^3 Kuhn cube) assembly section")
+    ap.add_argument("--no-sym", action="store_true", help="skip the symmetric-storage (upper triangle) timings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes (for counter calibration)")
     ap.add_argument("--cpu-baseline-only", action="store_true",
@@ -313,8 +314,10 @@ def main():
         wev.append((e0, e1))
     torch.cuda.synchronize()
     warm_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in wev]))
-    log("[bench] symmetric storage (upper triangle)")
-    sym = symmetric_storage(femhip, torch, plan, node, kappa2, f, gn, rowptr, colind, val, N, args.steps)
+    sym = None
+    if not args.no_sym:
+        log("[bench] symmetric storage (upper triangle)")
+        sym = symmetric_storage(femhip, torch, plan, node, kappa2, f, gn, rowptr, colind, val, N, args.steps)
     femhip.fe_plan_destroy(plan)
     roof = roofline(kernels, counters, N, NT, nnz, dim, nodal, ms_step, warm_ms)
     roof["copy_kernel_GBps"] = copy["GBps"]
@@ -531,7 +534,8 @@ def bench_c3(args):
         femhip.fe_assemble(plan, node, kappa, f, None, gn, val, val_bc, b, b_load, isd)
     e1.record(stream)
     e1.synchronize()
-    sym = symmetric_storage(femhip, torch, plan, node, kappa, f, gn, rowptr, colind, val, N, reps)
+    sym = None if args.no_sym else symmetric_storage(femhip, torch, plan, node, kappa, f, gn, rowptr, colind, val,
+                                                     N, reps)
     femhip.fe_plan_destroy(plan)
     warm_ms = e0.elapsed_time(e1) / reps
     roof = roofline(kernels, read_counters("kuhn129"), N, NT, nnz, 3, True, cold_ms, warm_ms)

@@ -75,8 +75,28 @@ __global__ __launch_bounds__(SB) void k_spmv(int32_t n, const int32_t *__restric
 {
     const int32_t i = blockIdx.x * SB + threadIdx.x;
     if (i >= n) return;
+    // the row in chunks of 8 entries: all of a chunk's column indices and values,
+    // then all its gathers of x, then the products in column order (the same sum
+    // whatever the chunk size)
+    constexpr int CH = 8;
+    const int32_t e = rowptr[i + 1];
     double s = 0.0;
-    for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q) s += cg_value<IND>(val, vidx, q) * x[colind[q]];
+    for (int32_t q0 = rowptr[i]; q0 < e; q0 += CH) {
+        int32_t c[CH];
+        double v[CH], xv[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+            if (q0 + t < e) {
+                c[t] = colind[q0 + t];
+                v[t] = cg_value<IND>(val, vidx, q0 + t);
+            }
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+            if (q0 + t < e) xv[t] = x[c[t]];
+#pragma unroll
+        for (int t = 0; t < CH; ++t)
+            if (q0 + t < e) s += v[t] * xv[t];
+    }
     y[i] = s;
 }
 
