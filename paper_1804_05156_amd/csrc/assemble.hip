@@ -22,6 +22,7 @@
 // when the vertex labels are a random permutation; the only label-ordered
 // accesses left are the row's own outputs.
 #include <cmath>
+#include <type_traits>
 
 #include "fe_internal.h"
 
@@ -134,6 +135,60 @@ FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, i
     for (int c = A.upper ? (int)((A.prow_info[k] >> 8) & 0xff) : 0; c < len; ++c) row[c] = acc[c * BLOCK + tid];
     row[len] = rowd ? gdi : bsum - lift;
     row[len + 1] = bsum;
+}
+
+// Label-order rows of one block, written together (label-order processing: the
+// block's rows are consecutive labels, so their outputs form one contiguous range of
+// val and val_bc).  Each thread stores its row's (row, column) pairs in a map of the
+// range in LDS; the block then walks the range with consecutive threads on
+// consecutive entries and stores val and val_bc with full-line writes, instead of
+// one partial line per thread and column.  The map is the column array of the
+// stored-column kernel (ROWCAP ints per row), free once the walk is done; a range
+// longer than the map (a long row inside the block) takes the per-row writes.
+// Map entry: row (bits 8..15), column (0..7), val_bc is 0 (bit 16) or 1 (bit 17).
+// b, b_load and the Dirichlet mask are one word per row, written per thread.
+template <int ROWCAP, int BLOCK>
+FE_DEV void write_rows_direct(const AsmArgs &A, const double *acc, int32_t *cols, int tid, int32_t kb0, int32_t k,
+                              bool live, int len, int diag, bool rowd, double bsum, double lift, double gdi)
+{
+    static_assert(BLOCK <= 256 && ROWCAP <= 256, "map entry fields");
+    int32_t *map = cols;
+    const int32_t kb1 = min(kb0 + BLOCK, A.N);
+    const int32_t *rp = A.upper ? A.urowptr : A.prowptr;
+    const int64_t S = rp[kb0];
+    const int64_t T = (int64_t)rp[kb1] - S;
+    const int c0 = A.upper ? diag : 0;   // first column written
+    if (live) {
+        A.b[k] = rowd ? gdi : bsum - lift;
+        if (A.b_load) A.b_load[k] = bsum;
+        if (A.isd) A.isd[k] = (uint8_t)rowd;
+    }
+    if (T > (int64_t)ROWCAP * BLOCK) {   // (uniform: a long row inside the block)
+        if (live) write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
+        return;
+    }
+    for (int32_t p = tid; p < T; p += BLOCK) map[p] = -1;   // (a long row's range stays unwritten)
+    __syncthreads();
+    if (live) {
+        const int4 r = A.precp[k];
+        const uint64_t dm = (uint64_t)(uint32_t)r.z | ((uint64_t)(uint32_t)r.w << 32);
+        const int32_t base = (int32_t)((A.upper ? (int64_t)A.urowptr[k] - c0 : (int64_t)A.prowptr[k]) - S);
+        for (int c = c0; c < len; ++c) {
+            int32_t ent = (tid << 8) | c;
+            if (rowd) ent |= (c == diag) ? (1 << 17) : (1 << 16);
+            else if ((dm >> c) & 1ull) ent |= 1 << 16;
+            map[base + c] = ent;
+        }
+    }
+    __syncthreads();
+    double *val = A.val + S, *vbc = A.val_bc ? A.val_bc + S : nullptr;
+    for (int32_t p = tid; p < T; p += BLOCK) {
+        const int32_t ent = map[p];
+        if (ent < 0) continue;
+        const double x = acc[(ent & 0xff) * BLOCK + ((ent >> 8) & 0xff)];
+        val[p] = x;
+        if (vbc) vbc[p] = (ent & (1 << 17)) ? 1.0 : ((ent & (1 << 16)) ? 0.0 : x);
+    }
 }
 
 // Label-order outputs from the processing-order rows: one wavefront per 64
@@ -463,6 +518,7 @@ FE_DEV void cross3(const double *u, const double *v, double *w)
 
 FE_DEV double dot3(const double *u, const double *v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; }
 
+
 // COLS: the other vertices' positions come from the row's stored columns (LDS),
 // indexed by the column offsets in each incidence's metadata word, instead of
 // from a gather of the element's record: same vertices, same arithmetic.
@@ -474,13 +530,22 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     const int tid = threadIdx.x;
     // contiguous rows per XCD: neighbours lie about N^(2/3) positions apart, a window
     // that interleaved blocks would need in every XCD's L2
-    const int32_t k = xcd_block(blockIdx.x, gridDim.x) * BLOCK + tid;
-    if (k >= A.N) return;
+    const int32_t kb0 = xcd_block(blockIdx.x, gridDim.x) * BLOCK;
+    const int32_t k = kb0 + tid;
+    // every thread reaches the block's row write (a barrier): rows past the end and
+    // long rows (k_assemble_long) only skip the computation
+    int len = 0, diag = 0;
+    bool rowd = false, live = false;
+    double bsum = 0.0, lift = 0.0, gdi = 0.0;
+    do {
+    if (k >= A.N) break;
     const int32_t s = A.pincptr[k], e = A.pincptr[k + 1];
     const uint32_t info = A.prow_info[k];
-    if (info & INFO_LONG) return;   // k_assemble_long
-    const int len = info & 0xff, diag = (info >> 8) & 0xff;
-    const bool rowd = (info >> 16) & 1;
+    if (info & INFO_LONG) break;
+    live = true;
+    len = info & 0xff;
+    diag = (info >> 8) & 0xff;
+    rowd = (info >> 16) & 1;
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
     if (COLS) {
         static_assert(!COLS || ROWCAP == 16, "stored columns: 16 per row");
@@ -502,7 +567,6 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
         Y0[0] = q0.x; Y0[1] = q0.y; Y0[2] = q1.x;
         fi = q1.y;
     }
-    double bsum = 0.0, lift = 0.0;
     int32_t err = 0;
     const double alpha = 0.58541019662496845446;   // (5 + 3 sqrt 5) / 20
     const double beta = 0.13819660112501051518;    // (5 - sqrt 5) / 20
@@ -513,101 +577,162 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                          (A.gd.kind != FE_FN_ZERO ? 7u << Meta<4>::DBIT : 0u);
     const bool sell = A.status[ST_SELL] != 0;
     uint32_t bmask = 0;
-    for (int32_t p0 = s; p0 < e; p0 += UNR) {
-        int2 km[UNR];
-        int4 ep[UNR];
-        double kt[UNR];
-        int pq[UNR][3];
-        double Y[UNR][3][3], F[UNR][3];   // F: nodal f at the other vertices
+    // One incidence: row a of K_t into the accumulators, the load term into bsum.
+    auto add_inc = [&](int2 kmu, double ktu, const double (*Yu)[3], const double *Fu) {
+        const uint32_t meta = (uint32_t)kmu.y;
+        const double *Y1 = Yu[0], *Y2 = Yu[1], *Y3 = Yu[2];
+        double d10[3], d20[3], d30[3], d31[3], d21[3];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            if (p0 + u < e) km[u] = A.pincm[inc_at(sell, A.sptr, s, k, p0 - s + u)];
+        for (int c = 0; c < 3; ++c) {
+            d10[c] = Y1[c] - Y0[c];
+            d20[c] = Y2[c] - Y0[c];
+            d30[c] = Y3[c] - Y0[c];
+            d31[c] = Y3[c] - Y1[c];
+            d21[c] = Y2[c] - Y1[c];
+        }
+        double n1[3], n2[3], n3[3], n0[3];
+        cross3(d20, d30, n1);   // side [0 2 3]
+        cross3(d30, d10, n2);   // side [0 3 1]
+        cross3(d10, d20, n3);   // side [0 1 2]
+        for (int c = 0; c < 3; ++c) n0[c] = -(n1[c] + n2[c] + n3[c]);
+        const double vol6 = dot3(n3, d30);
+        if (!(vol6 > 0.0) || !isfinite(vol6)) err |= ERR_MEASURE;
+        if (!(ktu > 0.0) || !isfinite(ktu)) err |= ERR_KAPPA;
+        const double sc = ktu / (6.0 * vol6);
+        const double kr0 = sc * dot3(n0, n0);
+        const double kr[3] = {sc * dot3(n0, n1), sc * dot3(n0, n2), sc * dot3(n0, n3)};
+        acc[diag * BLOCK + tid] += kr0;
+        int off[3];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            if (p0 + u < e) {
-                const int32_t t = km[u].x >> 2;
-                if (!COLS) ep[u] = ep4[t];
-                kt[u] = A.kappa ? A.kappa[t] : 1.0;
+        for (int jj = 0; jj < 3; ++jj) {
+            off[jj] = (meta >> (Meta<4>::OFF + Meta<4>::OB * jj)) & Meta<4>::OMASK;
+            acc[off[jj] * BLOCK + tid] += kr[jj];
+        }
+        const double vol = vol6 / 6.0;
+        // load (Section 3.2): symmetric 4-point rule; exact closed form for nodal f.
+        // Section 4's one-point rule |t| f(c_t) / 4 and vertex rule |t| f(x_i) / 4 on request.
+        if (A.load_rule == FE_LOAD_CENTROID && A.f.kind != FE_FN_ZERO) {
+            double fc;
+            if (nodal_f) {
+                fc = (fi + Fu[0] + Fu[1] + Fu[2]) / 4.0;
+            } else {
+                double c[3];
+                for (int q = 0; q < 3; ++q) c[q] = (Y0[q] + Y1[q] + Y2[q] + Y3[q]) / 4.0;
+                fc = fn_point<3>(A.f, c);
             }
+            bsum += vol * fc / 4.0;
+        } else if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) {
+            bsum += vol * fvert / 4.0;
+        } else if (nodal_f) {
+            const double sf = fi + Fu[0] + Fu[1] + Fu[2];
+            bsum += vol * (fi + sf) / 20.0;
+        } else if (A.f.kind != FE_FN_ZERO) {
+            double S[3];
 #pragma unroll
-        for (int u = 0; u < UNR; ++u)
-            if (p0 + u < e) {
-                const int a = km[u].x & 3;
-                const uint32_t meta = (uint32_t)km[u].y;
+            for (int c = 0; c < 3; ++c) S[c] = Y0[c] + Y1[c] + Y2[c] + Y3[c];
+            double q = 0.0;
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    pq[u][q] = COLS ? cols[(int)((meta >> (Meta<4>::OFF + Meta<4>::OB * q)) & Meta<4>::OMASK) * BLOCK + tid]
-                                    : sel4(ep[u], fe_other<4>(a, q));
-                    const double2 c0 = xy[2 * (int64_t)pq[u][q]], c1 = xy[2 * (int64_t)pq[u][q] + 1];
-                    Y[u][q][0] = c0.x; Y[u][q][1] = c0.y; Y[u][q][2] = c1.x;
-                    F[u][q] = c1.y;
+            for (int kq = 0; kq < 4; ++kq) {
+                const double *Yk = kq == 0 ? Y0 : Yu[kq - 1];
+                double pt[3];
+                for (int c = 0; c < 3; ++c) pt[c] = beta * S[c] + (alpha - beta) * Yk[c];
+                q += fn_point<3>(A.f, pt) * (kq == 0 ? alpha : beta);
+            }
+            bsum += vol * q / 4.0;
+        }
+        bmask |= meta;
+    };
+    if constexpr (COLS) {
+        // Software pipeline over batches of UNR incidences: the gathers of batch j + 1
+        // and the keys of batch j + 2 are in flight while batch j is added.  The wait
+        // counter retires loads in issue order, so every load is issued after the ones
+        // that are needed before it; the loop is unrolled twice so the two gather
+        // buffers swap roles instead of being copied (a copy would wait for the loads).
+        // Positions past the row's end are clamped to its last incidence: every load
+        // is valid and needs no branch, and only the additions are predicated.
+        if (e > s) {
+            const int32_t last = e - 1 - s;
+            auto walk = [&](auto has_kappa) {
+                constexpr bool KAP = decltype(has_kappa)::value;
+                auto ld_km = [&](int32_t q0, int2 *km) {
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) km[u] = A.pincm[inc_at(sell, A.sptr, s, k, min(q0 + u, last))];
+                };
+                // gathers of one batch: kappa and the other vertices' records, by the
+                // column offsets of the metadata word (kept in m for the additions)
+                auto ld_g = [&](const int2 *km, uint32_t *m, double *kt, double (*Y)[3][3], double (*F)[3]) {
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u) {
+                        kt[u] = KAP ? A.kappa[km[u].x >> 2] : 1.0;
+                        m[u] = (uint32_t)km[u].y;
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) {
+                            const int32_t pq = cols[(int)((m[u] >> (Meta<4>::OFF + Meta<4>::OB * q)) & Meta<4>::OMASK) * BLOCK + tid];
+                            const double2 c0 = xy[2 * (int64_t)pq], c1 = xy[2 * (int64_t)pq + 1];
+                            Y[u][q][0] = c0.x; Y[u][q][1] = c0.y; Y[u][q][2] = c1.x;
+                            F[u][q] = c1.y;
+                        }
+                    }
+                };
+                auto add_batch = [&](int32_t q0, const uint32_t *m, const double *kt, const double (*Y)[3][3],
+                                     const double (*F)[3]) {
+#pragma unroll
+                    for (int u = 0; u < UNR; ++u)
+                        if (q0 + u <= last) add_inc(make_int2(0, (int32_t)m[u]), kt[u], Y[u], F[u]);
+                };
+                int2 kmX[UNR], kmY[UNR];
+                uint32_t mX[UNR], mY[UNR];
+                double ktX[UNR], YX[UNR][3][3], FX[UNR][3];
+                double ktY[UNR], YY[UNR][3][3], FY[UNR][3];
+                ld_km(0, kmX);
+                ld_km(UNR, kmY);
+                ld_g(kmX, mX, ktX, YX, FX);
+                ld_km(2 * UNR, kmX);
+                for (int32_t q0 = 0; q0 <= last; q0 += 2 * UNR) {
+                    ld_g(kmY, mY, ktY, YY, FY);
+                    ld_km(q0 + 3 * UNR, kmY);
+                    add_batch(q0, mX, ktX, YX, FX);
+                    ld_g(kmX, mX, ktX, YX, FX);
+                    ld_km(q0 + 4 * UNR, kmX);
+                    add_batch(q0 + UNR, mY, ktY, YY, FY);
                 }
-            }
+            };
+            if (A.kappa) walk(std::true_type{});
+            else walk(std::false_type{});
+        }
+    } else {
+        for (int32_t p0 = s; p0 < e; p0 += UNR) {
+            int2 km[UNR];
+            int4 ep[UNR];
+            double kt[UNR];
+            double Y[UNR][3][3], F[UNR][3];   // F: nodal f at the other vertices
 #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            if (p0 + u >= e) break;
-            const uint32_t meta = (uint32_t)km[u].y;
-            const double *Y1 = Y[u][0], *Y2 = Y[u][1], *Y3 = Y[u][2];
-            double d10[3], d20[3], d30[3], d31[3], d21[3];
+            for (int u = 0; u < UNR; ++u)
+                if (p0 + u < e) km[u] = A.pincm[inc_at(sell, A.sptr, s, k, p0 - s + u)];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                d10[c] = Y1[c] - Y0[c];
-                d20[c] = Y2[c] - Y0[c];
-                d30[c] = Y3[c] - Y0[c];
-                d31[c] = Y3[c] - Y1[c];
-                d21[c] = Y2[c] - Y1[c];
-            }
-            double n1[3], n2[3], n3[3], n0[3];
-            cross3(d20, d30, n1);   // side [0 2 3]
-            cross3(d30, d10, n2);   // side [0 3 1]
-            cross3(d10, d20, n3);   // side [0 1 2]
-            for (int c = 0; c < 3; ++c) n0[c] = -(n1[c] + n2[c] + n3[c]);
-            const double vol6 = dot3(n3, d30);
-            if (!(vol6 > 0.0) || !isfinite(vol6)) err |= ERR_MEASURE;
-            if (!(kt[u] > 0.0) || !isfinite(kt[u])) err |= ERR_KAPPA;
-            const double sc = kt[u] / (6.0 * vol6);
-            const double kr0 = sc * dot3(n0, n0);
-            const double kr[3] = {sc * dot3(n0, n1), sc * dot3(n0, n2), sc * dot3(n0, n3)};
-            acc[diag * BLOCK + tid] += kr0;
-            int off[3];
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj) {
-                off[jj] = (meta >> (Meta<4>::OFF + Meta<4>::OB * jj)) & Meta<4>::OMASK;
-                acc[off[jj] * BLOCK + tid] += kr[jj];
-            }
-            const double vol = vol6 / 6.0;
-            // load (Section 3.2): symmetric 4-point rule; exact closed form for nodal f.
-            // Section 4's one-point rule |t| f(c_t) / 4 and vertex rule |t| f(x_i) / 4 on request.
-            if (A.load_rule == FE_LOAD_CENTROID && A.f.kind != FE_FN_ZERO) {
-                double fc;
-                if (nodal_f) {
-                    fc = (fi + F[u][0] + F[u][1] + F[u][2]) / 4.0;
-                } else {
-                    double c[3];
-                    for (int q = 0; q < 3; ++q) c[q] = (Y0[q] + Y1[q] + Y2[q] + Y3[q]) / 4.0;
-                    fc = fn_point<3>(A.f, c);
+            for (int u = 0; u < UNR; ++u)
+                if (p0 + u < e) {
+                    const int32_t t = km[u].x >> 2;
+                    ep[u] = ep4[t];
+                    kt[u] = A.kappa ? A.kappa[t] : 1.0;
                 }
-                bsum += vol * fc / 4.0;
-            } else if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) {
-                bsum += vol * fvert / 4.0;
-            } else if (nodal_f) {
-                const double sf = fi + F[u][0] + F[u][1] + F[u][2];
-                bsum += vol * (fi + sf) / 20.0;
-            } else if (A.f.kind != FE_FN_ZERO) {
-                double S[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) S[c] = Y0[c] + Y1[c] + Y2[c] + Y3[c];
-                double q = 0.0;
+            for (int u = 0; u < UNR; ++u)
+                if (p0 + u < e) {
+                    const int a = km[u].x & 3;
 #pragma unroll
-                for (int kq = 0; kq < 4; ++kq) {
-                    const double *Yk = kq == 0 ? Y0 : Y[u][kq - 1];
-                    double pt[3];
-                    for (int c = 0; c < 3; ++c) pt[c] = beta * S[c] + (alpha - beta) * Yk[c];
-                    q += fn_point<3>(A.f, pt) * (kq == 0 ? alpha : beta);
+                    for (int q = 0; q < 3; ++q) {
+                        const int pq = sel4(ep[u], fe_other<4>(a, q));
+                        const double2 c0 = xy[2 * (int64_t)pq], c1 = xy[2 * (int64_t)pq + 1];
+                        Y[u][q][0] = c0.x; Y[u][q][1] = c0.y; Y[u][q][2] = c1.x;
+                        F[u][q] = c1.y;
+                    }
                 }
-                bsum += vol * q / 4.0;
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+                if (p0 + u >= e) break;
+                add_inc(km[u], kt[u], Y[u], F[u]);
             }
-            bmask |= meta;
         }
     }
     // Boundary terms of the row (Neumann and Robin faces through its vertex, lifting
@@ -726,9 +851,14 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
         }
     }
     if (err) atomicOr(A.status + ST_ERR, err);
-    double gdi = 0.0;
     if (rowd) gdi = dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[k] : 0, Y0);
-    write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
+    } while (false);
+    if (COLS && A.direct) {
+        __syncthreads();   // (the walk above reads cols, which the writer reuses)
+        write_rows_direct<ROWCAP, BLOCK>(A, acc, cols, tid, kb0, k, live, len, diag, rowd, bsum, lift, gdi);
+    } else if (live) {
+        write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
+    }
 }
 
 // ----------------------------------------------------------------------------- long rows
