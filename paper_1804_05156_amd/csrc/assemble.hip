@@ -137,6 +137,47 @@ FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, i
     row[len + 1] = bsum;
 }
 
+// Processing-order row slots of one block, written together.  Consecutive rows'
+// slots (values, b, b_load) are consecutive in valp, so the block's slots form one
+// range; each thread enters its slot's entries in an LDS map of the range, then the
+// block walks the range with consecutive threads on consecutive entries, which
+// turns one partial-line store per thread and column into full-line stores.  Map
+// entry: row << 5 | column, column 30 for b and 31 for b_load (kept in rhs); a
+// range longer than the map (a long row inside the block) takes the per-row writes.
+template <int ROWCAP, int BLOCK>
+FE_DEV void write_rows_slots(const AsmArgs &A, const double *acc, uint16_t *map, double *rhs, int tid, int32_t kb0,
+                             int32_t k, bool live, int len, int diag, bool rowd, double bsum, double lift, double gdi)
+{
+    static_assert(BLOCK <= 2048 && ROWCAP <= 16, "map entry fields");
+    constexpr uint16_t NONE = 0xffff;
+    const int32_t kb1 = min(kb0 + BLOCK, A.N);
+    const int64_t S = (int64_t)A.prowptr[kb0] + 2 * (int64_t)kb0;
+    const int64_t T = (int64_t)A.prowptr[kb1] + 2 * (int64_t)kb1 - S;
+    if (T > (int64_t)(ROWCAP + 2) * BLOCK) {   // (uniform: a long row inside the block)
+        if (live) write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
+        return;
+    }
+    for (int32_t p = tid; p < T; p += BLOCK) map[p] = NONE;
+    __syncthreads();
+    if (live) {
+        const int32_t base = (int32_t)((int64_t)A.prowptr[k] + 2 * (int64_t)k - S);
+        // (the upper form needs the columns from the diagonal on)
+        for (int c = A.upper ? diag : 0; c < len; ++c) map[base + c] = (uint16_t)((tid << 5) | c);
+        map[base + len] = (uint16_t)((tid << 5) | 30);
+        map[base + len + 1] = (uint16_t)((tid << 5) | 31);
+        rhs[tid] = rowd ? gdi : bsum - lift;
+        rhs[BLOCK + tid] = bsum;
+    }
+    __syncthreads();
+    double *out = A.valp + S;
+    for (int32_t p = tid; p < T; p += BLOCK) {
+        const uint32_t ent = map[p];
+        if (ent == NONE) continue;
+        const int r = (int)(ent >> 5), c = (int)(ent & 31);
+        out[p] = c < 30 ? acc[c * BLOCK + r] : rhs[(c - 30) * BLOCK + r];
+    }
+}
+
 // Label-order rows of one block, written together (label-order processing: the
 // block's rows are consecutive labels, so their outputs form one contiguous range of
 // val and val_bc).  Each thread stores its row's (row, column) pairs in a map of the
@@ -294,19 +335,30 @@ template <int ROWCAP, int BLOCK, int UNR>
 __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
 {
     __shared__ double acc[ROWCAP * BLOCK];
+    constexpr bool SLOTW = ROWCAP <= 16;   // block-wide slot writes (map entry fields)
+    __shared__ uint16_t map[SLOTW ? (ROWCAP + 2) * BLOCK : 1];
+    __shared__ double rhs[SLOTW ? 2 * BLOCK : 1];
     const int tid = threadIdx.x;
-    const int32_t k = blockIdx.x * BLOCK + tid;
-    if (k >= A.N) return;
+    const int32_t kb0 = blockIdx.x * BLOCK;
+    const int32_t k = kb0 + tid;
+    // every thread reaches the block's row write (a barrier): rows past the end and
+    // long rows (k_assemble_long) only skip the computation
+    int len = 0, diag = 0;
+    bool rowd = false, live = false;
+    double bsum = 0.0, lift = 0.0, gdi = 0.0;
+    do {
+    if (k >= A.N) break;
     const int32_t s = A.pincptr[k], e = A.pincptr[k + 1];
     const uint32_t info = A.prow_info[k];
-    if (info & INFO_LONG) return;   // k_assemble_long
-    const int len = info & 0xff, diag = (info >> 8) & 0xff;
-    const bool rowd = (info >> 16) & 1;
+    if (info & INFO_LONG) break;
+    live = true;
+    len = info & 0xff;
+    diag = (info >> 8) & 0xff;
+    rowd = (info >> 16) & 1;
     for (int c = 0; c < len; ++c) acc[c * BLOCK + tid] = 0.0;
     const double2 X0 = reinterpret_cast<const double2 *>(A.xyp)[k];
     const double2 *xy = reinterpret_cast<const double2 *>(A.xyp);
     const int4 *ep4 = reinterpret_cast<const int4 *>(A.elemp);
-    double bsum = 0.0, lift = 0.0;
     int32_t err = 0;
     const bool nodal_f = A.f.kind == FE_FN_NODAL;
     const double fi = nodal_f ? A.fp[k] : 0.0;
@@ -494,12 +546,18 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
         }
     }
     if (err) atomicOr(A.status + ST_ERR, err);
-    double gdi = 0.0;
     if (rowd) {
         const double x0[2] = {X0.x, X0.y};
         gdi = dirichlet_value<2>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[k] : 0, x0);
     }
-    write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
+    } while (false);
+    if constexpr (SLOTW) {
+        if (!A.direct) {
+            write_rows_slots<ROWCAP, BLOCK>(A, acc, map, rhs, tid, kb0, k, live, len, diag, rowd, bsum, lift, gdi);
+            return;
+        }
+    }
+    if (live) write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
 }
 
 // ----------------------------------------------------------------------------- 3-D
@@ -1190,12 +1248,16 @@ __global__ __launch_bounds__(LNB) void k_assemble_long(AsmArgs A)
 template <int ROWCAP, int BLOCK> int launch(int dim, const AsmArgs &A, hipStream_t s)
 {
     const unsigned g = (unsigned)cdiv(A.N, BLOCK);
-    if (dim == 2) FE_TIMED("k_assemble_2d", s,
-             hipLaunchKernelGGL((k_assemble_2d<ROWCAP, BLOCK, 4>), dim3(g), dim3(BLOCK), 0, s, A));
-    else if (ROWCAP == 16 && A.rcols) FE_TIMED("k_assemble_3d", s,
-             hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2, ROWCAP == 16>), dim3(g), dim3(BLOCK), 0, s, A));
-    else FE_TIMED("k_assemble_3d", s,
-             hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2, false>), dim3(g), dim3(BLOCK), 0, s, A));
+    if (dim == 2) {
+        FE_TIMED("k_assemble_2d", s, hipLaunchKernelGGL((k_assemble_2d<ROWCAP, BLOCK, 4>), dim3(g), dim3(BLOCK), 0, s, A));
+    } else if constexpr (ROWCAP >= 16) {   // (3-D rows have at least 15 columns in the interior)
+        if (ROWCAP == 16 && A.rcols)
+            FE_TIMED("k_assemble_3d", s,
+                     hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2, ROWCAP == 16>), dim3(g), dim3(BLOCK), 0, s, A));
+        else
+            FE_TIMED("k_assemble_3d", s,
+                     hipLaunchKernelGGL((k_assemble_3d<ROWCAP, BLOCK, 2, false>), dim3(g), dim3(BLOCK), 0, s, A));
+    }
     return fe_launch_check();
 }
 
@@ -1267,7 +1329,10 @@ int assemble_impl(fe_plan *plan, const int32_t *urowptr, const double *node, con
     // block whose accumulators take 32 KB of LDS)
     const int mr = plan->max_row;
     const int wb = plan->asm_block;
-    if (mr <= 16) rc = (wb == 64)    ? launch<16, 64>(plan->dim, A, s)
+    if (plan->dim == 2 && mr <= 8) rc = (wb == 64)    ? launch<8, 64>(plan->dim, A, s)
+                                        : (wb == 128) ? launch<8, 128>(plan->dim, A, s)
+                                                      : launch<8, 256>(plan->dim, A, s);
+    else if (mr <= 16) rc = (wb == 64) ? launch<16, 64>(plan->dim, A, s)
                        : (wb == 128) ? launch<16, 128>(plan->dim, A, s)
                                      : launch<16, 256>(plan->dim, A, s);
     else if (mr <= 32 || plan->dim == 2) rc = (wb == 64) ? launch<32, 64>(plan->dim, A, s)
