@@ -99,6 +99,7 @@ struct fe_plan {
     const int32_t *elem;
     const int8_t *bdflag;
     int32_t bs, nb, nblk1;   // bucket shift (2^bs vertices per bucket), bucket count, level-1 chunks
+    int32_t chn;             // elements per level-1 chunk
     // device arrays inside the caller's workspace
     int32_t *status;      // ST_COUNT ints
     int64_t *totals;      // scan totals (4 slots)

@@ -32,7 +32,8 @@ namespace {
 
 constexpr int EBLOCK = 256;     // element-parallel kernels
 constexpr int L1B = 1024;       // threads of the level-1 kernels
-constexpr int L1CH = 32768;     // elements per level-1 chunk
+constexpr int L1CH = 32768;     // elements per level-1 chunk at most
+constexpr int L1CUS = 256;      // compute units: the level-1 chunk count is a multiple of it
 constexpr int NBMAX = 524288;   // buckets (2^19: with 2^12 vertices each, every int32 label)
 constexpr int VBMAX = 4096;     // vertices per bucket (2^bs) at most
 constexpr int BKB = 256;        // threads of the bucket kernel
@@ -86,7 +87,8 @@ FE_DEV int32_t check_element(const int32_t *__restrict__ elem, const int8_t *__r
 template <int NV>
 __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ elem, const int8_t *__restrict__ bd,
                                                  int32_t NT, int32_t N, int32_t bs, uint64_t cmul, int32_t nb,
-                                                 int32_t nblk1, int32_t *hist1, uint8_t *isd, int32_t *status)
+                                                 int32_t nblk1, int32_t chn, int32_t *hist1, uint8_t *isd,
+                                                 int32_t *status)
 {
     extern __shared__ int32_t h[];
     __shared__ int32_t block_runs;
@@ -94,8 +96,8 @@ __global__ __launch_bounds__(L1B) void k_l1_hist(const int32_t *__restrict__ ele
     if (threadIdx.x == 0) block_runs = 0;
     __syncthreads();
     const int32_t ch = l1_chunk(blockIdx.x, nblk1);
-    const int32_t t0 = ch * L1CH;
-    const int32_t t1 = min(NT, t0 + L1CH);
+    const int32_t t0 = ch * chn;
+    const int32_t t1 = min(NT, t0 + chn);
     int32_t err = 0;
     int32_t runs = 0;   // wavefront calls with 16 or more lanes in runs of equal buckets (lane 0 counts)
     // every lane runs every trip (the counts are aggregated across the wavefront)
@@ -153,7 +155,8 @@ FE_DEV void erec_words(int32_t t, const int32_t *v, int32_t NT, const int8_t *__
 // AGG (labels that follow the element order) also writes the element records.
 template <int NV, bool AGG>
 __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ elem, int32_t NT, int32_t bs,
-                                                    uint64_t cmul, int32_t nb, int32_t nblk1, const int32_t *__restrict__ offs,
+                                                    uint64_t cmul, int32_t nb, int32_t nblk1, int32_t chn,
+                                                    const int32_t *__restrict__ offs,
                                                     int2 *pairs, const int8_t *__restrict__ bd,
                                                     const uint8_t *__restrict__ isd, int4 *elemp)
 {
@@ -170,8 +173,8 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
         cnt[tid] = 0;
     }
     __syncthreads();
-    const int32_t t0 = ch * L1CH;
-    const int32_t t1 = min(NT, t0 + L1CH);
+    const int32_t t0 = ch * chn;
+    const int32_t t1 = min(NT, t0 + chn);
     for (int32_t s0 = t0; s0 < t1; s0 += L1SUB) {
         int32_t v[PER][NV], rk[PER][NV], w[PER][NV];
 #pragma unroll
@@ -1092,7 +1095,7 @@ __global__ __launch_bounds__(STB) void k_stats_final(int32_t nb, const int64_t *
 
 // Bucket size: about 4096 incidences per bucket on average, at most NBMAX buckets.
 struct Buckets {
-    int32_t bs, nb, fine, ncb, nblk1;
+    int32_t bs, nb, fine, ncb, nblk1, chn;   // chn: elements per level-1 chunk
     uint64_t cmul;   // ceil(2^32 / fine)
 };
 
@@ -1114,7 +1117,14 @@ Buckets choose_buckets(int64_t N, int64_t NT, int nv)
     B.fine = (int32_t)(B.nb > L1SLOTS ? cdiv(B.nb, L1SLOTS) : 1);
     B.ncb = (int32_t)cdiv(B.nb, B.fine);
     B.cmul = ((uint64_t)1 << 32) / (uint64_t)B.fine + (((uint64_t)1 << 32) % (uint64_t)B.fine ? 1 : 0);
-    B.nblk1 = (int32_t)cdiv(NT > 0 ? NT : 1, L1CH);
+    // level-1 chunks: a whole number of chunks per CU (129^3: 512 chunks of 24576
+    // elements instead of 384 of 32768, which left half of the CUs with one chunk and
+    // half with two; 2049^2 keeps 256 of 32768), in multiples of the LDS sub-chunk
+    const int64_t nt = NT > 0 ? NT : 1;
+    const int64_t want = cdiv(cdiv(nt, (int64_t)L1CH), (int64_t)L1CUS) * L1CUS;
+    const int64_t ch = cdiv(cdiv(nt, want), (int64_t)L1SUB) * L1SUB;
+    B.chn = (int32_t)ch;
+    B.nblk1 = (int32_t)cdiv(nt, ch);
     return B;
 }
 
@@ -1282,7 +1292,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
     if (NT > 0)
         FE_TIMED("k_l1_hist", s,
                  hipLaunchKernelGGL(k_l1_hist<NV>, dim3((unsigned)P->nblk1), dim3(L1B), l1lds, s, P->elem, P->bdflag, NT, N,
-                               P->bs, P->cmul, P->ncb, P->nblk1, P->hist1, P->isd, P->status));
+                               P->bs, P->cmul, P->ncb, P->nblk1, P->chn, P->hist1, P->isd, P->status));
     if ((rc = fe_launch_check())) return rc;
     // Vertex indices are validated by the histogram kernel only: stop here, before
     // any kernel uses elem entries as addresses, if one was out of range.
@@ -1297,7 +1307,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
         // that found such runs.
         int64_t calls = 0;
         for (int64_t ch = 0; ch < P->nblk1; ++ch) {
-            const int64_t len = std::min<int64_t>(L1CH, (int64_t)NT - ch * L1CH);
+            const int64_t len = std::min<int64_t>(P->chn, (int64_t)NT - ch * P->chn);
             calls += cdiv(len, L1B) * NV * (L1B / 64);
         }
         // (label-order processing stores labels as positions in the element records)
@@ -1308,7 +1318,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, true>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
-                                        P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
+                                        P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, P->chn, (const int32_t *)P->hist1, P->pairs,
                                         P->bdflag, (const uint8_t *)P->isd, reinterpret_cast<int4 *>(P->elemp)));
             FE_TIMED("k_l1_fine", s,
                      hipLaunchKernelGGL(k_l1_fine<true>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->fine, P->ncb,
@@ -1319,7 +1329,7 @@ template <int NV> int plan_build(fe_plan *P, hipStream_t s)
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * l1lds)));
             FE_TIMED("k_l1_scatter", s,
                      hipLaunchKernelGGL((k_l1_scatter<NV, false>), dim3((unsigned)P->nblk1), dim3(L1B), 2 * l1lds, s,
-                                        P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, (const int32_t *)P->hist1, P->pairs,
+                                        P->elem, NT, P->bs, P->cmul, P->ncb, P->nblk1, P->chn, (const int32_t *)P->hist1, P->pairs,
                                         nullptr, nullptr, nullptr));
             FE_TIMED("k_l1_fine", s,
                      hipLaunchKernelGGL(k_l1_fine<false>, dim3((unsigned)P->ncb), dim3(FB), 0, s, P->nb, P->bs, P->fine, P->ncb,
@@ -1505,6 +1515,7 @@ extern "C" int fe_plan_create(const fe_mesh *mesh, void *ws, size_t ws_bytes, fe
     P->nb = Bk.nb;
     P->ncb = Bk.ncb;
     P->nblk1 = Bk.nblk1;
+    P->chn = Bk.chn;
     P->status = reinterpret_cast<int32_t *>(base + L.off[W_STATUS]);
     P->totals = reinterpret_cast<int64_t *>(base + L.off[W_TOTALS]);
     P->part = reinterpret_cast<int64_t *>(base + L.off[W_PART]);
