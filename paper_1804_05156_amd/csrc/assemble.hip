@@ -137,96 +137,110 @@ FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, i
     row[len + 1] = bsum;
 }
 
-// Processing-order row slots of one block, written together.  Consecutive rows'
-// slots (values, b, b_load) are consecutive in valp, so the block's slots form one
-// range; each thread enters its slot's entries in an LDS map of the range, then the
-// block walks the range with consecutive threads on consecutive entries, which
-// turns one partial-line store per thread and column into full-line stores.  Map
-// entry: row << 5 | column, column 30 for b and 31 for b_load (kept in rhs); a
-// range longer than the map (a long row inside the block) takes the per-row writes.
-template <int ROWCAP, int BLOCK>
-FE_DEV void write_rows_slots(const AsmArgs &A, const double *acc, uint16_t *map, double *rhs, int tid, int32_t kb0,
-                             int32_t k, bool live, int len, int diag, bool rowd, double bsum, double lift, double gdi)
+// Order the LDS accesses of one wavefront: every lane's earlier LDS stores are seen
+// by every lane's later loads (the row writers below work per wavefront, with no
+// workgroup barrier).
+FE_DEV void wave_lds_sync()
 {
-    static_assert(BLOCK <= 2048 && ROWCAP <= 16, "map entry fields");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Processing-order row slots of one wavefront, written together.  Consecutive rows'
+// slots (values, b, b_load) are consecutive in valp, so the wavefront's 64 slots form
+// one range; each lane enters its slot's entries in an LDS map of the range, then
+// the lanes walk the range on consecutive entries, which turns one partial-line
+// store per lane and column into full-line stores.  Map entry: lane << 5 | column,
+// column 30 for b and 31 for b_load (kept in rhs); a range longer than the map (a
+// long row among the 64) takes the per-row writes.  map: (ROWCAP + 2) * 64 entries
+// and rhs: 128 values, both the wavefront's own.
+template <int ROWCAP, int BLOCK>
+FE_DEV void write_rows_slots(const AsmArgs &A, const double *acc, uint16_t *map, double *rhs, int tid, int32_t k,
+                             bool live, int len, int diag, bool rowd, double bsum, double lift, double gdi)
+{
+    static_assert(ROWCAP <= 16, "map entry fields");
     constexpr uint16_t NONE = 0xffff;
-    const int32_t kb1 = min(kb0 + BLOCK, A.N);
-    const int64_t S = (int64_t)A.prowptr[kb0] + 2 * (int64_t)kb0;
-    const int64_t T = (int64_t)A.prowptr[kb1] + 2 * (int64_t)kb1 - S;
-    if (T > (int64_t)(ROWCAP + 2) * BLOCK) {   // (uniform: a long row inside the block)
+    const int lane = tid & 63;
+    const int32_t kw0 = k - lane, kw1 = min(kw0 + 64, A.N);
+    const int64_t S = (int64_t)A.prowptr[kw0] + 2 * (int64_t)kw0;
+    const int32_t T = (int32_t)((int64_t)A.prowptr[kw1] + 2 * (int64_t)kw1 - S);
+    if (T > (ROWCAP + 2) * 64) {   // (uniform in the wavefront: a long row among its rows)
         if (live) write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
         return;
     }
-    for (int32_t p = tid; p < T; p += BLOCK) map[p] = NONE;
-    __syncthreads();
+    for (int32_t p = lane; p < T; p += 64) map[p] = NONE;
+    wave_lds_sync();
     if (live) {
         const int32_t base = (int32_t)((int64_t)A.prowptr[k] + 2 * (int64_t)k - S);
         // (the upper form needs the columns from the diagonal on)
-        for (int c = A.upper ? diag : 0; c < len; ++c) map[base + c] = (uint16_t)((tid << 5) | c);
-        map[base + len] = (uint16_t)((tid << 5) | 30);
-        map[base + len + 1] = (uint16_t)((tid << 5) | 31);
-        rhs[tid] = rowd ? gdi : bsum - lift;
-        rhs[BLOCK + tid] = bsum;
+        for (int c = A.upper ? diag : 0; c < len; ++c) map[base + c] = (uint16_t)((lane << 5) | c);
+        map[base + len] = (uint16_t)((lane << 5) | 30);
+        map[base + len + 1] = (uint16_t)((lane << 5) | 31);
+        rhs[lane] = rowd ? gdi : bsum - lift;
+        rhs[64 + lane] = bsum;
     }
-    __syncthreads();
+    wave_lds_sync();
     double *out = A.valp + S;
-    for (int32_t p = tid; p < T; p += BLOCK) {
+    const double *accw = acc + (tid - lane);
+    for (int32_t p = lane; p < T; p += 64) {
         const uint32_t ent = map[p];
         if (ent == NONE) continue;
         const int r = (int)(ent >> 5), c = (int)(ent & 31);
-        out[p] = c < 30 ? acc[c * BLOCK + r] : rhs[(c - 30) * BLOCK + r];
+        out[p] = c < 30 ? accw[c * BLOCK + r] : rhs[(c - 30) * 64 + r];
     }
 }
 
-// Label-order rows of one block, written together (label-order processing: the
-// block's rows are consecutive labels, so their outputs form one contiguous range of
-// val and val_bc).  Each thread stores its row's (row, column) pairs in a map of the
-// range in LDS; the block then walks the range with consecutive threads on
-// consecutive entries and stores val and val_bc with full-line writes, instead of
-// one partial line per thread and column.  The map is the column array of the
-// stored-column kernel (ROWCAP ints per row), free once the walk is done; a range
-// longer than the map (a long row inside the block) takes the per-row writes.
-// Map entry: row (bits 8..15), column (0..7), val_bc is 0 (bit 16) or 1 (bit 17).
-// b, b_load and the Dirichlet mask are one word per row, written per thread.
+// Label-order rows of one wavefront, written together (label-order processing: the
+// 64 rows are consecutive labels, so their outputs form one contiguous range of val
+// and val_bc).  Each lane stores its row's (lane, column) pairs in an LDS map of the
+// range; the lanes then walk the range on consecutive entries and store val and
+// val_bc with full-line writes, instead of one partial line per lane and column.
+// The map is the wavefront's own part of the stored-column array (ROWCAP ints per
+// row), free once its walk is done; a range longer than the map (a long row among
+// the 64) takes the per-row writes.  Map entry: lane (bits 8..13), column (0..7),
+// val_bc is 0 (bit 16) or 1 (bit 17).  b, b_load and the Dirichlet mask are one word
+// per row, written per lane.
 template <int ROWCAP, int BLOCK>
-FE_DEV void write_rows_direct(const AsmArgs &A, const double *acc, int32_t *cols, int tid, int32_t kb0, int32_t k,
-                              bool live, int len, int diag, bool rowd, double bsum, double lift, double gdi)
+FE_DEV void write_rows_direct(const AsmArgs &A, const double *acc, int32_t *map, int tid, int32_t k, bool live,
+                              int len, int diag, bool rowd, double bsum, double lift, double gdi)
 {
-    static_assert(BLOCK <= 256 && ROWCAP <= 256, "map entry fields");
-    int32_t *map = cols;
-    const int32_t kb1 = min(kb0 + BLOCK, A.N);
+    static_assert(ROWCAP <= 256, "map entry fields");
+    const int lane = tid & 63;
+    const int32_t kw0 = k - lane, kw1 = min(kw0 + 64, A.N);
     const int32_t *rp = A.upper ? A.urowptr : A.prowptr;
-    const int64_t S = rp[kb0];
-    const int64_t T = (int64_t)rp[kb1] - S;
+    const int64_t S = rp[kw0];
+    const int32_t T = (int32_t)((int64_t)rp[kw1] - S);
     const int c0 = A.upper ? diag : 0;   // first column written
     if (live) {
         A.b[k] = rowd ? gdi : bsum - lift;
         if (A.b_load) A.b_load[k] = bsum;
         if (A.isd) A.isd[k] = (uint8_t)rowd;
     }
-    if (T > (int64_t)ROWCAP * BLOCK) {   // (uniform: a long row inside the block)
+    if (T > ROWCAP * 64) {   // (uniform in the wavefront: a long row among its rows)
         if (live) write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
         return;
     }
-    for (int32_t p = tid; p < T; p += BLOCK) map[p] = -1;   // (a long row's range stays unwritten)
-    __syncthreads();
+    for (int32_t p = lane; p < T; p += 64) map[p] = -1;   // (a long row's range stays unwritten)
+    wave_lds_sync();
     if (live) {
         const int4 r = A.precp[k];
         const uint64_t dm = (uint64_t)(uint32_t)r.z | ((uint64_t)(uint32_t)r.w << 32);
         const int32_t base = (int32_t)((A.upper ? (int64_t)A.urowptr[k] - c0 : (int64_t)A.prowptr[k]) - S);
         for (int c = c0; c < len; ++c) {
-            int32_t ent = (tid << 8) | c;
+            int32_t ent = (lane << 8) | c;
             if (rowd) ent |= (c == diag) ? (1 << 17) : (1 << 16);
             else if ((dm >> c) & 1ull) ent |= 1 << 16;
             map[base + c] = ent;
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     double *val = A.val + S, *vbc = A.val_bc ? A.val_bc + S : nullptr;
-    for (int32_t p = tid; p < T; p += BLOCK) {
+    const double *accw = acc + (tid - lane);
+    for (int32_t p = lane; p < T; p += 64) {
         const int32_t ent = map[p];
         if (ent < 0) continue;
-        const double x = acc[(ent & 0xff) * BLOCK + ((ent >> 8) & 0xff)];
+        const double x = accw[(ent & 0xff) * BLOCK + ((ent >> 8) & 0xff)];
         val[p] = x;
         if (vbc) vbc[p] = (ent & (1 << 17)) ? 1.0 : ((ent & (1 << 16)) ? 0.0 : x);
     }
@@ -339,8 +353,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
     __shared__ uint16_t map[SLOTW ? (ROWCAP + 2) * BLOCK : 1];
     __shared__ double rhs[SLOTW ? 2 * BLOCK : 1];
     const int tid = threadIdx.x;
-    const int32_t kb0 = blockIdx.x * BLOCK;
-    const int32_t k = kb0 + tid;
+    const int32_t k = blockIdx.x * BLOCK + tid;
     // every thread reaches the block's row write (a barrier): rows past the end and
     // long rows (k_assemble_long) only skip the computation
     int len = 0, diag = 0;
@@ -553,7 +566,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
     } while (false);
     if constexpr (SLOTW) {
         if (!A.direct) {
-            write_rows_slots<ROWCAP, BLOCK>(A, acc, map, rhs, tid, kb0, k, live, len, diag, rowd, bsum, lift, gdi);
+            write_rows_slots<ROWCAP, BLOCK>(A, acc, map + (tid >> 6) * ((ROWCAP + 2) * 64), rhs + (tid >> 6) * 128, tid, k,
+                                            live, len, diag, rowd, bsum, lift, gdi);
             return;
         }
     }
@@ -584,12 +598,15 @@ template <int ROWCAP, int BLOCK, int UNR, bool COLS>
 __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
 {
     __shared__ double acc[ROWCAP * BLOCK];
+    // stored columns, each wavefront's rows in its own part: column q of the row of
+    // lane l of wavefront w at (w * ROWCAP + q) * 64 + l (the part is later the
+    // wavefront's row-write map)
     __shared__ int32_t cols[COLS ? ROWCAP * BLOCK : 1];
     const int tid = threadIdx.x;
+    int32_t *mycols = cols + (COLS ? (tid >> 6) * (ROWCAP * 64) + (tid & 63) : 0);
     // contiguous rows per XCD: neighbours lie about N^(2/3) positions apart, a window
     // that interleaved blocks would need in every XCD's L2
-    const int32_t kb0 = xcd_block(blockIdx.x, gridDim.x) * BLOCK;
-    const int32_t k = kb0 + tid;
+    const int32_t k = xcd_block(blockIdx.x, gridDim.x) * BLOCK + tid;
     // every thread reaches the block's row write (a barrier): rows past the end and
     // long rows (k_assemble_long) only skip the computation
     int len = 0, diag = 0;
@@ -611,10 +628,10 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int4 v = rc[q];
-            cols[(4 * q) * BLOCK + tid] = v.x;
-            cols[(4 * q + 1) * BLOCK + tid] = v.y;
-            cols[(4 * q + 2) * BLOCK + tid] = v.z;
-            cols[(4 * q + 3) * BLOCK + tid] = v.w;
+            mycols[(4 * q) * 64] = v.x;
+            mycols[(4 * q + 1) * 64] = v.y;
+            mycols[(4 * q + 2) * 64] = v.z;
+            mycols[(4 * q + 3) * 64] = v.w;
         }
     }
     const double2 *xy = reinterpret_cast<const double2 *>(A.xyp);
@@ -725,7 +742,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                         m[u] = (uint32_t)km[u].y;
 #pragma unroll
                         for (int q = 0; q < 3; ++q) {
-                            const int32_t pq = cols[(int)((m[u] >> (Meta<4>::OFF + Meta<4>::OB * q)) & Meta<4>::OMASK) * BLOCK + tid];
+                            const int32_t pq = mycols[(int)((m[u] >> (Meta<4>::OFF + Meta<4>::OB * q)) & Meta<4>::OMASK) * 64];
                             const double2 c0 = xy[2 * (int64_t)pq], c1 = xy[2 * (int64_t)pq + 1];
                             Y[u][q][0] = c0.x; Y[u][q][1] = c0.y; Y[u][q][2] = c1.x;
                             F[u][q] = c1.y;
@@ -912,8 +929,8 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
     if (rowd) gdi = dirichlet_value<3>(A.gd, A.gd.kind == FE_FN_NODAL ? A.pi[k] : 0, Y0);
     } while (false);
     if (COLS && A.direct) {
-        __syncthreads();   // (the walk above reads cols, which the writer reuses)
-        write_rows_direct<ROWCAP, BLOCK>(A, acc, cols, tid, kb0, k, live, len, diag, rowd, bsum, lift, gdi);
+        // (the wavefront's own part of cols, which its walk above has finished reading)
+        write_rows_direct<ROWCAP, BLOCK>(A, acc, mycols - (tid & 63), tid, k, live, len, diag, rowd, bsum, lift, gdi);
     } else if (live) {
         write_row<BLOCK>(A, acc, tid, k, len, rowd, bsum, lift, gdi);
     }
