@@ -349,10 +349,17 @@ template <int ROWCAP, int BLOCK, int UNR>
 __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
 {
     __shared__ double acc[ROWCAP * BLOCK];
-    constexpr bool SLOTW = ROWCAP <= 16;   // block-wide slot writes (map entry fields)
-    __shared__ uint16_t map[SLOTW ? (ROWCAP + 2) * BLOCK : 1];
-    __shared__ double rhs[SLOTW ? 2 * BLOCK : 1];
+    constexpr bool SLOTW = ROWCAP <= 16;   // wavefront-wide slot writes (map entry fields)
+    // each wavefront's own LDS: the source term at the midpoints of its rows' edges
+    // during the walk (ROWCAP values per row, 8-column rows only), then its row-write
+    // map and rhs values
+    constexpr bool MIDC = ROWCAP <= 8;
+    constexpr int WMID = MIDC ? ROWCAP * 64 : 0, WOUT = 128 + ((ROWCAP + 2) * 64 + 3) / 4;   // doubles
+    constexpr int WREG = WMID > WOUT ? WMID : WOUT;
+    __shared__ double wscr[SLOTW ? (BLOCK / 64) * WREG : 1];
     const int tid = threadIdx.x;
+    double *wown = wscr + (SLOTW ? (tid >> 6) * WREG : 0);
+    double *fmid = wown + (tid & 63);   // (column c of this lane's row at fmid[c * 64])
     const int32_t k = blockIdx.x * BLOCK + tid;
     // every thread reaches the block's row write (a barrier): rows past the end and
     // long rows (k_assemble_long) only skip the computation
@@ -384,6 +391,13 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
     const uint32_t BND = (3u << Meta<3>::NBIT) | (3u << Meta<3>::RBIT) |
                          (A.gd.kind != FE_FN_ZERO ? 3u << Meta<3>::DBIT : 0u);
     uint32_t bmask = 0;
+    // Analytic f at edge midpoints (the default rule): the midpoint of edge (i, j) is
+    // met by both triangles of the edge, so its value is kept per column and computed
+    // once, when the column is first met.  One evaluation per incidence covers the
+    // usual case of one new column; a second runs only where both are new.  The
+    // values and their sums are the same as evaluating at every incidence.
+    const bool mcache = MIDC && A.load_rule == FE_LOAD_DEFAULT && A.f.kind == FE_FN_SINPROD;
+    uint32_t seen = 0;   // columns whose midpoint value is in fmid
     for (int32_t p0 = s; p0 < e; p0 += UNR) {
         int2 km[UNR];
         int4 ep[UNR];
@@ -438,6 +452,26 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                     if (nodal_f) {
                         f1 = 0.5 * (A.fp[p2[u]] + fi);
                         f2 = 0.5 * (fi + A.fp[p1[u]]);
+                    } else if (mcache) {
+                        // f1 at the midpoint towards X2 (column o2), f2 towards X1 (o1)
+                        const bool n1 = !((seen >> o1) & 1u), n2 = !((seen >> o2) & 1u);
+                        double fa = 0.0, fb = 0.0;
+                        if (n1 || n2) {
+                            const double2 Xn = n2 ? X2[u] : X1[u];
+                            const double mm[2] = {0.5 * (Xn.x + X0.x), 0.5 * (Xn.y + X0.y)};
+                            fa = fn_point<2>(A.f, mm);
+                            const int cn = n2 ? o2 : o1;
+                            fmid[cn * 64] = fa;
+                            seen |= 1u << cn;
+                        }
+                        if (n1 && n2) {
+                            const double mm[2] = {0.5 * (X0.x + X1[u].x), 0.5 * (X0.y + X1[u].y)};
+                            fb = fn_point<2>(A.f, mm);
+                            fmid[o1 * 64] = fb;
+                            seen |= 1u << o1;
+                        }
+                        f1 = n2 ? fa : fmid[o2 * 64];
+                        f2 = n1 ? (n2 ? fb : fa) : fmid[o1 * 64];
                     } else {
                         const double m1[2] = {0.5 * (X2[u].x + X0.x), 0.5 * (X2[u].y + X0.y)};
                         const double m2[2] = {0.5 * (X0.x + X1[u].x), 0.5 * (X0.y + X1[u].y)};
@@ -566,8 +600,9 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
     } while (false);
     if constexpr (SLOTW) {
         if (!A.direct) {
-            write_rows_slots<ROWCAP, BLOCK>(A, acc, map + (tid >> 6) * ((ROWCAP + 2) * 64), rhs + (tid >> 6) * 128, tid, k,
-                                            live, len, diag, rowd, bsum, lift, gdi);
+            // (the wavefront's walk is done: its midpoint values are no longer needed)
+            write_rows_slots<ROWCAP, BLOCK>(A, acc, reinterpret_cast<uint16_t *>(wown + 128), wown, tid, k, live, len,
+                                            diag, rowd, bsum, lift, gdi);
             return;
         }
     }

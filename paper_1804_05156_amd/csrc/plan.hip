@@ -555,8 +555,13 @@ template <int B, int CAP> struct LdsSet {
 // The same set in CAP registers, sorted and padded with INT32_MAX.  Inserting c
 // into sorted a is new[m] = max(min(a[m], c), a[m-1]) for every m (a[-1] = -inf):
 // branch-free and with fixed register indices, so no LDS and no divergent loops.
-template <int CAP> struct RegSet {
+// SPLIT (2-D rows, mostly at most 8 columns): while no active lane of the wavefront
+// holds more than CAP/2 columns, the compares and the shift cover the lower half
+// only: the upper half is padding then, which no compare can match and no shift
+// needs to move.  (3-D rows fill both halves: there the vote would only cost.)
+template <int CAP, bool SPLIT> struct RegSet {
     static_assert(CAP % 4 == 0, "stored as int4");
+    static constexpr int HALF = CAP / 2;
     int32_t a[CAP];
     int u;
     FE_DEV void init(int32_t *, int, int32_t i)
@@ -584,24 +589,38 @@ template <int CAP> struct RegSet {
         }
         u = n;
     }
-    FE_DEV bool insert(int32_t c)
+    template <int W> FE_DEV bool has(int32_t c) const
     {
         bool dup = false;
 #pragma unroll
-        for (int m = 0; m < CAP; ++m) dup |= (a[m] == c);
-        if (dup) return true;
-        if (u == CAP) return false;
+        for (int m = 0; m < W; ++m) dup |= (a[m] == c);
+        return dup;
+    }
+    template <int W> FE_DEV void shift_in(int32_t c)
+    {
 #pragma unroll
-        for (int m = CAP - 1; m > 0; --m) a[m] = max(min(a[m], c), a[m - 1]);
+        for (int m = W - 1; m > 0; --m) a[m] = max(min(a[m], c), a[m - 1]);
         a[0] = min(a[0], c);
+    }
+    FE_DEV bool insert(int32_t c)
+    {
+        const bool wide = !SPLIT || __ballot(u >= HALF) != 0;   // (uniform in the wavefront)
+        if (wide ? has<CAP>(c) : has<HALF>(c)) return true;
+        if (u == CAP) return false;
+        if (wide) shift_in<CAP>(c);
+        else shift_in<HALF>(c);
         ++u;
         return true;
     }
     FE_DEV int find(int32_t c) const
     {
+        const bool wide = !SPLIT || __ballot(u > HALF) != 0;
         int m = 0;
 #pragma unroll
-        for (int q = 0; q < CAP; ++q) m += (a[q] < c) ? 1 : 0;
+        for (int q = 0; q < HALF; ++q) m += (a[q] < c) ? 1 : 0;
+        if (wide)
+#pragma unroll
+            for (int q = HALF; q < CAP; ++q) m += (a[q] < c) ? 1 : 0;
         return m;
     }
     FE_DEV int32_t at(int m) const   // (m is a compile-time index in the unrolled callers)
@@ -638,7 +657,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
 {
     constexpr int B = REG ? REGB : RowCaps<NV>::BLOCK, COLCAP = RowCaps<NV>::COL;
     __shared__ int32_t cols[REG ? 1 : COLCAP * B];
-    using Set = typename std::conditional<REG, RegSet<REGCAP>, LdsSet<B, COLCAP>>::type;
+    using Set = typename std::conditional<REG, RegSet<REGCAP, NV == 3>, LdsSet<B, COLCAP>>::type;
     constexpr int SETCAP = REG ? REGCAP : COLCAP;
     const int tid = threadIdx.x;
     // 3-D: contiguous rows per XCD (neighbours lie about N^(2/3) positions apart, a
