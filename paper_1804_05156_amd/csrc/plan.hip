@@ -686,6 +686,84 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
     bool ok = true;
+    // Metadata word of one incidence (local vertex, column offsets of the other
+    // vertices, Dirichlet / Neumann / Robin bits), from its key, its element record and
+    // the other vertices' labels; adds its Dirichlet columns to dmask.
+    auto meta_of = [&](int32_t key, const int4 &ep, const int32_t *c, uint64_t &dmask) -> uint32_t {
+        const int a = key % NV;
+        uint32_t meta = (uint32_t)a;
+#pragma unroll
+        for (int jj = 0; jj < NV - 1; ++jj) {
+            const uint32_t wb = (uint32_t)word_i4(ep, fe_other<NV>(a, jj));   // packed code and flag
+            const int m = set.find(c[jj]);                                   // present by construction
+            meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
+            if ((wb >> EREC_DIR) & 1u) {
+                meta |= 1u << (Meta<NV>::DBIT + jj);
+                dmask |= 1ull << m;
+            }
+            const uint32_t code = (wb >> EREC_CODE) & 3u;
+            if (code == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
+            if (code == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
+        }
+        return meta;
+    };
+    // Final pass: the row's columns and its row record.
+    auto finish = [&](uint64_t dmask) {
+        const int u = set.u;
+        const int32_t ps = R.prowptr[k];
+        int diag = 0;
+#pragma unroll
+        for (int m = 0; m < SETCAP; ++m) {
+            if (m >= u) break;
+            const int32_t c = set.at(m);
+            R.colindp[ps + m] = c;
+            if (c == i) diag = m;
+        }
+        const uint32_t info = (uint32_t)u | ((uint32_t)diag << 8) | ((uint32_t)(R.isdp[k] ? 1 : 0) << 16);
+        R.prow_info[k] = info;
+        R.precp[k] = make_int4(ps, (int32_t)info, (int32_t)(uint32_t)dmask, (int32_t)(uint32_t)(dmask >> 32));
+    };
+    // 2-D final pass, rows of at most RUNR incidences (nearly every row): one walk.
+    // The keys, element records and labels loaded to form the column set stay in
+    // registers for the metadata words, instead of a second walk that loads them again.
+    constexpr bool FUSE = FINAL && REG && NV == 3;
+    if constexpr (FUSE) {
+        if (d <= RUNR) {
+            int32_t key[RUNR];
+            int4 ep[RUNR];
+            int32_t c[RUNR][NV - 1];
+            const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
+            set.init(cols, tid, i);
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (q < d) key[q] = klist[src + q];
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (q < d) {
+                    const int32_t t = key[q] / NV;
+                    const int a = key[q] - t * NV;
+                    ep[q] = ep4[t];
+#pragma unroll
+                    for (int jj = 0; jj < NV - 1; ++jj)
+                        c[q][jj] = LBL ? sel_i4(ep[q], fe_other<NV>(a, jj)) : R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
+                }
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (q < d)
+#pragma unroll
+                    for (int jj = 0; jj < NV - 1; ++jj) ok = ok && set.insert(c[q][jj]);
+            if (!ok) {
+                atomicOr(R.status + ST_ERR, ERR_RETRY);
+                return;
+            }
+            uint64_t dmask = 0;
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (q < d) R.pincm[s + q] = make_int2(key[q], (int32_t)meta_of(key[q], ep[q], c[q], dmask));
+            finish(dmask);
+            return;
+        }
+    }
     // 3-D rows (about 24 incidences, 15 columns): the count pass stores the register
     // set and the final pass loads it instead of walking the incidences again.  In
     // 2-D (6 incidences) the stores cost the count pass more than the walk costs.
@@ -746,10 +824,40 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         if (!FINAL) R.prowptr[k] = 0;
         return;
     }
-    // Metadata word of every incidence of the row (local vertex, column offsets of the
-    // other vertices, Dirichlet / Neumann / Robin bits) to pincm; returns the row's
+    // The metadata words of every incidence of the row to pincm; returns the row's
     // Dirichlet-column mask.
-    auto meta_walk = [&]() -> uint64_t {
+    auto meta_walk2 = [&]() -> uint64_t {
+        uint64_t dmask = 0;
+        const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
+        const bool sell = NV == 4 && R.status[ST_SELL] != 0;
+        for (int32_t j0 = 0; j0 < d; j0 += RUNR) {
+            int32_t key[RUNR];
+            int4 ep[RUNR];
+            int32_t c[RUNR][NV - 1];
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) key[q] = klist[src + j0 + q];
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d) {
+                    const int32_t t = key[q] / NV;
+                    const int a = key[q] - t * NV;
+                    ep[q] = ep4[t];
+#pragma unroll
+                    for (int jj = 0; jj < NV - 1; ++jj) {
+                        const int b = fe_other<NV>(a, jj);
+                        // labels (LBL: the record's processing positions are the labels)
+                        c[q][jj] = LBL ? (int32_t)((uint32_t)word_i4(ep[q], b) & EREC_POS) : R.elem[(int64_t)b * R.NT + t];
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < RUNR; ++q)
+                if (j0 + q < d)
+                    R.pincm[inc_at(sell, R.sptr, s, k, j0 + q)] = make_int2(key[q], (int32_t)meta_of(key[q], ep[q], c[q], dmask));
+        }
+        return dmask;
+    };
+    auto meta_walk3 = [&]() -> uint64_t {
         uint64_t dmask = 0;
         const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
         const bool sell = NV == 4 && R.status[ST_SELL] != 0;
@@ -807,39 +915,35 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         }
         return dmask;
     };
+    // (3-D keeps the walk whose loads, codes and offsets run as separate loops: that
+    // schedule holds more of a batch's loads in flight than the per-incidence form)
+    auto meta_walk = [&]() -> uint64_t {
+        if constexpr (NV == 4) return meta_walk3();
+        else return meta_walk2();
+    };
     // 3-D label-order processing with stored sets: the count pass writes the
     // metadata while the row's element records are still in cache, and the final
     // pass only writes the columns and the row record.
     constexpr bool MERGE = LBL && SLOT;
-    const int u = set.u;
     if (!FINAL) {
         if constexpr (SLOT) set.store(R.rslot + (int64_t)k * (REGCAP / 4));
         if constexpr (MERGE) {
             const uint64_t dm = meta_walk();
             R.rmask[k] = make_int2((int32_t)(uint32_t)dm, (int32_t)(uint32_t)(dm >> 32));
         }
-        R.prowptr[k] = u;
+        R.prowptr[k] = set.u;
         return;
     }
-    const int32_t ps = R.prowptr[k];
-    int diag = 0;
-#pragma unroll
-    for (int m = 0; m < SETCAP; ++m) {
-        if (m >= u) break;
-        const int32_t c = set.at(m);
-        R.colindp[ps + m] = c;
-        if (c == i) diag = m;
+    if constexpr (FINAL) {
+        uint64_t dmask;
+        if constexpr (MERGE) {
+            const int2 mm = R.rmask[k];
+            dmask = (uint64_t)(uint32_t)mm.x | ((uint64_t)(uint32_t)mm.y << 32);
+        } else {
+            dmask = meta_walk();
+        }
+        finish(dmask);
     }
-    uint64_t dmask;
-    if constexpr (MERGE) {
-        const int2 mm = R.rmask[k];
-        dmask = (uint64_t)(uint32_t)mm.x | ((uint64_t)(uint32_t)mm.y << 32);
-    } else {
-        dmask = meta_walk();
-    }
-    const uint32_t info = (uint32_t)u | ((uint32_t)diag << 8) | ((uint32_t)(R.isdp[k] ? 1 : 0) << 16);
-    R.prow_info[k] = info;
-    R.precp[k] = make_int4(ps, (int32_t)info, (int32_t)(uint32_t)dmask, (int32_t)(uint32_t)(dmask >> 32));
 }
 
 // Sliced incidence layout (3-D): SELLW times the longest row of each slice of SELLW
