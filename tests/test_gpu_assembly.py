@@ -356,6 +356,38 @@ def test_long_rows_in_a_large_mesh(permute):
     assert plan.info["sort_runs"] == (0 if permute else 1)
 
 
+@pytest.mark.parametrize("permute", [False, True])
+def test_mid_degree_vertex_in_a_large_mesh(permute):
+    """A 129^2 jittered mesh with a fan of 12 beside it: one row of 13 columns among
+    rows of at most 7.  The register column set works at full width in the wavefronts
+    around that row and at half width elsewhere, and the numeric kernel takes the
+    16-column accumulators, which evaluate the source at every incidence instead of
+    once per edge midpoint.  Against the oracle, and bit for bit against the square
+    mesh alone (same incidences per row, so the same sums) for the square's rows."""
+    log(f"case: mid-degree vertex in a large mesh, permute {permute}")
+    sq = meshgen.square_mesh(129, jitter=0.2, permute=permute, seed=89, kappa="lognormal")
+    fan = _fan(12)
+    fan.node[0] += 2.0
+    m = _union(sq, fan)
+    specs = [(FE_FN_SINPROD, (2 * math.pi ** 2,)), (FE_FN_LINEAR, (0.2, 0.1, -0.3))]
+    (f, fo), (gd, gdo), _ = fns(*specs)
+    plan, asm = run_gpu(m, None, f, gd)
+    assert plan.info["max_row"] == 13 and plan.info["n_long"] == 0
+    g = host(plan, asm)
+    compare(g, oracle.assemble(m.node, m.elem, m.bdflag, m.kappa, f=fo, gD=gdo), data=data_scale(m, specs))
+    plan_sq, asm_sq = run_gpu(sq, None, f, gd)
+    assert plan_sq.info["max_row"] <= 8
+    h = host(plan_sq, asm_sq)
+    n = sq.n_node
+    nz = h["rowptr"][-1]
+    assert np.array_equal(g["rowptr"][:n + 1], h["rowptr"])
+    assert np.array_equal(g["colind"][:nz], h["colind"])
+    for key in ("val", "val_bc"):
+        assert np.array_equal(g[key][:nz], h[key]), key
+    for key in ("b", "b_load", "is_d"):
+        assert np.array_equal(g[key][:n], h[key]), key
+
+
 def test_vertex_degree_limit_is_reported():
     """A vertex in 4096 triangles has 8193 candidate columns, one more than the long-
     row kernels hold: the plan refuses it with FE_ELIMIT.  4095 still fits."""
