@@ -478,7 +478,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                         f1 = fn_point<2>(A.f, m1);
                         f2 = fn_point<2>(A.f, m2);
                     }
-                    bsum += area2 * (f1 + f2) / 12.0;
+                    bsum += area2 * (f1 + f2);   // (/ 12 once per row, below)
                 } else if (A.load_rule == FE_LOAD_CENTROID) {
                     double fc;
                     if (nodal_f) {
@@ -487,14 +487,17 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_2d(AsmArgs A)
                         const double c[2] = {(X0.x + X1[u].x + X2[u].x) / 3.0, (X0.y + X1[u].y + X2[u].y) / 3.0};
                         fc = fn_point<2>(A.f, c);
                     }
-                    bsum += area2 * fc / 6.0;
+                    bsum += area2 * fc;   // (/ 6 once per row)
                 } else {
-                    bsum += area2 * fvert / 6.0;
+                    bsum += area2 * fvert;   // (/ 6 once per row)
                 }
             }
             bmask |= meta;
         }
     }
+    // the load terms were summed without their constant factor (1/12 for the
+    // midpoint rule, 1/6 for the others): one division per row
+    if (A.f.kind != FE_FN_ZERO) bsum /= (A.load_rule == FE_LOAD_DEFAULT ? 12.0 : 6.0);
     // Boundary terms of the row: Neumann and Robin sides through its vertex and the
     // lifting of Dirichlet neighbours.  Few rows have any, so they are added by a
     // second walk over the incidences that carry such a bit, which keeps the
@@ -718,9 +721,9 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
             off[jj] = (meta >> (Meta<4>::OFF + Meta<4>::OB * jj)) & Meta<4>::OMASK;
             acc[off[jj] * BLOCK + tid] += kr[jj];
         }
-        const double vol = vol6 / 6.0;
         // load (Section 3.2): symmetric 4-point rule; exact closed form for nodal f.
         // Section 4's one-point rule |t| f(c_t) / 4 and vertex rule |t| f(x_i) / 4 on request.
+        // (Summed in units of 6|t|: the constant factor divides the row's sum once, below.)
         if (A.load_rule == FE_LOAD_CENTROID && A.f.kind != FE_FN_ZERO) {
             double fc;
             if (nodal_f) {
@@ -730,12 +733,12 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                 for (int q = 0; q < 3; ++q) c[q] = (Y0[q] + Y1[q] + Y2[q] + Y3[q]) / 4.0;
                 fc = fn_point<3>(A.f, c);
             }
-            bsum += vol * fc / 4.0;
+            bsum += vol6 * fc;
         } else if (A.load_rule == FE_LOAD_TRAPEZOID && A.f.kind != FE_FN_ZERO) {
-            bsum += vol * fvert / 4.0;
+            bsum += vol6 * fvert;
         } else if (nodal_f) {
             const double sf = fi + Fu[0] + Fu[1] + Fu[2];
-            bsum += vol * (fi + sf) / 20.0;
+            bsum += vol6 * (fi + sf);
         } else if (A.f.kind != FE_FN_ZERO) {
             double S[3];
 #pragma unroll
@@ -748,7 +751,7 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
                 for (int c = 0; c < 3; ++c) pt[c] = beta * S[c] + (alpha - beta) * Yk[c];
                 q += fn_point<3>(A.f, pt) * (kq == 0 ? alpha : beta);
             }
-            bsum += vol * q / 4.0;
+            bsum += vol6 * q;
         }
         bmask |= meta;
     };
@@ -845,6 +848,10 @@ __global__ __launch_bounds__(BLOCK) void k_assemble_3d(AsmArgs A)
             }
         }
     }
+    // the load terms were summed in units of 6|t| without their constant factor
+    // (1/24, or 1/120 for the nodal closed form): one division per row
+    if (A.f.kind != FE_FN_ZERO)
+        bsum /= (A.load_rule == FE_LOAD_DEFAULT && nodal_f) ? 120.0 : 24.0;
     // Boundary terms of the row (Neumann and Robin faces through its vertex, lifting
     // of Dirichlet neighbours): a second walk over the incidences that carry such a
     // bit, as in 2-D.
