@@ -657,6 +657,10 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
 {
     constexpr int B = REG ? REGB : RowCaps<NV>::BLOCK, COLCAP = RowCaps<NV>::COL;
     __shared__ int32_t cols[REG ? 1 : COLCAP * B];
+    // 3-D register form: the finished column set is also put in LDS for the metadata
+    // walk's lookups (a bisection: four LDS reads instead of 32 register compares)
+    constexpr bool LFIND = REG && NV == 4;
+    __shared__ int32_t sset[LFIND ? REGCAP * B : 1];
     using Set = typename std::conditional<REG, RegSet<REGCAP, NV == 3>, LdsSet<B, COLCAP>>::type;
     constexpr int SETCAP = REG ? REGCAP : COLCAP;
     const int tid = threadIdx.x;
@@ -901,7 +905,16 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                     uint32_t meta = (uint32_t)(key[q] % NV);
 #pragma unroll
                     for (int jj = 0; jj < NV - 1; ++jj) {
-                        const int m = set.find(c[q][jj]);   // present by construction
+                        int m;   // present by construction
+                        if constexpr (LFIND) {
+                            const int32_t cc = c[q][jj];
+                            m = (sset[7 * B + tid] < cc) ? 8 : 0;
+                            m += (sset[(m + 3) * B + tid] < cc) ? 4 : 0;
+                            m += (sset[(m + 1) * B + tid] < cc) ? 2 : 0;
+                            m += (sset[m * B + tid] < cc) ? 1 : 0;
+                        } else {
+                            m = set.find(c[q][jj]);
+                        }
                         meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
                         if (dz[q][jj]) {
                             meta |= 1u << (Meta<NV>::DBIT + jj);
@@ -918,6 +931,10 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     // (3-D keeps the walk whose loads, codes and offsets run as separate loops: that
     // schedule holds more of a batch's loads in flight than the per-incidence form)
     auto meta_walk = [&]() -> uint64_t {
+        if constexpr (LFIND) {
+#pragma unroll
+            for (int q = 0; q < REGCAP; ++q) sset[q * B + tid] = set.a[q];   // sorted, padded
+        }
         if constexpr (NV == 4) return meta_walk3();
         else return meta_walk2();
     };
