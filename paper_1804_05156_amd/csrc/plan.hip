@@ -494,7 +494,15 @@ __global__ __launch_bounds__(EBLOCK) void k_ident(int32_t N, int64_t ninc, const
     isdp[v] = (uint8_t)((vi.y >> 30) & 1);
 }
 
-FE_DEV int32_t word_i4(const int4 &q, int c) { return c == 0 ? q.x : (c == 1 ? q.y : (c == 2 ? q.z : q.w)); }
+// Word c (0..3) of a record, by selects on the bits of c: a chain of equality tests
+// compiles to branches, each of which waits for the record's load right away.
+FE_DEV int32_t word_i4(const int4 &q, int c)
+{
+    const int32_t x = q.x, y = q.y, z = q.z, w = q.w;   // (selects of values, not of addresses)
+    const int32_t lo = (c & 1) ? y : x;
+    const int32_t hi = (c & 1) ? w : z;
+    return (c & 2) ? hi : lo;
+}
 // Processing position of local vertex c of an element record.
 FE_DEV int32_t sel_i4(const int4 &q, int c) { return word_i4(q, c) & EREC_POS; }
 
