@@ -870,20 +870,24 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         return dmask;
     };
     auto meta_walk3 = [&]() -> uint64_t {
+        // batches of 4 in the count pass (label-order processing): 88 VGPRs and 5 waves
+        // per SIMD instead of 148 and 3 with 8 (129^3: 691 -> 648 us); 3 or 2 per batch
+        // hold too few loads in flight (704, 848 us)
+        constexpr int MB = FINAL ? RUNR : 4;
         uint64_t dmask = 0;
         const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
         const bool sell = NV == 4 && R.status[ST_SELL] != 0;
-        for (int32_t j0 = 0; j0 < d; j0 += RUNR) {
-            int32_t key[RUNR];
-            int4 ep[RUNR];
-            int32_t c[RUNR][NV - 1];
-            uint8_t dz[RUNR][NV - 1];
-            int8_t code[RUNR][NV - 1];
+        for (int32_t j0 = 0; j0 < d; j0 += MB) {
+            int32_t key[MB];
+            int4 ep[MB];
+            int32_t c[MB][NV - 1];
+            uint8_t dz[MB][NV - 1];
+            int8_t code[MB][NV - 1];
 #pragma unroll
-            for (int q = 0; q < RUNR; ++q)
+            for (int q = 0; q < MB; ++q)
                 if (j0 + q < d) key[q] = klist[src + j0 + q];
 #pragma unroll
-            for (int q = 0; q < RUNR; ++q)
+            for (int q = 0; q < MB; ++q)
                 if (j0 + q < d) {
                     const int32_t t = key[q] / NV;
                     const int a = key[q] - t * NV;
@@ -895,7 +899,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                     }
                 }
 #pragma unroll
-            for (int q = 0; q < RUNR; ++q)
+            for (int q = 0; q < MB; ++q)
                 if (j0 + q < d) {
                     const int a = key[q] % NV;
 #pragma unroll
@@ -908,7 +912,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                     }
                 }
 #pragma unroll
-            for (int q = 0; q < RUNR; ++q)
+            for (int q = 0; q < MB; ++q)
                 if (j0 + q < d) {
                     uint32_t meta = (uint32_t)(key[q] % NV);
 #pragma unroll
