@@ -698,16 +698,29 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
     bool ok = true;
+    // The side codes and Dirichlet flags of an incidence's other vertices, three bits
+    // each (code, then flag), from its element record.  Taken as soon as the record is
+    // loaded, so that its four registers are free again while the set is formed
+    // (2-D final pass: 107 -> 84 VGPRs, 4 -> 5 waves per SIMD, 287 -> 278 us).
+    static_assert(EREC_DIR == EREC_CODE + 2, "code and flag are adjacent");
+    auto flags_of = [&](int32_t key, const int4 &ep) -> uint32_t {
+        const int a = key % NV;
+        uint32_t fl = 0;
+#pragma unroll
+        for (int jj = 0; jj < NV - 1; ++jj)
+            fl |= (((uint32_t)word_i4(ep, fe_other<NV>(a, jj)) >> EREC_CODE) & 7u) << (3 * jj);
+        return fl;
+    };
     // Metadata word of one incidence (local vertex, column offsets of the other
-    // vertices, Dirichlet / Neumann / Robin bits), from its key, its element record and
+    // vertices, Dirichlet / Neumann / Robin bits), from its key, the flags above and
     // the other vertices' labels; adds its Dirichlet columns to dmask.
-    auto meta_of = [&](int32_t key, const int4 &ep, const int32_t *c, uint64_t &dmask) -> uint32_t {
+    auto meta_of = [&](int32_t key, uint32_t fl, const int32_t *c, uint64_t &dmask) -> uint32_t {
         const int a = key % NV;
         uint32_t meta = (uint32_t)a;
 #pragma unroll
         for (int jj = 0; jj < NV - 1; ++jj) {
-            const uint32_t wb = (uint32_t)word_i4(ep, fe_other<NV>(a, jj));   // packed code and flag
-            const int m = set.find(c[jj]);                                   // present by construction
+            const uint32_t wb = (fl >> (3 * jj)) << EREC_CODE;   // packed code and flag
+            const int m = set.find(c[jj]);                       // present by construction
             meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
             if ((wb >> EREC_DIR) & 1u) {
                 meta |= 1u << (Meta<NV>::DBIT + jj);
@@ -742,7 +755,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     if constexpr (FUSE) {
         if (d <= RUNR) {
             int32_t key[RUNR];
-            int4 ep[RUNR];
+            uint32_t fl[RUNR];
             int32_t c[RUNR][NV - 1];
             const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
             set.init(cols, tid, i);
@@ -754,10 +767,11 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 if (q < d) {
                     const int32_t t = key[q] / NV;
                     const int a = key[q] - t * NV;
-                    ep[q] = ep4[t];
+                    const int4 ep = ep4[t];
+                    fl[q] = flags_of(key[q], ep);
 #pragma unroll
                     for (int jj = 0; jj < NV - 1; ++jj)
-                        c[q][jj] = LBL ? sel_i4(ep[q], fe_other<NV>(a, jj)) : R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
+                        c[q][jj] = LBL ? sel_i4(ep, fe_other<NV>(a, jj)) : R.elem[(int64_t)fe_other<NV>(a, jj) * R.NT + t];
                 }
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
@@ -771,7 +785,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             uint64_t dmask = 0;
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
-                if (q < d) R.pincm[s + q] = make_int2(key[q], (int32_t)meta_of(key[q], ep[q], c[q], dmask));
+                if (q < d) R.pincm[s + q] = make_int2(key[q], (int32_t)meta_of(key[q], fl[q], c[q], dmask));
             finish(dmask);
             return;
         }
@@ -844,7 +858,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         const bool sell = NV == 4 && R.status[ST_SELL] != 0;
         for (int32_t j0 = 0; j0 < d; j0 += RUNR) {
             int32_t key[RUNR];
-            int4 ep[RUNR];
+            uint32_t fl[RUNR];
             int32_t c[RUNR][NV - 1];
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
@@ -854,26 +868,29 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 if (j0 + q < d) {
                     const int32_t t = key[q] / NV;
                     const int a = key[q] - t * NV;
-                    ep[q] = ep4[t];
+                    const int4 ep = ep4[t];
+                    fl[q] = flags_of(key[q], ep);
 #pragma unroll
                     for (int jj = 0; jj < NV - 1; ++jj) {
                         const int b = fe_other<NV>(a, jj);
                         // labels (LBL: the record's processing positions are the labels)
-                        c[q][jj] = LBL ? (int32_t)((uint32_t)word_i4(ep[q], b) & EREC_POS) : R.elem[(int64_t)b * R.NT + t];
+                        c[q][jj] = LBL ? (int32_t)((uint32_t)word_i4(ep, b) & EREC_POS) : R.elem[(int64_t)b * R.NT + t];
                     }
                 }
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
                 if (j0 + q < d)
-                    R.pincm[inc_at(sell, R.sptr, s, k, j0 + q)] = make_int2(key[q], (int32_t)meta_of(key[q], ep[q], c[q], dmask));
+                    R.pincm[inc_at(sell, R.sptr, s, k, j0 + q)] = make_int2(key[q], (int32_t)meta_of(key[q], fl[q], c[q], dmask));
         }
         return dmask;
     };
     auto meta_walk3 = [&]() -> uint64_t {
-        // batches of 4 in the count pass (label-order processing): 88 VGPRs and 5 waves
-        // per SIMD instead of 148 and 3 with 8 (129^3: 691 -> 648 us); 3 or 2 per batch
-        // hold too few loads in flight (704, 848 us)
-        constexpr int MB = FINAL ? RUNR : 4;
+        // Batches of 6 in the count pass (label-order processing): 90 VGPRs and 5 waves
+        // per SIMD (129^3: 639 us).  With 8, 110 VGPRs and 4 waves (645 us; 148 and 3
+        // waves, 691 us, before the packed flags); with 4, 70 VGPRs and 7 waves (695 us:
+        // more rows in flight than the L2 serves well); 3 or 2 hold too few loads in
+        // flight.
+        constexpr int MB = FINAL ? RUNR : 6;
         uint64_t dmask = 0;
         const int4 *ep4 = reinterpret_cast<const int4 *>(R.elemp);
         const bool sell = NV == 4 && R.status[ST_SELL] != 0;
@@ -881,8 +898,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             int32_t key[MB];
             int4 ep[MB];
             int32_t c[MB][NV - 1];
-            uint8_t dz[MB][NV - 1];
-            int8_t code[MB][NV - 1];
+            uint32_t fl[MB];
 #pragma unroll
             for (int q = 0; q < MB; ++q)
                 if (j0 + q < d) key[q] = klist[src + j0 + q];
@@ -902,14 +918,11 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             for (int q = 0; q < MB; ++q)
                 if (j0 + q < d) {
                     const int a = key[q] % NV;
+                    fl[q] = flags_of(key[q], ep[q]);
+                    if (LBL)
 #pragma unroll
-                    for (int jj = 0; jj < NV - 1; ++jj) {
-                        const int b = fe_other<NV>(a, jj);
-                        const uint32_t wb = (uint32_t)word_i4(ep[q], b);   // packed code and flag
-                        if (LBL) c[q][jj] = (int32_t)(wb & EREC_POS);      // processing position = label
-                        code[q][jj] = (int8_t)((wb >> EREC_CODE) & 3u);
-                        dz[q][jj] = (uint8_t)((wb >> EREC_DIR) & 1u);
-                    }
+                        for (int jj = 0; jj < NV - 1; ++jj)   // processing position = label
+                            c[q][jj] = sel_i4(ep[q], fe_other<NV>(a, jj));
                 }
 #pragma unroll
             for (int q = 0; q < MB; ++q)
@@ -928,12 +941,13 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                             m = set.find(c[q][jj]);
                         }
                         meta |= (uint32_t)m << (Meta<NV>::OFF + Meta<NV>::OB * jj);
-                        if (dz[q][jj]) {
+                        const uint32_t f3 = (fl[q] >> (3 * jj)) & 7u;   // code, then the flag
+                        if (f3 >> 2) {
                             meta |= 1u << (Meta<NV>::DBIT + jj);
                             dmask |= 1ull << m;
                         }
-                        if (code[q][jj] == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
-                        if (code[q][jj] == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
+                        if ((f3 & 3u) == FE_BD_NEUMANN) meta |= 1u << (Meta<NV>::NBIT + jj);
+                        if ((f3 & 3u) == FE_BD_ROBIN) meta |= 1u << (Meta<NV>::RBIT + jj);
                     }
                     R.pincm[inc_at(sell, R.sptr, s, k, j0 + q)] = make_int2(key[q], (int32_t)meta);
                 }
