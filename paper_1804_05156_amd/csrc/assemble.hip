@@ -137,16 +137,6 @@ FE_DEV void write_row(const AsmArgs &A, const double *acc, int tid, int32_t k, i
     row[len + 1] = bsum;
 }
 
-// Order the LDS accesses of one wavefront: every lane's earlier LDS stores are seen
-// by every lane's later loads (the row writers below work per wavefront, with no
-// workgroup barrier).
-FE_DEV void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Processing-order row slots of one wavefront, written together.  Consecutive rows'
 // slots (values, b, b_load) are consecutive in valp, so the wavefront's 64 slots form
 // one range; each lane enters its slot's entries in an LDS map of the range, then

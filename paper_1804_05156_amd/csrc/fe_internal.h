@@ -226,6 +226,16 @@ template <int DIM> FE_DEV double fn_dudn(const DevFn &f, const double *x, const 
 
 // Deterministic block-wide sum (fixed combination order) of one double per thread.
 // `lds` needs BLOCK/64 doubles.  Every thread of the block must call it.
+// Order the LDS accesses of one wavefront: every lane's earlier LDS stores are seen
+// by every lane's later loads (for work shared within a wavefront, with no workgroup
+// barrier).
+FE_DEV void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int BLOCK> FE_DEV double block_sum(double v, double *lds)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

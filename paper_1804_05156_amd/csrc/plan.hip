@@ -669,6 +669,12 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     // walk's lookups (a bisection: four LDS reads instead of 32 register compares)
     constexpr bool LFIND = REG && NV == 4;
     __shared__ int32_t sset[LFIND ? REGCAP * B : 1];
+    // 2-D general count pass: the keys a wavefront copies (its rows' incidence lists,
+    // one contiguous range of pinc) are gathered in LDS and stored together, a full
+    // line per store, instead of 4 bytes per lane at each row's own place
+    constexpr bool STG = REG && NV == 3 && !FINAL && !LBL;
+    constexpr int KCAP = 512;   // keys per wavefront (64 rows of 8); longer ranges go direct
+    __shared__ int32_t kst[STG ? KCAP * (B / 64) : 1];
     using Set = typename std::conditional<REG, RegSet<REGCAP, NV == 3>, LdsSet<B, COLCAP>>::type;
     constexpr int SETCAP = REG ? REGCAP : COLCAP;
     const int tid = threadIdx.x;
@@ -698,6 +704,19 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
     bool ok = true;
+    // the wavefront's range of pinc (its active lanes' rows are consecutive positions)
+    // (wavefront-uniform values, read through the first lane so they sit in scalar
+    // registers)
+    int32_t *wk = kst + (STG ? __builtin_amdgcn_readfirstlane(tid >> 6) * KCAP : 0);
+    int32_t wbase = 0, wlen = 0;
+    bool staged = false;
+    if constexpr (STG) {
+        const uint64_t act = __ballot(1);
+        const int last = 63 - __clzll((long long)act);
+        wbase = __builtin_amdgcn_readfirstlane(s);
+        wlen = __builtin_amdgcn_readfirstlane(__shfl(s + d, last) - wbase);
+        staged = wlen <= KCAP;
+    }
     // The side codes and Dirichlet flags of an incidence's other vertices, three bits
     // each (code, then flag), from its element record.  Taken as soon as the record is
     // loaded, so that its four registers are free again while the set is formed
@@ -828,7 +847,8 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                     if (j0 + q < d) {
                         const int32_t t = key[q] / NV;
                         const int a = key[q] - t * NV;
-                        R.pinc[s + j0 + q] = key[q];
+                        if (staged) wk[s - wbase + j0 + q] = key[q];
+                        else R.pinc[s + j0 + q] = key[q];
                         R.elemp[(int64_t)t * 4 + a] = k | (int32_t)((uint32_t)code[q] << EREC_CODE) | rowdir;
                     }
 #pragma unroll
@@ -836,6 +856,17 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
                 if (j0 + q < d)
 #pragma unroll
                     for (int jj = 0; jj < NV - 1; ++jj) ok = ok && set.insert(c[q][jj]);
+        }
+    }
+    if constexpr (STG) {
+        // (every lane of the wavefront that walked a row is here: the active lanes share
+        // the stores; a row whose set overflowed stops early, and the pass is rerun)
+        if (staged) {
+            wave_lds_sync();
+            const uint64_t act = __ballot(1);
+            const int nact = __popcll(act);
+            const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+            for (int32_t j = r; j < wlen; j += nact) R.pinc[wbase + j] = wk[j];
         }
     }
     if (!ok) {
