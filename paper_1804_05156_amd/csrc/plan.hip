@@ -675,6 +675,10 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     constexpr bool STG = REG && NV == 3 && !FINAL && !LBL;
     constexpr int KCAP = 512;   // keys per wavefront (64 rows of 8); longer ranges go direct
     __shared__ int32_t kst[STG ? KCAP * (B / 64) : 1];
+    // 2-D final pass, the same for a wavefront's (key, metadata) words and columns
+    constexpr bool STF = REG && NV == 3 && FINAL;
+    __shared__ int2 mst[STF ? KCAP * (B / 64) : 1];
+    __shared__ int32_t cst[STF ? KCAP * (B / 64) : 1];
     using Set = typename std::conditional<REG, RegSet<REGCAP, NV == 3>, LdsSet<B, COLCAP>>::type;
     constexpr int SETCAP = REG ? REGCAP : COLCAP;
     const int tid = threadIdx.x;
@@ -752,7 +756,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         return meta;
     };
     // Final pass: the row's columns and its row record.
-    auto finish = [&](uint64_t dmask) {
+    auto finish = [&](uint64_t dmask, int32_t *cw = nullptr) {   // cw: columns to LDS, at ps - cw's base
         const int u = set.u;
         const int32_t ps = R.prowptr[k];
         int diag = 0;
@@ -760,7 +764,8 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         for (int m = 0; m < SETCAP; ++m) {
             if (m >= u) break;
             const int32_t c = set.at(m);
-            R.colindp[ps + m] = c;
+            if (cw) cw[m] = c;
+            else R.colindp[ps + m] = c;
             if (c == i) diag = m;
         }
         const uint32_t info = (uint32_t)u | ((uint32_t)diag << 8) | ((uint32_t)(R.isdp[k] ? 1 : 0) << 16);
@@ -772,6 +777,19 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     // registers for the metadata words, instead of a second walk that loads them again.
     constexpr bool FUSE = FINAL && REG && NV == 3;
     if constexpr (FUSE) {
+        // the wavefront's ranges of pincm and colindp, staged when every row takes
+        // the one walk and both ranges fit
+        const uint64_t act = __ballot(1);
+        const int last = 63 - __clzll((long long)act);
+        const int32_t ps0 = R.prowptr[k], pe0 = R.prowptr[k + 1];
+        const int32_t mb = __builtin_amdgcn_readfirstlane(s);
+        const int32_t ml = __builtin_amdgcn_readfirstlane(__shfl(s + d, last)) - mb;
+        const int32_t cb = __builtin_amdgcn_readfirstlane(ps0);
+        const int32_t cl = __builtin_amdgcn_readfirstlane(__shfl(pe0, last)) - cb;
+        const bool stg = __all(d <= RUNR) && ml <= KCAP && cl <= KCAP;
+        const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+        int2 *mw = mst + wv * KCAP;
+        int32_t *cw = cst + wv * KCAP;
         if (d <= RUNR) {
             int32_t key[RUNR];
             uint32_t fl[RUNR];
@@ -804,8 +822,22 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             uint64_t dmask = 0;
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
-                if (q < d) R.pincm[s + q] = make_int2(key[q], (int32_t)meta_of(key[q], fl[q], c[q], dmask));
-            finish(dmask);
+                if (q < d) {
+                    const int2 w = make_int2(key[q], (int32_t)meta_of(key[q], fl[q], c[q], dmask));
+                    if (stg) mw[s - mb + q] = w;
+                    else R.pincm[s + q] = w;
+                }
+            finish(dmask, stg ? cw + (ps0 - cb) : nullptr);
+            if (stg) {
+                // (the active lanes share the stores; a row whose set overflowed left,
+                // and the pass is rerun)
+                wave_lds_sync();
+                const uint64_t a2 = __ballot(1);
+                const int nact = __popcll(a2);
+                const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(a2 >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)a2, 0u));
+                for (int32_t j = r; j < ml; j += nact) R.pincm[mb + j] = mw[j];
+                for (int32_t j = r; j < cl; j += nact) R.colindp[cb + j] = cw[j];
+            }
             return;
         }
     }
