@@ -672,13 +672,16 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     // 2-D general count pass: the keys a wavefront copies (its rows' incidence lists,
     // one contiguous range of pinc) are gathered in LDS and stored together, a full
     // line per store, instead of 4 bytes per lane at each row's own place
-    constexpr bool STG = REG && NV == 3 && !FINAL && !LBL;
+    constexpr bool STG = REG && !FINAL && !LBL;
     constexpr int KCAP = 512;   // keys per wavefront (64 rows of 8); longer ranges go direct
-    __shared__ int32_t kst[STG ? KCAP * (B / 64) : 1];
+    constexpr int KCAPS = NV == 3 ? KCAP : 2048;   // (3-D: 64 rows of 32)
+    __shared__ int32_t kst[STG ? KCAPS * (B / 64) : 1];
     // 2-D final pass, the same for a wavefront's (key, metadata) words and columns
     constexpr bool STF = REG && NV == 3 && FINAL;
     __shared__ int2 mst[STF ? KCAP * (B / 64) : 1];
-    __shared__ int32_t cst[STF ? KCAP * (B / 64) : 1];
+    // (and, in both dimensions, the final pass's columns; 3-D: 64 rows of 16)
+    constexpr int CCAP = NV == 3 ? KCAP : 1024;
+    __shared__ int32_t cst[(REG && FINAL) ? CCAP * (B / 64) : 1];
     using Set = typename std::conditional<REG, RegSet<REGCAP, NV == 3>, LdsSet<B, COLCAP>>::type;
     constexpr int SETCAP = REG ? REGCAP : COLCAP;
     const int tid = threadIdx.x;
@@ -711,7 +714,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     // the wavefront's range of pinc (its active lanes' rows are consecutive positions)
     // (wavefront-uniform values, read through the first lane so they sit in scalar
     // registers)
-    int32_t *wk = kst + (STG ? __builtin_amdgcn_readfirstlane(tid >> 6) * KCAP : 0);
+    int32_t *wk = kst + (STG ? __builtin_amdgcn_readfirstlane(tid >> 6) * KCAPS : 0);
     int32_t wbase = 0, wlen = 0;
     bool staged = false;
     if constexpr (STG) {
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         const int last = 63 - __clzll((long long)act);
         wbase = __builtin_amdgcn_readfirstlane(s);
         wlen = __builtin_amdgcn_readfirstlane(__shfl(s + d, last) - wbase);
-        staged = wlen <= KCAP;
+        staged = wlen <= KCAPS;
     }
     // The side codes and Dirichlet flags of an incidence's other vertices, three bits
     // each (code, then flag), from its element record.  Taken as soon as the record is
@@ -786,10 +789,10 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
         const int32_t ml = __builtin_amdgcn_readfirstlane(__shfl(s + d, last)) - mb;
         const int32_t cb = __builtin_amdgcn_readfirstlane(ps0);
         const int32_t cl = __builtin_amdgcn_readfirstlane(__shfl(pe0, last)) - cb;
-        const bool stg = __all(d <= RUNR) && ml <= KCAP && cl <= KCAP;
+        const bool stg = __all(d <= RUNR) && ml <= KCAP && cl <= CCAP;
         const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
         int2 *mw = mst + wv * KCAP;
-        int32_t *cw = cst + wv * KCAP;
+        int32_t *cw = cst + wv * CCAP;
         if (d <= RUNR) {
             int32_t key[RUNR];
             uint32_t fl[RUNR];
@@ -1047,6 +1050,25 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             dmask = (uint64_t)(uint32_t)mm.x | ((uint64_t)(uint32_t)mm.y << 32);
         } else {
             dmask = meta_walk();
+        }
+        if constexpr (REG && NV == 4) {
+            // the wavefront's columns gathered in LDS and stored together (the active
+            // lanes share the stores; a row whose set overflowed left, and the pass is
+            // rerun)
+            const uint64_t act = __ballot(1);
+            const int last = 63 - __clzll((long long)act);
+            const int32_t ps0 = R.prowptr[k];
+            const int32_t cb = __builtin_amdgcn_readfirstlane(ps0);
+            const int32_t cl = __builtin_amdgcn_readfirstlane(__shfl(R.prowptr[k + 1], last)) - cb;
+            if (cl <= CCAP) {
+                int32_t *cw = cst + __builtin_amdgcn_readfirstlane(tid >> 6) * CCAP;
+                finish(dmask, cw + (ps0 - cb));
+                wave_lds_sync();
+                const int nact = __popcll(act);
+                const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+                for (int32_t j = r; j < cl; j += nact) R.colindp[cb + j] = cw[j];
+                return;
+            }
         }
         finish(dmask);
     }
