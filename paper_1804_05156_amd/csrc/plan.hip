@@ -1060,10 +1060,31 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     // pass only writes the columns and the row record.
     constexpr bool MERGE = LBL && SLOT;
     if (!FINAL) {
-        if constexpr (SLOT) set.store(R.rslot + (int64_t)k * (REGCAP / 4));
         if constexpr (MERGE) {
-            const uint64_t dm = meta_walk();
+            const uint64_t dm = meta_walk();   // (puts the set in sset first)
             R.rmask[k] = make_int2((int32_t)(uint32_t)dm, (int32_t)(uint32_t)(dm >> 32));
+        } else if constexpr (SLOT) {
+            // (general path: the wavefront's part of the key-copy buffer, free again)
+            static_assert(!SLOT || MERGE || KCAPS >= 64 * REGCAP, "room for the sets");
+            wave_lds_sync();
+#pragma unroll
+            for (int q = 0; q < REGCAP; ++q) wk[q * 64 + (tid & 63)] = set.a[q];
+        }
+        if constexpr (SLOT) {
+            // the wavefront's slots (64 rows of REGCAP words, contiguous) stored together
+            // from the LDS copy of the sets; rows of lanes that left early (no
+            // incidences: never read; an overflowed set: the pass is rerun) get whatever
+            // their LDS column holds
+            wave_lds_sync();
+            const uint64_t act = __ballot(1);
+            const int nact = __popcll(act);
+            const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+            const int32_t kw0 = __builtin_amdgcn_readfirstlane(k - (tid & 63));
+            const int nw = min(64, R.N - kw0) * REGCAP;
+            constexpr int CS = MERGE ? B : 64;   // stride of a set's words
+            const int32_t *col = MERGE ? sset + (tid & ~63) : wk;
+            int32_t *slot = reinterpret_cast<int32_t *>(R.rslot) + (int64_t)kw0 * REGCAP;
+            for (int j = r; j < nw; j += nact) slot[j] = col[(j % REGCAP) * CS + j / REGCAP];
         }
         R.prowptr[k] = set.u;
         return;
