@@ -160,12 +160,17 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
                                                     int2 *pairs, const int8_t *__restrict__ bd,
                                                     const uint8_t *__restrict__ isd, int4 *elemp)
 {
+    // Labels that follow the element order give long runs at any sub-chunk size, so
+    // AGG takes half-size sub-chunks: half the LDS, twice the workgroups per CU (129^3
+    // 274 -> 209 us).  Random labels need the long sub-chunks for their runs (2049^2
+    // with 1024: 88 -> 111 us).
+    constexpr int SUB = AGG ? L1SUB / 2 : L1SUB;
     extern __shared__ int32_t dyn[];
-    __shared__ int2 buf[L1SUB * NV];
+    __shared__ int2 buf[SUB * NV];
     __shared__ int32_t sl[2 * (L1B / 64)];
     int32_t *cur = dyn;        // next global position of each bucket
     int32_t *cnt = dyn + nb;   // sub-chunk pairs per bucket, then their LDS start
-    constexpr int PER = L1SUB / L1B;
+    constexpr int PER = SUB / L1B;
     const int32_t ch = l1_chunk(blockIdx.x, nblk1);
     const int tid = threadIdx.x;
     if (tid < nb) {
@@ -175,7 +180,7 @@ __global__ __launch_bounds__(L1B) void k_l1_scatter(const int32_t *__restrict__ 
     __syncthreads();
     const int32_t t0 = ch * chn;
     const int32_t t1 = min(NT, t0 + chn);
-    for (int32_t s0 = t0; s0 < t1; s0 += L1SUB) {
+    for (int32_t s0 = t0; s0 < t1; s0 += SUB) {
         int32_t v[PER][NV], rk[PER][NV], w[PER][NV];
 #pragma unroll
         for (int e = 0; e < PER; ++e) {
