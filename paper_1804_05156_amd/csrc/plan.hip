@@ -699,6 +699,12 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     // walk's lookups (a bisection: four LDS reads instead of 32 register compares)
     constexpr bool LFIND = REG && NV == 4;
     __shared__ int32_t sset[LFIND ? REGCAP * B : 1];
+    // 3-D label-order count pass: the wavefront's rows read one contiguous range of the
+    // label-order lists (both walks read it); it is loaded once into LDS with whole-line
+    // loads, and the walks take their keys from there
+    constexpr bool KLD = REG && NV == 4 && LBL && !FINAL;
+    constexpr int KLCAP = 1536;   // keys per wavefront (64 rows of 24); longer ranges read directly
+    __shared__ int32_t klds[KLD ? KLCAP * (B / 64) : 1];
     // 2-D general count pass: the keys a wavefront copies (its rows' incidence lists,
     // one contiguous range of pinc) are gathered in LDS and stored together, a full
     // line per store, instead of 4 bytes per lane at each row's own place
@@ -741,6 +747,21 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     const int32_t *klist = from_pinc ? R.pinc : R.sorted_l;
     Set set;
     bool ok = true;
+    const int32_t *kl = klist + src;   // this row's keys
+    if constexpr (KLD) {
+        const uint64_t act = __ballot(1);
+        const int last = 63 - __clzll((long long)act);
+        const int32_t kb = __builtin_amdgcn_readfirstlane(src);
+        const int32_t kn = __builtin_amdgcn_readfirstlane(__shfl(src + d, last)) - kb;
+        if (kn <= KLCAP) {
+            int32_t *kw = klds + __builtin_amdgcn_readfirstlane(tid >> 6) * KLCAP;
+            const int nact = __popcll(act);
+            const int r = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+            for (int32_t j = r; j < kn; j += nact) kw[j] = klist[kb + j];
+            wave_lds_sync();
+            kl = kw + (src - kb);
+        }
+    }
     // the wavefront's range of pinc (its active lanes' rows are consecutive positions)
     // (wavefront-uniform values, read through the first lane so they sit in scalar
     // registers)
@@ -889,7 +910,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             int32_t code[RUNR];
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
-                if (j0 + q < d) key[q] = klist[src + j0 + q];
+                if (j0 + q < d) key[q] = kl[j0 + q];
 #pragma unroll
             for (int q = 0; q < RUNR; ++q)
                 if (j0 + q < d) {
@@ -997,7 +1018,7 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
             uint32_t fl[MB];
 #pragma unroll
             for (int q = 0; q < MB; ++q)
-                if (j0 + q < d) key[q] = klist[src + j0 + q];
+                if (j0 + q < d) key[q] = kl[j0 + q];
 #pragma unroll
             for (int q = 0; q < MB; ++q)
                 if (j0 + q < d) {
