@@ -555,3 +555,34 @@ def test_element_prefix_sum_beyond_tile_limit_sampled():
     plan, asm, g = _sampled_full_size(m, [(FE_FN_CONST, (1.0,))], nsample=32)
     assert not plan.info["sort_runs"]
     assert plan.nnz == 3 * N + 2 * m.n_elem - 2
+
+
+@pytest.mark.parametrize("dim,permute", [(2, False), (2, True), (3, False), (3, True)])
+def test_every_element_listed_twice(dim, permute):
+    """Each element listed twice (the copy with its own kappa): sparse() adds the
+    duplicate contributions like any others (Section 2.2).  Every vertex then has twice
+    its incidences, 12 in 2-D and 48 in the 3-D Kuhn mesh, which takes the row passes
+    and numeric kernels past their per-wavefront buffers (64 rows of 8 keys in 2-D, of
+    24 in the 3-D key lists, of 32 in the 3-D key copy) and the 2-D one-walk final pass
+    (8 incidences), onto their direct paths."""
+    log(f"case: every element twice, dim={dim} permute={permute}")
+    if dim == 2:
+        m = meshgen.square_mesh(65, jitter=0.2, permute=permute, seed=31, kappa="lognormal", sides=(1, 2, 1, 2))
+    else:
+        m = meshgen.kuhn_cube(12, jitter=0.15, permute=permute, seed=32, kappa="lognormal")
+    rng = np.random.default_rng(33)
+    elem = np.ascontiguousarray(np.concatenate([m.elem, m.elem], axis=1))
+    bd = np.ascontiguousarray(np.concatenate([m.bdflag, m.bdflag], axis=1))
+    kappa = np.concatenate([m.kappa, np.exp(rng.normal(size=m.kappa.shape))])
+    m2 = meshgen.Mesh(m.node, elem, bd, kappa)
+    specs = [(FE_FN_SINPROD, (TWO_PI2 if dim == 2 else 3 * math.pi ** 2,)), (FE_FN_LINEAR, (0.3, 1.1, -0.7, 0.2)[:dim + 1]),
+             (FE_FN_DUDN_SINPROD, (1.3,))]
+    (f, fo), (gd, gdo), (gn, gno) = fns(*specs)
+    plan, asm = run_gpu(m2, None, f, gd, gn)
+    g = host(plan, asm)
+    ora = oracle.assemble(m2.node, m2.elem, m2.bdflag, m2.kappa, f=fo, gD=gdo, gN=gno)
+    compare(g, ora, data=data_scale(m2, specs))
+    # the pattern is the single mesh's
+    plan1, _ = run_gpu(m, None, f, gd, gn)
+    assert np.array_equal(plan1.rowptr.cpu().numpy(), g["rowptr"])
+    assert np.array_equal(plan1.colind[:plan1.nnz].cpu().numpy(), g["colind"])
