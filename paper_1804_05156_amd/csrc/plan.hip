@@ -705,11 +705,11 @@ __global__ __launch_bounds__(REG ? REGB : RowCaps<NV>::BLOCK) void k_rows(RowArg
     constexpr bool KLD = REG && NV == 4 && LBL && !FINAL;
     constexpr int KLCAP = 1536;   // keys per wavefront (64 rows of 24); longer ranges read directly
     __shared__ int32_t klds[KLD ? KLCAP * (B / 64) : 1];
-    // 2-D general count pass: the keys a wavefront copies (its rows' incidence lists,
+    // General-path count pass: the keys a wavefront copies (its rows' incidence lists,
     // one contiguous range of pinc) are gathered in LDS and stored together, a full
     // line per store, instead of 4 bytes per lane at each row's own place
     constexpr bool STG = REG && !FINAL && !LBL;
-    constexpr int KCAP = 512;   // keys per wavefront (64 rows of 8); longer ranges go direct
+    constexpr int KCAP = 512;   // 2-D keys per wavefront (64 rows of 8); longer ranges go direct
     constexpr int KCAPS = NV == 3 ? KCAP : 2048;   // (3-D: 64 rows of 32)
     __shared__ int32_t kst[STG ? KCAPS * (B / 64) : 1];
     // 2-D final pass, the same for a wavefront's (key, metadata) words and columns
